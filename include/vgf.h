@@ -1,0 +1,142 @@
+/*
+ * vgf.h -- C ABI of the MI355X (gfx950) free-space Poisson solver library
+ * libvgf.so: the Vico-Greengard-Ferrando (VGF) method and, beside it, the
+ * Hockney-Eastwood (HE) method, as compared in Zou, Kim & Cerfon,
+ * arXiv:2103.08531.
+ *
+ * Problem (Sec. I, Eq. 1): Laplace(phi) = -rho in free space, E = -grad(phi),
+ * for rho sampled on a uniform grid of n_a points with spacing h_a per axis
+ * (Sec. I, the text around Eq. 3). The solution is the convolution of rho
+ * with the free-space Green's function (Eq. 2):
+ *   HE : with the trapezoidal rule and the kernel h^d G(|n h|), its origin
+ *        value regularised (Eq. 3 and the sentence after it);
+ *   VGF: with the kernel obtained once per grid as the inverse DFT, on the
+ *        (4N)^d oversampled grid, of the closed-form spectrum of the kernel
+ *        truncated at radius L (Eqs. 4-8), restricted to offsets |n_a| < N_a
+ *        (Sec. II, last paragraph).
+ * Each solve is then an aperiodic convolution computed with FFTs on the
+ * zero-padded (2N)^d grid (Eq. 3); the field is obtained by Fourier
+ * differentiation, i.e. multiplying by -i k_a before the inverse transform
+ * (Sec. III.A), with the factor of the Nyquist wavenumber set to zero.
+ *
+ * Conventions common to every call:
+ *  - Every status is a vgf_status; VGF_OK is 0, errors are negative. No C++
+ *    exception crosses this interface and no call aborts the process.
+ *  - rho, phi, E and gradient buffers are DEVICE pointers owned by the
+ *    caller, C-contiguous with the last axis fastest, in the plan's precision
+ *    (double for VGF_F64, float for VGF_F32). E is planar: E[a] starts at
+ *    E + a * prod(n), a = 0..dim-1, and holds -d(phi)/dx_a.
+ *  - Calls are asynchronous and stream-ordered on the stream passed in; none
+ *    synchronises with the host except vgf_plan_create, vgf_plan_get_kernel
+ *    and vgf_plan_get_spectrum, which do. A plan owns a workspace and must be
+ *    used by one stream at a time; distinct plans are independent.
+ *  - Supported sizes: every n_a in {8, 12, 16, 24, 32, 48, 64, 96, 128, 192,
+ *    256, 384, 512} (the padded length 2 n_a must be an FFT length the
+ *    library instantiates). Other sizes return VGF_ERR_UNSUPPORTED_SIZE.
+ */
+#ifndef VGF_H
+#define VGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vgf_plan_s* vgf_plan;
+
+typedef enum {
+  VGF_OK = 0,
+  VGF_ERR_INVALID_ARG = -1,      /* null pointer, bad dim/method/precision/flags */
+  VGF_ERR_UNSUPPORTED_SIZE = -2, /* an n_a outside the supported set */
+  VGF_ERR_L_WINDOW = -3,         /* L outside (diameter, min_a(4 n_a h_a - extent_a)) */
+  VGF_ERR_OUT_OF_MEMORY = -4,    /* device allocation failed or exceeds VGF_MAX_WORKSPACE */
+  VGF_ERR_HIP = -5,              /* a HIP runtime call failed (see vgf_plan_hip_error) */
+  VGF_ERR_NOT_REQUESTED = -6     /* an output that the plan was not created for */
+} vgf_status;
+
+typedef enum { VGF_METHOD_VGF = 0, VGF_METHOD_HE = 1 } vgf_method;
+typedef enum { VGF_F64 = 0, VGF_F32 = 1 } vgf_precision;
+enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u };
+
+/* Build a plan for a fixed grid (Sec. II: one precomputation per grid, then
+ * a solve per right-hand side).
+ *   out      : receives the plan handle (host pointer, not null).
+ *   dim      : 2 or 3.
+ *   n[dim]   : points per axis (host array).
+ *   h[dim]   : grid spacing per axis, > 0 (host array).
+ *   method   : VGF_METHOD_VGF or VGF_METHOD_HE.
+ *   prec     : arithmetic and buffer type of every solve. The kernel spectrum
+ *              is always computed in FP64 and, for VGF_F32, rounded to FP32
+ *              once; FFT twiddles are FP64 values rounded to the plan type.
+ *   L        : truncation radius of the VGF kernel (Eq. 4). L <= 0 selects
+ *              1.1 x the box diameter. Must lie strictly inside
+ *              (diameter, min_a(4 n_a h_a - (n_a - 1) h_a)): below it the
+ *              truncated kernel misses source-target pairs (Sec. II), above
+ *              it the 4N-periodic images reach the box. Ignored for HE.
+ *   outputs  : VGF_OUT_PHI | VGF_OUT_E, the fields later solves may return.
+ *   stream   : stream on which the FP64 precompute runs; the call
+ *              synchronises it before returning.
+ * Errors: INVALID_ARG, UNSUPPORTED_SIZE, L_WINDOW, OUT_OF_MEMORY, HIP. On
+ * error *out is set to NULL and nothing is leaked. */
+vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const double* h,
+                           vgf_method method, vgf_precision prec, double L,
+                           unsigned outputs, hipStream_t stream);
+
+/* One solve (the per-right-hand-side path of Sec. II / Eq. 3):
+ *   rho : device input, prod(n) values.
+ *   phi : device output, prod(n) values, or NULL to skip the potential.
+ *   E   : device output, dim * prod(n) values (planar), or NULL.
+ * Requesting a field the plan was not created for returns NOT_REQUESTED;
+ * phi == E == NULL returns INVALID_ARG. Enqueued on `stream`. */
+vgf_status vgf_solve(vgf_plan plan, const void* rho, void* phi, void* E, hipStream_t stream);
+
+/* Adjoint of vgf_solve (for reverse-mode differentiation):
+ *   g_rho = K^T g_phi + sum_a K_a^T g_E[a],
+ * where K maps rho to phi and K_a maps rho to E[a]. g_phi or g_E may be NULL
+ * (treated as zero), not both. All buffers are device buffers shaped like the
+ * corresponding forward outputs / input. Enqueued on `stream`. */
+vgf_status vgf_solve_adjoint(vgf_plan plan, const void* g_phi, const void* g_E, void* g_rho,
+                             hipStream_t stream);
+
+/* Many independent solves, possibly on different plans (grids), enqueued as
+ * one unit: rho[i], phi[i], E[i] follow vgf_solve for plans[i] (phi and E
+ * arrays may be NULL, or hold NULL entries). The same plan may appear more
+ * than once: its solves are then serialised on its workspace. Enqueued on
+ * `stream`; on the first invalid entry nothing is enqueued. */
+vgf_status vgf_solve_batched(const vgf_plan* plans, int count, const void* const* rho,
+                             void* const* phi, void* const* E, hipStream_t stream);
+
+/* The truncation radius the plan uses (0 for HE). */
+vgf_status vgf_plan_get_L(vgf_plan plan, double* L);
+
+/* Device bytes held by the plan (spectra, twiddles and solve workspace). */
+vgf_status vgf_plan_workspace_bytes(vgf_plan plan, size_t* bytes);
+
+/* Copies the FP64 restricted kernel w[n], n in [0,n_0) x ... (even octant;
+ * the "numerical Green's function" of Sec. II, or the HE kernel) to the
+ * host buffer `host_out` of prod(n) doubles. Synchronous. */
+vgf_status vgf_plan_get_kernel(vgf_plan plan, double* host_out);
+
+/* Copies the FP64 spectrum of the 2N-periodic kernel (real and even) on the
+ * octant kappa in [0, n_0] x ... to `host_out` (prod(n_a + 1) doubles),
+ * unscaled (DFT convention sum_n W[n] exp(-2 pi i kappa.n / 2N)).
+ * Synchronous. */
+vgf_status vgf_plan_get_spectrum(vgf_plan plan, double* host_out);
+
+/* The last HIP error code recorded by a call on this plan (hipSuccess if
+ * none). */
+int vgf_plan_hip_error(vgf_plan plan);
+
+void vgf_plan_destroy(vgf_plan plan);
+
+/* Static, NUL-terminated description of a status code. */
+const char* vgf_status_string(vgf_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VGF_H */

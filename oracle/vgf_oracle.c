@@ -192,15 +192,24 @@ int orc_vgf_kernel(int dim, const int64_t* n, const double* h, double L,
         double wgt = (m == 0 || m == 2 * N) ? 1.0 : 2.0;
         cosm[m * N + j] = wgt * c / (double)M;
       }
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int64_t o = 0; o < outer; ++o)
-      for (int64_t j = 0; j < N; ++j)
-        for (int64_t i = 0; i < inner; ++i) {
-          ksum acc = {0.0, 0.0};
-          for (int64_t m = 0; m < in_len; ++m)
-            kadd(&acc, cosm[m * N + j] * buf[(o * in_len + m) * inner + i]);
-          out[(o * N + j) * inner + i] = kval(&acc);
+    /* every output is one compensated sum over m in increasing order; the
+     * loops run m outside i only so that rows are read contiguously */
+#pragma omp parallel
+    {
+      ksum* acc = (ksum*)malloc(sizeof(ksum) * (size_t)inner);
+#pragma omp for collapse(2) schedule(static)
+      for (int64_t o = 0; o < outer; ++o)
+        for (int64_t j = 0; j < N; ++j) {
+          for (int64_t i = 0; i < inner; ++i) acc[i].s = acc[i].c = 0.0;
+          for (int64_t m = 0; m < in_len; ++m) {
+            const double cm = cosm[m * N + j];
+            const double* row = buf + (o * in_len + m) * inner;
+            for (int64_t i = 0; i < inner; ++i) kadd(&acc[i], cm * row[i]);
+          }
+          for (int64_t i = 0; i < inner; ++i) out[(o * N + j) * inner + i] = kval(&acc[i]);
         }
+      free(acc);
+    }
     free(cosm);
     free(buf);
     buf = out;
@@ -382,8 +391,21 @@ double orc_conv_direct_point(int dim, const int64_t* n, const double* w_oct,
 /* any other factor). Unnormalised: y[k] = sum_j x[j] exp(sign 2 pi i jk/n).*/
 /* ------------------------------------------------------------------------ */
 
-static void fft_rec(int64_t n, const cplx* x, int64_t stride, cplx* y,
-                    int sign) {
+/* Twiddle table of a top-level length n0: tab[t] = exp(sign 2 pi i t / n0),
+ * t in [0, n0), each entry from cis_frac (long double, rounded once). A
+ * sub-transform of length n = n0 / stride_t reads tab[(t mod n) * tstep]. */
+static cplx* make_table(int64_t n0, int sign) {
+  cplx* tab = (cplx*)malloc(sizeof(cplx) * (size_t)n0);
+  for (int64_t t = 0; t < n0; ++t) {
+    double c, s;
+    cis_frac(t, n0, &c, &s);
+    tab[t] = c + sign * s * I;
+  }
+  return tab;
+}
+
+static void fft_rec(int64_t n, const cplx* x, int64_t stride, cplx* y, const cplx* tab,
+                    int64_t tstep) {
   if (n == 1) {
     y[0] = x[0];
     return;
@@ -393,30 +415,19 @@ static void fft_rec(int64_t n, const cplx* x, int64_t stride, cplx* y,
   if (r == n) { /* direct DFT */
     for (int64_t k = 0; k < n; ++k) {
       cplx acc = 0.0;
-      for (int64_t j = 0; j < n; ++j) {
-        double c, s;
-        cis_frac(j * k, n, &c, &s);
-        acc += x[j * stride] * (c + sign * s * I);
-      }
+      for (int64_t j = 0; j < n; ++j) acc += x[j * stride] * tab[((j * k) % n) * tstep];
       y[k] = acc;
     }
     return;
   }
-  for (int64_t s = 0; s < r; ++s) fft_rec(m, x + s * stride, stride * r, y + s * m, sign);
+  for (int64_t s = 0; s < r; ++s)
+    fft_rec(m, x + s * stride, stride * r, y + s * m, tab, tstep * r);
   cplx t[3];
   for (int64_t k = 0; k < m; ++k) {
-    for (int64_t s = 0; s < r; ++s) {
-      double c, sn;
-      cis_frac(s * k, n, &c, &sn);
-      t[s] = y[s * m + k] * (c + sign * sn * I);
-    }
+    for (int64_t s = 0; s < r; ++s) t[s] = y[s * m + k] * tab[((s * k) % n) * tstep];
     for (int64_t q = 0; q < r; ++q) {
       cplx acc = 0.0;
-      for (int64_t s = 0; s < r; ++s) {
-        double c, sn;
-        cis_frac(s * q, r, &c, &sn);
-        acc += t[s] * (c + sign * sn * I);
-      }
+      for (int64_t s = 0; s < r; ++s) acc += t[s] * tab[((s * q * m) % n) * tstep];
       y[q * m + k] = acc;
     }
   }
@@ -426,9 +437,11 @@ static void fft_rec(int64_t n, const cplx* x, int64_t stride, cplx* y,
 void orc_fft1d(int64_t n, double* xy, int sign) {
   cplx* x = (cplx*)xy;
   cplx* y = (cplx*)malloc(sizeof(cplx) * (size_t)n);
-  fft_rec(n, x, 1, y, sign);
+  cplx* tab = make_table(n, sign);
+  fft_rec(n, x, 1, y, tab, 1);
   memcpy(x, y, sizeof(cplx) * (size_t)n);
   free(y);
+  free(tab);
 }
 
 /* Textbook O(n^2) DFT, the brute-force check of orc_fft1d. */
@@ -454,6 +467,7 @@ static void fftnd(int dim, const int64_t* shape, cplx* x, int sign) {
     int64_t len = shape[a], inner = 1, outer = 1;
     for (int b = a + 1; b < dim; ++b) inner *= shape[b];
     for (int b = 0; b < a; ++b) outer *= shape[b];
+    cplx* tab = make_table(len, sign);
 #pragma omp parallel
     {
       cplx* line = (cplx*)malloc(sizeof(cplx) * (size_t)len);
@@ -463,12 +477,13 @@ static void fftnd(int dim, const int64_t* shape, cplx* x, int sign) {
         for (int64_t i = 0; i < inner; ++i) {
           cplx* base = x + o * len * inner + i;
           for (int64_t j = 0; j < len; ++j) line[j] = base[j * inner];
-          fft_rec(len, line, 1, res, sign);
+          fft_rec(len, line, 1, res, tab, 1);
           for (int64_t j = 0; j < len; ++j) base[j * inner] = res[j];
         }
       free(line);
       free(res);
     }
+    free(tab);
   }
 }
 

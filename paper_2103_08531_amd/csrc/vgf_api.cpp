@@ -1,0 +1,572 @@
+// vgf_api.cpp -- host runtime behind the C ABI in include/vgf.h.
+//
+// A plan fixes the grid, the method (VGF or HE), the precision and the
+// requested outputs. Plan creation runs the one-time FP64 precompute on the
+// GPU (Sec. II of the paper: the windowed-kernel spectrum on the
+// 4N-oversampled grid, its inverse DFT restricted to the 2N solve grid, and
+// that kernel's 2N spectrum), then keeps only what solves need: the real,
+// even kernel spectrum on its non-negative octant, pre-divided by the inverse
+// FFT normalisation prod_a(2 N_a) and rounded once to the plan precision.
+//
+// Solve data flow (3D; axis 2 contiguous, P_a = 2 N_a, H = N_2 + 1):
+//   rho [N0][N1][N2]  --r2c axis 2-->  X1 [N0][N1][H]
+//   X1                --c2c axis 1-->  X2 [N0][P1][H]
+//   X2  --fused axis 0 (fwd, x kernel, x -i k_a kernel, inv)-->  Y_f [N0][P1][H]
+//   Y_f               --c2c^-1 axis 1--> Z_f [N0][N1][H]
+//   Z_f               --c2r axis 2-->  phi / E_a [N0][N1][N2]
+// 2D skips the middle-axis passes. All passes are asynchronous on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "vgf.h"
+#include "vgf_internal.hpp"
+
+using vgf::cplx;
+
+struct vgf_plan_s {
+  int dim = 0;
+  int64_t n[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int64_t P[3] = {1, 1, 1};
+  int64_t H = 1;  // N_last + 1
+  vgf_method method = VGF_METHOD_VGF;
+  vgf_precision prec = VGF_F64;
+  double L = 0.0;
+  unsigned outputs = 0;
+  int nf_max = 0;
+
+  // device memory
+  void* spec = nullptr;          // octant prod(n_a+1), plan type, scaled by 1/prod(P)
+  double* w64 = nullptr;         // restricted kernel octant prod(n_a), FP64
+  double* spec64 = nullptr;      // unscaled spectrum octant, FP64
+  void* tw[3] = {nullptr, nullptr, nullptr};  // per-axis twiddles exp(-2 pi i e / P_a)
+  void* ws = nullptr;            // solve workspace
+  size_t off_x1 = 0, off_x2 = 0, off_y = 0, off_z = 0;
+  size_t bytes = 0;
+  hipError_t last_err = hipSuccess;
+};
+
+namespace {
+
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+
+bool size_supported(int64_t n) { return n >= 8 && vgf::supported_fft_len(2 * n); }
+
+int64_t prod(const int64_t* v, int d) {
+  int64_t p = 1;
+  for (int a = 0; a < d; ++a) p *= v[a];
+  return p;
+}
+
+// cos / sin of 2 pi t / n, argument reduced exactly in integers and the
+// function evaluated in long double, then rounded once.
+void cis(int64_t t, int64_t n, long double* c, long double* s) {
+  t %= n;
+  if (t < 0) t += n;
+  const long double ang = 2.0L * kPiL * (long double)t / (long double)n;
+  *c = cosl(ang);
+  *s = sinl(ang);
+}
+
+template <typename T> std::vector<cplx<T>> make_twiddles(int64_t P) {
+  std::vector<cplx<T>> v((size_t)P);
+  for (int64_t e = 0; e < P; ++e) {
+    long double c, s;
+    cis(e, P, &c, &s);
+    v[(size_t)e].x = (T)(double)c;
+    v[(size_t)e].y = (T)(double)(-s);
+  }
+  return v;
+}
+
+size_t max_workspace_env() {
+  const char* e = std::getenv("VGF_MAX_WORKSPACE");
+  if (!e || !*e) return (size_t)-1;
+  char* end = nullptr;
+  unsigned long long v = std::strtoull(e, &end, 10);
+  return (size_t)v;
+}
+
+struct DevFree {
+  void operator()(void* p) const {
+    if (p) (void)hipFree(p);
+  }
+};
+
+void release(vgf_plan p) {
+  if (!p) return;
+  DevFree f;
+  f(p->spec);
+  f(p->w64);
+  f(p->spec64);
+  for (int a = 0; a < 3; ++a) f(p->tw[a]);
+  f(p->ws);
+  delete p;
+}
+
+// Uploads an FP64 table and applies it along one axis:
+// out[o][j][i] = sum_m mat[m*J + j] in[o][m][i]. Waits for the stream so
+// the host table can be reused for the next axis.
+hipError_t apply_axis(const std::vector<double>& host_mat, double* dmat, const double* in,
+                      double* out, int64_t outer, int M, int J, int64_t inner, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(dmat, host_mat.data(), sizeof(double) * host_mat.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = vgf::launch_axis_apply(in, out, dmat, outer, M, J, inner, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+// The one-time FP64 precompute. Fills p->w64 (kernel octant), p->spec64
+// (spectrum octant) and p->spec (plan-precision scaled copy); temporaries
+// are freed before returning.
+vgf_status precompute(vgf_plan p, hipStream_t s) {
+  const int d = p->dim;
+  double *bufA = nullptr, *bufB = nullptr, *mat = nullptr;
+  std::vector<double> host_mat;
+  int64_t cur[3] = {1, 1, 1}, ext[3] = {1, 1, 1}, oct = 1, gsz = 1, maxmat = 0;
+  double dk[3] = {0, 0, 0}, pp = 1.0;
+  hipError_t err = hipSuccess;
+
+  for (int a = 0; a < d; ++a) {
+    ext[a] = 2 * p->n[a] + 1;
+    oct *= p->n[a] + 1;
+    pp *= (double)p->P[a];
+    maxmat = std::max<int64_t>(maxmat, std::max(ext[a] * p->n[a], p->n[a] * (p->n[a] + 1)));
+  }
+  gsz = p->method == VGF_METHOD_VGF ? prod(ext, d) : oct;
+  do {
+    if ((err = hipMalloc(&bufA, sizeof(double) * (size_t)gsz)) != hipSuccess) break;
+    if ((err = hipMalloc(&bufB, sizeof(double) * (size_t)gsz)) != hipSuccess) break;
+    if ((err = hipMalloc(&mat, sizeof(double) * (size_t)maxmat)) != hipSuccess) break;
+
+    if (p->method == VGF_METHOD_VGF) {
+      // (i) spectrum samples on m in [0, 2N]^d of the 4N grid, k = 2 pi m / (4 N h)
+      for (int a = 0; a < d; ++a)
+        dk[a] = (double)(2.0L * kPiL / (4.0L * (long double)p->n[a] * (long double)p->h[a]));
+      if ((err = vgf::launch_ghat(bufA, d, ext, dk, p->L, s)) != hipSuccess) break;
+      // (ii) inverse DFT over the 4N grid restricted to n_a in [0, N_a):
+      //  out[j] = (4N)^{-1} (f(0) + 2 sum_{0<m<2N} f(m) cos(2 pi m j / 4N) + f(2N) cos(pi j))
+      for (int a = 0; a < d; ++a) cur[a] = ext[a];
+      double *src = bufA, *dst = bufB;
+      for (int a = 0; a < d && err == hipSuccess; ++a) {
+        const int64_t N = p->n[a], M4 = 4 * p->n[a], Mi = ext[a];
+        host_mat.assign((size_t)(Mi * N), 0.0);
+        for (int64_t m = 0; m < Mi; ++m)
+          for (int64_t j = 0; j < N; ++j) {
+            long double c, sn;
+            cis(m * j, M4, &c, &sn);
+            const long double wgt = (m == 0 || m == 2 * N) ? 1.0L : 2.0L;
+            host_mat[(size_t)(m * N + j)] = (double)(wgt * c / (long double)M4);
+          }
+        int64_t outer = 1, inner = 1;
+        for (int b = 0; b < a; ++b) outer *= cur[b];
+        for (int b = a + 1; b < d; ++b) inner *= cur[b];
+        double* target = (a == d - 1) ? p->w64 : dst;
+        err = apply_axis(host_mat, mat, src, target, outer, (int)Mi, (int)N, inner, s);
+        cur[a] = N;
+        std::swap(src, dst);
+      }
+      if (err != hipSuccess) break;
+    } else {
+      if ((err = vgf::launch_he_kernel(p->w64, d, p->n, p->h, s)) != hipSuccess) break;
+    }
+
+    // (iii) spectrum of the 2N-periodic even kernel (zero where |n_a| = N_a):
+    //  S[k] = w[0] + 2 sum_{0<n<N} w[n] cos(2 pi n k / 2N),  k in [0, N]
+    for (int a = 0; a < d; ++a) cur[a] = p->n[a];
+    const double* from = p->w64;
+    double* tmp[2] = {bufA, bufB};
+    for (int a = 0; a < d && err == hipSuccess; ++a) {
+      const int64_t N = p->n[a], P2 = 2 * p->n[a];
+      host_mat.assign((size_t)(N * (N + 1)), 0.0);
+      for (int64_t m = 0; m < N; ++m)
+        for (int64_t k = 0; k <= N; ++k) {
+          long double c, sn;
+          cis(m * k, P2, &c, &sn);
+          host_mat[(size_t)(m * (N + 1) + k)] = (double)((m == 0 ? 1.0L : 2.0L) * c);
+        }
+      int64_t outer = 1, inner = 1;
+      for (int b = 0; b < a; ++b) outer *= cur[b];
+      for (int b = a + 1; b < d; ++b) inner *= cur[b];
+      double* target = (a == d - 1) ? p->spec64 : tmp[a % 2];
+      err = apply_axis(host_mat, mat, from, target, outer, (int)N, (int)(N + 1), inner, s);
+      cur[a] = N + 1;
+      from = target;
+    }
+    if (err != hipSuccess) break;
+
+    // plan-precision copy, divided by the inverse FFT normalisation
+    if (p->prec == VGF_F32)
+      err = vgf::launch_scale_convert<float>(p->spec64, (float*)p->spec, oct, 1.0 / pp, s);
+    else
+      err = vgf::launch_scale_convert<double>(p->spec64, (double*)p->spec, oct, 1.0 / pp, s);
+    if (err != hipSuccess) break;
+    err = hipStreamSynchronize(s);
+  } while (false);
+
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(bufA);
+  (void)hipFree(bufB);
+  (void)hipFree(mat);
+  if (err == hipSuccess) return VGF_OK;
+  p->last_err = err;
+  return err == hipErrorOutOfMemory ? VGF_ERR_OUT_OF_MEMORY : VGF_ERR_HIP;
+}
+
+vgf_status hip_status(vgf_plan p, hipError_t e) {
+  if (e == hipSuccess) return VGF_OK;
+  p->last_err = e;
+  return VGF_ERR_HIP;
+}
+
+template <typename T> struct Bufs {
+  cplx<T>* x1;
+  cplx<T>* x2;
+  cplx<T>* y;
+  cplx<T>* z;
+};
+
+template <typename T> Bufs<T> bufs(vgf_plan p) {
+  char* base = (char*)p->ws;
+  return Bufs<T>{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2),
+                 (cplx<T>*)(base + p->off_y), (cplx<T>*)(base + p->off_z)};
+}
+
+template <typename T> vgf::FusedGeom<T> fused_geom(vgf_plan p) {
+  vgf::FusedGeom<T> g{};
+  const int d = p->dim;
+  g.dim = d;
+  g.n0 = (int)p->n[0];
+  g.n1 = (int)p->n[1];
+  g.n2 = d == 3 ? (int)p->n[2] : 0;
+  g.h_last = (int)p->H;
+  g.ncols = d == 3 ? p->P[1] * p->H : p->H;
+  g.ks0 = (T)(double)(2.0L * kPiL / ((long double)p->P[0] * (long double)p->h[0]));
+  g.ks1 = (T)(double)(2.0L * kPiL / ((long double)p->P[1] * (long double)p->h[1]));
+  g.ks2 = d == 3 ? (T)(double)(2.0L * kPiL / ((long double)p->P[2] * (long double)p->h[2])) : T(0);
+  return g;
+}
+
+template <typename T>
+vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H;
+  const int64_t vol = prod(p->n, d);
+  Bufs<T> b = bufs<T>(p);
+  const T* spec = (const T*)p->spec;
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  vgf::FusedGeom<T> g = fused_geom<T>(p);
+  g.nf = 0;
+  if (phi) g.fields[g.nf++] = 0;
+  if (E)
+    for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
+  hipError_t e;
+  if (d == 3) {
+    const int64_t P1 = p->P[1];
+    g.out_fs = N0 * P1 * H;
+    e = vgf::launch_r2c<T>((int)p->P[2], rho, b.x1, N0 * N1, tw(2), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    vgf::StridedArgs fa{H, H, H, N1 * H, P1 * H, 0, 0, (int)N0, 1};
+    e = vgf::launch_c2c<T>((int)P1, -1, b.x1, b.x2, fa, tw(1), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    e = vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    vgf::StridedArgs ia{H, H, H, P1 * H, N1 * H, N0 * P1 * H, N0 * N1 * H, (int)N0, g.nf};
+    e = vgf::launch_c2c<T>((int)P1, 1, b.y, b.z, ia, tw(1), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    const int64_t zfs = N0 * N1 * H;
+    int f0 = 0;
+    if (phi) {
+      e = vgf::launch_c2r<T>((int)p->P[2], b.z, phi, N0 * N1, 1, 0, 0, tw(2), s);
+      if (e != hipSuccess) return hip_status(p, e);
+      f0 = 1;
+    }
+    if (E) {
+      e = vgf::launch_c2r<T>((int)p->P[2], b.z + f0 * zfs, E, N0 * N1, d, zfs, vol, tw(2), s);
+      if (e != hipSuccess) return hip_status(p, e);
+    }
+  } else {
+    g.out_fs = N0 * H;
+    e = vgf::launch_r2c<T>((int)p->P[1], rho, b.x1, N0, tw(1), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    e = vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    const int64_t yfs = N0 * H;
+    int f0 = 0;
+    if (phi) {
+      e = vgf::launch_c2r<T>((int)p->P[1], b.y, phi, N0, 1, 0, 0, tw(1), s);
+      if (e != hipSuccess) return hip_status(p, e);
+      f0 = 1;
+    }
+    if (E) {
+      e = vgf::launch_c2r<T>((int)p->P[1], b.y + f0 * yfs, E, N0, d, yfs, vol, tw(1), s);
+      if (e != hipSuccess) return hip_status(p, e);
+    }
+  }
+  return VGF_OK;
+}
+
+template <typename T>
+vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H;
+  Bufs<T> b = bufs<T>(p);
+  const T* spec = (const T*)p->spec;
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  vgf::FusedGeom<T> g = fused_geom<T>(p);
+  g.nf = 0;
+  if (g_phi) g.fields[g.nf++] = 0;
+  if (g_E)
+    for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
+  hipError_t e;
+  if (d == 3) {
+    const int64_t P1 = p->P[1];
+    const int64_t lines = N0 * N1, zfs = N0 * N1 * H, yfs = N0 * P1 * H;
+    // forward half-transforms of every incoming gradient into the Z region
+    int f0 = 0;
+    if (g_phi) {
+      e = vgf::launch_r2c<T>((int)p->P[2], g_phi, b.z, lines, tw(2), s);
+      if (e != hipSuccess) return hip_status(p, e);
+      f0 = 1;
+    }
+    if (g_E) {
+      e = vgf::launch_r2c<T>((int)p->P[2], g_E, b.z + f0 * zfs, d * lines, tw(2), s);
+      if (e != hipSuccess) return hip_status(p, e);
+    }
+    vgf::StridedArgs fa{H, H, H, N1 * H, P1 * H, zfs, yfs, (int)N0, g.nf};
+    e = vgf::launch_c2c<T>((int)P1, -1, b.z, b.y, fa, tw(1), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    g.in_fs = yfs;
+    e = vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x2, g, spec, tw(0), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    vgf::StridedArgs ia{H, H, H, P1 * H, N1 * H, 0, 0, (int)N0, 1};
+    e = vgf::launch_c2c<T>((int)P1, 1, b.x2, b.x1, ia, tw(1), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    e = vgf::launch_c2r<T>((int)p->P[2], b.x1, g_rho, lines, 1, 0, 0, tw(2), s);
+    if (e != hipSuccess) return hip_status(p, e);
+  } else {
+    const int64_t yfs = N0 * H;
+    int f0 = 0;
+    if (g_phi) {
+      e = vgf::launch_r2c<T>((int)p->P[1], g_phi, b.y, N0, tw(1), s);
+      if (e != hipSuccess) return hip_status(p, e);
+      f0 = 1;
+    }
+    if (g_E) {
+      e = vgf::launch_r2c<T>((int)p->P[1], g_E, b.y + f0 * yfs, d * N0, tw(1), s);
+      if (e != hipSuccess) return hip_status(p, e);
+    }
+    g.in_fs = yfs;
+    e = vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x1, g, spec, tw(0), s);
+    if (e != hipSuccess) return hip_status(p, e);
+    e = vgf::launch_c2r<T>((int)p->P[1], b.x1, g_rho, N0, 1, 0, 0, tw(1), s);
+    if (e != hipSuccess) return hip_status(p, e);
+  }
+  return VGF_OK;
+}
+
+vgf_status check_solve_args(vgf_plan p, const void* rho, const void* phi, const void* E) {
+  if (!p || !rho) return VGF_ERR_INVALID_ARG;
+  if (!phi && !E) return VGF_ERR_INVALID_ARG;
+  if (phi && !(p->outputs & VGF_OUT_PHI)) return VGF_ERR_NOT_REQUESTED;
+  if (E && !(p->outputs & VGF_OUT_E)) return VGF_ERR_NOT_REQUESTED;
+  return VGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vgf_status_string(vgf_status st) {
+  switch (st) {
+    case VGF_OK: return "ok";
+    case VGF_ERR_INVALID_ARG: return "invalid argument";
+    case VGF_ERR_UNSUPPORTED_SIZE: return "unsupported grid size";
+    case VGF_ERR_L_WINDOW: return "truncation radius L outside the admissible window";
+    case VGF_ERR_OUT_OF_MEMORY: return "out of device memory (or above VGF_MAX_WORKSPACE)";
+    case VGF_ERR_HIP: return "HIP runtime error";
+    case VGF_ERR_NOT_REQUESTED: return "output not requested at plan creation";
+  }
+  return "unknown status";
+}
+
+vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const double* h,
+                           vgf_method method, vgf_precision prec, double L, unsigned outputs,
+                           hipStream_t stream) {
+  if (!out) return VGF_ERR_INVALID_ARG;
+  *out = nullptr;
+  if ((dim != 2 && dim != 3) || !n || !h) return VGF_ERR_INVALID_ARG;
+  if (method != VGF_METHOD_VGF && method != VGF_METHOD_HE) return VGF_ERR_INVALID_ARG;
+  if (prec != VGF_F64 && prec != VGF_F32) return VGF_ERR_INVALID_ARG;
+  if (outputs == 0 || (outputs & ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E))) return VGF_ERR_INVALID_ARG;
+  for (int a = 0; a < dim; ++a) {
+    if (!(h[a] > 0.0) || !std::isfinite(h[a])) return VGF_ERR_INVALID_ARG;
+    if (n[a] <= 0) return VGF_ERR_INVALID_ARG;
+  }
+  for (int a = 0; a < dim; ++a)
+    if (!size_supported(n[a])) return VGF_ERR_UNSUPPORTED_SIZE;
+
+  double diam2 = 0.0, upper = INFINITY;
+  for (int a = 0; a < dim; ++a) {
+    const double ext = (double)(n[a] - 1) * h[a];
+    diam2 += ext * ext;
+    upper = std::min(upper, 4.0 * (double)n[a] * h[a] - ext);
+  }
+  const double diam = std::sqrt(diam2);
+  double Lp = 0.0;
+  if (method == VGF_METHOD_VGF) {
+    Lp = (L > 0.0) ? L : 1.1 * diam;
+    if (!(Lp > diam) || !(Lp < upper) || !std::isfinite(Lp)) return VGF_ERR_L_WINDOW;
+  }
+
+  vgf_plan p = new (std::nothrow) vgf_plan_s();
+  if (!p) return VGF_ERR_OUT_OF_MEMORY;
+  p->dim = dim;
+  for (int a = 0; a < dim; ++a) {
+    p->n[a] = n[a];
+    p->h[a] = h[a];
+    p->P[a] = 2 * n[a];
+  }
+  p->H = n[dim - 1] + 1;
+  p->method = method;
+  p->prec = prec;
+  p->L = Lp;
+  p->outputs = outputs;
+  p->nf_max = ((outputs & VGF_OUT_PHI) ? 1 : 0) + ((outputs & VGF_OUT_E) ? dim : 0);
+
+  const size_t rb = prec == VGF_F32 ? 4 : 8, cb = 2 * rb;
+  const int64_t N0 = n[0], N1 = n[1], H = p->H;
+  int64_t oct = 1, vol = 1;
+  for (int a = 0; a < dim; ++a) {
+    oct *= (n[a] + 1);
+    vol *= n[a];
+  }
+  size_t x1 = 0, x2 = 0, y = 0, z = 0;
+  if (dim == 3) {
+    x1 = (size_t)(N0 * N1 * H);
+    x2 = (size_t)(N0 * p->P[1] * H);
+    y = (size_t)p->nf_max * x2;
+    z = (size_t)p->nf_max * x1;
+  } else {
+    x1 = (size_t)(N0 * H);
+    y = (size_t)p->nf_max * x1;
+  }
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  p->off_x1 = 0;
+  p->off_x2 = align(x1 * cb);
+  p->off_y = p->off_x2 + align(x2 * cb);
+  p->off_z = p->off_y + align(y * cb);
+  const size_t ws_bytes = p->off_z + align(z * cb);
+  size_t tw_bytes = 0;
+  for (int a = 0; a < dim; ++a) tw_bytes += (size_t)p->P[a] * cb;
+  p->bytes = ws_bytes + tw_bytes + (size_t)oct * (rb + 8) + (size_t)vol * 8;
+  if (p->bytes > max_workspace_env()) {
+    release(p);
+    return VGF_ERR_OUT_OF_MEMORY;
+  }
+
+  hipError_t err = hipSuccess;
+  vgf_status st = VGF_OK;
+  do {
+    if ((err = hipMalloc(&p->ws, ws_bytes)) != hipSuccess) break;
+    if ((err = hipMalloc(&p->spec, (size_t)oct * rb)) != hipSuccess) break;
+    if ((err = hipMalloc((void**)&p->spec64, (size_t)oct * 8)) != hipSuccess) break;
+    if ((err = hipMalloc((void**)&p->w64, (size_t)vol * 8)) != hipSuccess) break;
+    for (int a = 0; a < dim && err == hipSuccess; ++a) {
+      err = hipMalloc(&p->tw[a], (size_t)p->P[a] * cb);
+      if (err != hipSuccess) break;
+      if (prec == VGF_F32) {
+        auto t = make_twiddles<float>(p->P[a]);
+        err = hipMemcpy(p->tw[a], t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
+      } else {
+        auto t = make_twiddles<double>(p->P[a]);
+        err = hipMemcpy(p->tw[a], t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
+      }
+    }
+  } while (false);
+  if (err != hipSuccess) {
+    st = err == hipErrorOutOfMemory ? VGF_ERR_OUT_OF_MEMORY : VGF_ERR_HIP;
+    release(p);
+    (void)hipGetLastError();
+    return st;
+  }
+  st = precompute(p, stream);
+  if (st != VGF_OK) {
+    release(p);
+    (void)hipGetLastError();
+    return st;
+  }
+  *out = p;
+  return VGF_OK;
+}
+
+vgf_status vgf_solve(vgf_plan p, const void* rho, void* phi, void* E, hipStream_t stream) {
+  vgf_status st = check_solve_args(p, rho, phi, E);
+  if (st != VGF_OK) return st;
+  if (p->prec == VGF_F32)
+    return solve_t<float>(p, (const float*)rho, (float*)phi, (float*)E, stream);
+  return solve_t<double>(p, (const double*)rho, (double*)phi, (double*)E, stream);
+}
+
+vgf_status vgf_solve_adjoint(vgf_plan p, const void* g_phi, const void* g_E, void* g_rho,
+                             hipStream_t stream) {
+  if (!p || !g_rho || (!g_phi && !g_E)) return VGF_ERR_INVALID_ARG;
+  if (g_phi && !(p->outputs & VGF_OUT_PHI)) return VGF_ERR_NOT_REQUESTED;
+  if (g_E && !(p->outputs & VGF_OUT_E)) return VGF_ERR_NOT_REQUESTED;
+  if (p->prec == VGF_F32)
+    return adjoint_t<float>(p, (const float*)g_phi, (const float*)g_E, (float*)g_rho, stream);
+  return adjoint_t<double>(p, (const double*)g_phi, (const double*)g_E, (double*)g_rho, stream);
+}
+
+vgf_status vgf_solve_batched(const vgf_plan* plans, int count, const void* const* rho,
+                             void* const* phi, void* const* E, hipStream_t stream) {
+  if (count < 0 || (count > 0 && (!plans || !rho))) return VGF_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    vgf_status st = check_solve_args(plans[i], rho[i], phi ? phi[i] : nullptr, E ? E[i] : nullptr);
+    if (st != VGF_OK) return st;
+  }
+  for (int i = 0; i < count; ++i) {
+    vgf_status st = vgf_solve(plans[i], rho[i], phi ? phi[i] : nullptr, E ? E[i] : nullptr, stream);
+    if (st != VGF_OK) return st;
+  }
+  return VGF_OK;
+}
+
+vgf_status vgf_plan_get_L(vgf_plan p, double* L) {
+  if (!p || !L) return VGF_ERR_INVALID_ARG;
+  *L = p->L;
+  return VGF_OK;
+}
+
+vgf_status vgf_plan_workspace_bytes(vgf_plan p, size_t* bytes) {
+  if (!p || !bytes) return VGF_ERR_INVALID_ARG;
+  *bytes = p->bytes;
+  return VGF_OK;
+}
+
+vgf_status vgf_plan_get_kernel(vgf_plan p, double* host_out) {
+  if (!p || !host_out) return VGF_ERR_INVALID_ARG;
+  const size_t cnt = (size_t)prod(p->n, p->dim);
+  return hip_status(p, hipMemcpy(host_out, p->w64, cnt * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+vgf_status vgf_plan_get_spectrum(vgf_plan p, double* host_out) {
+  if (!p || !host_out) return VGF_ERR_INVALID_ARG;
+  size_t cnt = 1;
+  for (int a = 0; a < p->dim; ++a) cnt *= (size_t)(p->n[a] + 1);
+  return hip_status(p, hipMemcpy(host_out, p->spec64, cnt * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+int vgf_plan_hip_error(vgf_plan p) { return p ? (int)p->last_err : (int)hipErrorInvalidValue; }
+
+void vgf_plan_destroy(vgf_plan p) { release(p); }
+
+}  // extern "C"

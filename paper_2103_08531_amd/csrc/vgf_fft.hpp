@@ -1,0 +1,280 @@
+// vgf_fft.hpp -- device-side building blocks of the batched FFTs used by the
+// solve path (gfx950, wave64).
+//
+// A workgroup transforms NL lines of length P at once. The lines are the
+// columns of an LDS tile laid out [position][line] with row pitch LP, so the
+// NL lines of a tile are contiguous in both HBM (adjacent columns of the
+// array) and LDS, and a wavefront touches consecutive addresses in both.
+// Thread tid owns line l = tid % NL and the butterflies j = q, q + NQ, ...
+// (q = tid / NL, NQ = NT / NL) of every stage.
+//
+// The transform is a Stockham autosort FFT: stage s with radix R and
+// Ns = product of the earlier radices reads positions j + r*P/R, multiplies
+// input r by w^(r*(j mod Ns)*P/(Ns*R)) (w = exp(-+2 pi i / P)), does an
+// R-point DFT and writes positions (j div Ns)*Ns*R + (j mod Ns) + r*Ns.
+// Results come out in natural order. Radices are 8, 4, 2 and 3.
+//
+// Zero padding to 2N (Eq. 3 of the paper pads rho to twice the box) is never
+// materialised: the forward transforms see only the first P/2 inputs, and
+// the first stage (radix R even, Ns = 1) skips its inputs r >= R/2, which are
+// exactly the positions >= P/2. Symmetrically, the inverse transforms keep
+// only the first P/2 outputs, and their last stage (Ns = P/R) stores only
+// outputs r < R/2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "vgf_internal.hpp"
+
+namespace vgf {
+
+template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C c_mulc(C a, C b) {
+  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by S*i  (S = -1: -i, S = +1: +i)
+template <int S, typename C> __device__ __forceinline__ C c_muli(C a) {
+  if constexpr (S < 0) return C{a.y, -a.x};
+  else return C{-a.y, a.x};
+}
+
+// ---------------------------------------------------------------------------
+// radix plan (compile time). P = 2^a 3^b. Forward order: the power-of-two
+// stages (8s, then the 4s or the 2), then the 3s; the inverse uses the
+// reverse order, so the last forward stage and the first inverse stage have
+// the same radix and the same butterfly-to-thread map.
+// ---------------------------------------------------------------------------
+constexpr int pow2_of(int P) { int a = 0; while (P % 2 == 0) { P /= 2; ++a; } return a; }
+constexpr int pow3_of(int P) { while (P % 2 == 0) P /= 2; int b = 0; while (P % 3 == 0) { P /= 3; ++b; } return b; }
+constexpr bool fft_len_ok(int P) {
+  int p = P;
+  while (p % 2 == 0) p /= 2;
+  while (p % 3 == 0) p /= 3;
+  return p == 1 && pow2_of(P) >= 1;
+}
+constexpr int n_pow2_stages(int P) { return (pow2_of(P) + 2) / 3; }
+constexpr int n_stages(int P) { return n_pow2_stages(P) + pow3_of(P); }
+constexpr int fwd_radix(int P, int s) {
+  const int a = pow2_of(P), q = a / 3, r = a % 3, s2 = n_pow2_stages(P);
+  if (s >= s2) return 3;
+  if (r == 0) return 8;
+  if (r == 2) return (s < q) ? 8 : 4;
+  if (q == 0) return 2;
+  return (s < q - 1) ? 8 : 4;
+}
+template <int SIGN> constexpr int radix_at(int P, int s) {
+  return SIGN < 0 ? fwd_radix(P, s) : fwd_radix(P, n_stages(P) - 1 - s);
+}
+template <int SIGN> constexpr int ns_at(int P, int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= radix_at<SIGN>(P, i);
+  return ns;
+}
+
+// ---------------------------------------------------------------------------
+// R-point DFTs in registers, y_k = sum_j x_j exp(S 2 pi i jk / R)
+// ---------------------------------------------------------------------------
+template <typename T> struct K {
+  static constexpr T r12 = T(0.70710678118654752440084436210484903928);  // 1/sqrt(2)
+  static constexpr T s3 = T(0.86602540378443864676372317075293618347);   // sqrt(3)/2
+};
+
+template <int S, typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  C t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+  C t2 = c_add(a1, a3), t3 = c_muli<S>(c_sub(a1, a3));
+  a0 = c_add(t0, t2);
+  a2 = c_sub(t0, t2);
+  a1 = c_add(t1, t3);
+  a3 = c_sub(t1, t3);
+}
+
+template <int S, typename C> __device__ __forceinline__ void dft8_impl(C* v) {
+  using T = decltype(v[0].x);
+  // even / odd 4-point DFTs
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<S>(e0, e1, e2, e3);
+  dft4<S>(o0, o1, o2, o3);
+  // twiddles w8^k, w8 = exp(S 2 pi i / 8)
+  const T c = K<T>::r12;
+  C t1, t2, t3;
+  if constexpr (S < 0) {
+    t1 = C{(o1.x + o1.y) * c, (o1.y - o1.x) * c};   // (1 - i)/sqrt2
+    t3 = C{(o3.y - o3.x) * c, -(o3.x + o3.y) * c};  // (-1 - i)/sqrt2
+  } else {
+    t1 = C{(o1.x - o1.y) * c, (o1.x + o1.y) * c};   // (1 + i)/sqrt2
+    t3 = C{-(o3.x + o3.y) * c, (o3.x - o3.y) * c};  // (-1 + i)/sqrt2
+  }
+  t2 = c_muli<S>(o2);
+  v[0] = c_add(e0, o0);
+  v[4] = c_sub(e0, o0);
+  v[1] = c_add(e1, t1);
+  v[5] = c_sub(e1, t1);
+  v[2] = c_add(e2, t2);
+  v[6] = c_sub(e2, t2);
+  v[3] = c_add(e3, t3);
+  v[7] = c_sub(e3, t3);
+}
+
+template <int S, typename C> __device__ __forceinline__ void dft3_impl(C* v) {
+  using T = decltype(v[0].x);
+  C a0 = v[0], a1 = v[1], a2 = v[2];
+  C s = c_add(a1, a2), d = c_sub(a1, a2);
+  C m = C{a0.x - T(0.5) * s.x, a0.y - T(0.5) * s.y};
+  // S*i*(sqrt3/2)*d
+  C u = c_muli<S>(C{K<T>::s3 * d.x, K<T>::s3 * d.y});
+  v[0] = c_add(a0, s);
+  v[1] = c_add(m, u);
+  v[2] = c_sub(m, u);
+}
+
+template <int R, int S, typename C> struct Dft;
+template <int S, typename C> struct Dft<2, S, C> {
+  __device__ __forceinline__ static void run(C* v) { C a = v[0], b = v[1]; v[0] = c_add(a, b); v[1] = c_sub(a, b); }
+};
+template <int S, typename C> struct Dft<3, S, C> {
+  __device__ __forceinline__ static void run(C* v) { dft3_impl<S>(v); }
+};
+template <int S, typename C> struct Dft<4, S, C> {
+  __device__ __forceinline__ static void run(C* v) { dft4<S>(v[0], v[1], v[2], v[3]); }
+};
+template <int S, typename C> struct Dft<8, S, C> {
+  __device__ __forceinline__ static void run(C* v) { dft8_impl<S>(v); }
+};
+
+// ---------------------------------------------------------------------------
+// one Stockham stage of a workgroup-wide batched transform
+// ---------------------------------------------------------------------------
+template <typename T, int P, int NT, int NL, int LP, int SIGN, int S>
+struct Stage {
+  using C = cplx<T>;
+  static constexpr int R = radix_at<SIGN>(P, S);
+  static constexpr int NS = ns_at<SIGN>(P, S);
+  static constexpr int NB = P / R;  // butterflies per line
+  static constexpr int NQ = NT / NL;
+  static constexpr int NTASK = (NB + NQ - 1) / NQ;
+  static constexpr bool EXACT = (NB % NQ) == 0;
+  static constexpr bool LAST = (S == n_stages(P) - 1);
+  static_assert(NT % NL == 0, "threads must cover whole lines");
+
+  struct Regs { C v[NTASK][R]; };
+
+  __device__ __forceinline__ static bool active(int t, int q) { return EXACT || (q + t * NQ) < NB; }
+  __device__ __forceinline__ static int in_pos(int j, int r) { return j + r * NB; }
+  __device__ __forceinline__ static int out_pos(int j, int r) { return (j / NS) * NS * R + (j % NS) + r * NS; }
+
+  __device__ __forceinline__ static C twiddle(const C* tw, int e) {
+    C w = tw[e];
+    if constexpr (SIGN > 0) w.y = -w.y;
+    return w;
+  }
+
+  // first stage (Ns = 1, no twiddles); ld(pos) returns the input at pos.
+  // PRUNE: inputs at positions >= P/2 are zero and are not read.
+  template <bool PRUNE, class Load>
+  __device__ __forceinline__ static void load_first(Regs& g, int q, Load&& ld) {
+    static_assert(S == 0, "load_first is the first stage");
+    static_assert(!PRUNE || R % 2 == 0, "pruned inputs need an even first radix");
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      const int j = q + t * NQ;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (PRUNE && r >= R / 2) g.v[t][r] = C{T(0), T(0)};
+        else g.v[t][r] = ld(in_pos(j, r));
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void butterflies(Regs& g, int q) {
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t)
+      if (active(t, q)) Dft<R, SIGN, C>::run(g.v[t]);
+  }
+
+  // read this stage's inputs from the LDS tile and apply the twiddles
+  __device__ __forceinline__ static void lds_in(Regs& g, const C* lds, const C* tw, int l, int q) {
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      const int j = q + t * NQ;
+#pragma unroll
+      for (int r = 0; r < R; ++r) g.v[t][r] = lds[in_pos(j, r) * LP + l];
+      if constexpr (NS > 1) {
+        const int base = (j % NS) * (P / (NS * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) g.v[t][r] = c_mul(g.v[t][r], twiddle(tw, r * base));
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void lds_out(const Regs& g, C* lds, int l, int q) {
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      const int j = q + t * NQ;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[out_pos(j, r) * LP + l] = g.v[t][r];
+    }
+  }
+
+  // last stage outputs (Ns = P/R, so positions are j + r*NB); st(pos, value).
+  // PRUNE: only positions < P/2 are stored.
+  template <bool PRUNE, class Store>
+  __device__ __forceinline__ static void store_last(const Regs& g, int q, Store&& st) {
+    static_assert(LAST, "store_last is the last stage");
+    static_assert(!PRUNE || R % 2 == 0, "pruned outputs need an even last radix");
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      const int j = q + t * NQ;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (PRUNE && r >= R / 2) continue;
+        st(out_pos(j, r), g.v[t][r]);
+      }
+    }
+  }
+};
+
+template <int B, int E> struct StaticFor {
+  template <class F> __device__ __forceinline__ static void run(F&& f) {
+    if constexpr (B < E) {
+      f(std::integral_constant<int, B>{});
+      StaticFor<B + 1, E>::run(f);
+    }
+  }
+};
+
+// Runs stages [1, n_stages - 1) of a transform through the LDS tile. On entry
+// stage 0's outputs are in LDS (and a barrier has been passed); on exit the
+// last stage's twiddled-and-transformed results are in `last`.
+template <typename T, int P, int NT, int NL, int LP, int SIGN>
+__device__ __forceinline__ void middle_and_last(
+    typename Stage<T, P, NT, NL, LP, SIGN, n_stages(P) - 1>::Regs& last, cplx<T>* lds,
+    const cplx<T>* tw, int l, int q) {
+  constexpr int NSTG = n_stages(P);
+  StaticFor<1, NSTG - 1>::run([&](auto sI) {
+    constexpr int s = decltype(sI)::value;
+    using St = Stage<T, P, NT, NL, LP, SIGN, s>;
+    typename St::Regs g;
+    St::lds_in(g, lds, tw, l, q);
+    St::butterflies(g, q);
+    __syncthreads();
+    St::lds_out(g, lds, l, q);
+    __syncthreads();
+  });
+  using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1>;
+  SL::lds_in(last, lds, tw, l, q);
+  SL::butterflies(last, q);
+}
+
+}  // namespace vgf

@@ -1,0 +1,78 @@
+// vgf_internal.hpp -- declarations shared by the host runtime and the kernel
+// translation units of libvgf (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vgf {
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename T> using cplx = typename cplx_of<T>::type;
+
+// FFT lengths (2N) the library instantiates.
+inline bool supported_fft_len(int64_t P) {
+  switch (P) {
+    case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192:
+    case 256: case 384: case 512: case 768: case 1024:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// Strided line transform geometry: element pos of column col, batch b,
+// field f is at base + f*fs + b*bs + pos*ls + col.
+struct StridedArgs {
+  int64_t ncols;
+  int64_t ls_in, ls_out;
+  int64_t bs_in, bs_out;
+  int64_t fs_in, fs_out;
+  int nbatch, nfields;
+};
+
+// Geometry of the axis-0 (outermost) fused pass.
+template <typename T> struct FusedGeom {
+  int64_t ncols;     // columns of the inner plane: P1*H2 (3D) or H1 (2D)
+  int64_t out_fs;    // field stride of the output (forward)
+  int64_t in_fs;     // field stride of the input (adjoint)
+  int dim;
+  int n0, n1, n2;    // points per axis (n2 unused in 2D)
+  int h_last;        // N_last + 1
+  T ks0, ks1, ks2;   // 2 pi / (P_a h_a)
+  int nf;            // number of fields
+  int fields[4];     // 0: phi, 1 + a: E_a
+};
+
+template <typename T>
+hipError_t launch_r2c(int P, const T* in, cplx<T>* out, int64_t nlines, const cplx<T>* tw,
+                      hipStream_t s);
+template <typename T>
+hipError_t launch_c2r(int P, const cplx<T>* in, T* out, int64_t nlines, int nf, int64_t in_fs,
+                      int64_t out_fs, const cplx<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_c2c(int P, int sign, const cplx<T>* in, cplx<T>* out, const StridedArgs& sa,
+                      const cplx<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_fused(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,
+                        const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
+
+// ---- plan-time precompute (FP64) ----
+// F{G^L}(|k_m|) on m in [0, ext_0) x [0, ext_1) (x [0, ext_2)),
+// k_{m,a} = m_a * dk_a.
+hipError_t launch_ghat(double* out, int dim, const int64_t* ext, const double* dk, double L,
+                       hipStream_t s);
+// HE kernel octant: vol * G(|n h|), origin vol * G0.
+hipError_t launch_he_kernel(double* out, int dim, const int64_t* n, const double* h,
+                            hipStream_t s);
+// out[o][j][i] = sum_{m < M} mat[m*J + j] * in[(o*M + m)*inner + i]
+hipError_t launch_axis_apply(const double* in, double* out, const double* mat, int64_t outer,
+                             int M, int J, int64_t inner, hipStream_t s);
+// out[i] = (T)(in[i] * scale)
+template <typename T>
+hipError_t launch_scale_convert(const double* in, T* out, int64_t count, double scale,
+                                hipStream_t s);
+
+}  // namespace vgf

@@ -1,0 +1,264 @@
+"""Thin ctypes binding of libvgf.so (include/vgf.h).
+
+Only argument marshalling lives here: every step of the solve runs in the HIP
+kernels of libvgf.so. torch provides device memory (tensors are passed by
+data_ptr) and the current HIP stream. There is no CPU fallback: if the
+library is missing or no GPU is present, the calls raise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvgf.so")
+
+OK = 0
+STATUS = {0: "VGF_OK", -1: "VGF_ERR_INVALID_ARG", -2: "VGF_ERR_UNSUPPORTED_SIZE",
+          -3: "VGF_ERR_L_WINDOW", -4: "VGF_ERR_OUT_OF_MEMORY", -5: "VGF_ERR_HIP",
+          -6: "VGF_ERR_NOT_REQUESTED"}
+METHODS = {"vgf": 0, "he": 1}
+PRECISIONS = {"f64": 0, "f32": 1}
+OUT_PHI, OUT_E = 1, 2
+EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batched",
+           "vgf_plan_get_L", "vgf_plan_workspace_bytes", "vgf_plan_get_kernel",
+           "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
+           "vgf_status_string"]
+
+
+class VGFError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (%s)" % (what, STATUS.get(status, status),
+                                          lib().vgf_status_string(status).decode()))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libvgf.so not built (run paper_2103_08531_amd/build.py): %s" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp, i64p, dp = C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)
+        L.vgf_plan_create.restype = C.c_int
+        L.vgf_plan_create.argtypes = [C.POINTER(vp), C.c_int, i64p, dp, C.c_int, C.c_int,
+                                      C.c_double, C.c_uint, vp]
+        L.vgf_solve.restype = C.c_int
+        L.vgf_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.vgf_solve_adjoint.restype = C.c_int
+        L.vgf_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]
+        L.vgf_solve_batched.restype = C.c_int
+        L.vgf_solve_batched.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp), C.POINTER(vp),
+                                        C.POINTER(vp), vp]
+        L.vgf_plan_get_L.restype = C.c_int
+        L.vgf_plan_get_L.argtypes = [vp, dp]
+        L.vgf_plan_workspace_bytes.restype = C.c_int
+        L.vgf_plan_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.vgf_plan_get_kernel.restype = C.c_int
+        L.vgf_plan_get_kernel.argtypes = [vp, dp]
+        L.vgf_plan_get_spectrum.restype = C.c_int
+        L.vgf_plan_get_spectrum.argtypes = [vp, dp]
+        L.vgf_plan_hip_error.restype = C.c_int
+        L.vgf_plan_hip_error.argtypes = [vp]
+        L.vgf_plan_destroy.restype = None
+        L.vgf_plan_destroy.argtypes = [vp]
+        L.vgf_status_string.restype = C.c_char_p
+        L.vgf_status_string.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != OK:
+        raise VGFError(st, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A solver plan for one grid (Sec. II: precompute once, then solve per rho).
+
+    n: points per axis (2 or 3 values); h: spacings; method 'vgf' or 'he';
+    precision 'f64' or 'f32'; L: VGF truncation radius (None: 1.1 x diameter);
+    outputs: subset of {'phi', 'E'}.
+    """
+
+    def __init__(self, n, h, method="vgf", precision="f64", L=None, outputs=("phi", "E"),
+                 stream=None):
+        torch = _torch()
+        self.n = tuple(int(x) for x in n)
+        self.h = tuple(float(x) for x in h)
+        self.dim = len(self.n)
+        self.method = method
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.outputs = tuple(outputs)
+        flags = (OUT_PHI if "phi" in outputs else 0) | (OUT_E if "E" in outputs else 0)
+        n_arr = (C.c_int64 * self.dim)(*self.n)
+        h_arr = (C.c_double * self.dim)(*self.h)
+        handle = C.c_void_p()
+        self._h = None
+        st = lib().vgf_plan_create(C.byref(handle), self.dim, n_arr, h_arr,
+                                   METHODS[method], PRECISIONS[precision],
+                                   0.0 if L is None else float(L), flags, _stream(stream))
+        _check(st, "vgf_plan_create")
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    @property
+    def L(self):
+        v = C.c_double()
+        _check(lib().vgf_plan_get_L(self.handle, C.byref(v)), "vgf_plan_get_L")
+        return v.value
+
+    @property
+    def workspace_bytes(self):
+        v = C.c_size_t()
+        _check(lib().vgf_plan_workspace_bytes(self.handle, C.byref(v)), "vgf_plan_workspace_bytes")
+        return v.value
+
+    def kernel(self):
+        out = np.zeros(self.n, dtype=np.float64)
+        _check(lib().vgf_plan_get_kernel(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "vgf_plan_get_kernel")
+        return out
+
+    def spectrum(self):
+        out = np.zeros(tuple(x + 1 for x in self.n), dtype=np.float64)
+        _check(lib().vgf_plan_get_spectrum(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "vgf_plan_get_spectrum")
+        return out
+
+    def _check_tensor(self, t, shape, name):
+        if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError("%s must be a contiguous %s CUDA tensor of shape %s (got %s %s %s)"
+                             % (name, self.dtype, shape, t.dtype, tuple(t.shape), t.device))
+
+    def solve(self, rho, phi=None, E=None, want_phi=True, want_E=True, stream=None):
+        """Returns (phi, E); fields not wanted come back as None."""
+        torch = _torch()
+        self._check_tensor(rho, self.n, "rho")
+        want_phi = want_phi and "phi" in self.outputs
+        want_E = want_E and "E" in self.outputs
+        if want_phi and phi is None:
+            phi = torch.empty(self.n, dtype=self.dtype, device=rho.device)
+        if want_E and E is None:
+            E = torch.empty((self.dim,) + self.n, dtype=self.dtype, device=rho.device)
+        if not want_phi:
+            phi = None
+        if not want_E:
+            E = None
+        if phi is not None:
+            self._check_tensor(phi, self.n, "phi")
+        if E is not None:
+            self._check_tensor(E, (self.dim,) + self.n, "E")
+        st = lib().vgf_solve(self.handle, _ptr(rho), _ptr(phi), _ptr(E), _stream(stream))
+        _check(st, "vgf_solve")
+        return phi, E
+
+    def adjoint(self, g_phi=None, g_E=None, g_rho=None, stream=None):
+        torch = _torch()
+        ref = g_phi if g_phi is not None else g_E
+        if ref is None:
+            raise ValueError("adjoint needs g_phi or g_E")
+        if g_phi is not None:
+            self._check_tensor(g_phi, self.n, "g_phi")
+        if g_E is not None:
+            self._check_tensor(g_E, (self.dim,) + self.n, "g_E")
+        if g_rho is None:
+            g_rho = torch.empty(self.n, dtype=self.dtype, device=ref.device)
+        self._check_tensor(g_rho, self.n, "g_rho")
+        st = lib().vgf_solve_adjoint(self.handle, _ptr(g_phi), _ptr(g_E), _ptr(g_rho),
+                                     _stream(stream))
+        _check(st, "vgf_solve_adjoint")
+        return g_rho
+
+    def close(self):
+        if self._h is not None:
+            lib().vgf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def solve_batched(plans, rhos, phis=None, Es=None, stream=None):
+    """One vgf_solve_batched call over parallel lists (phis / Es entries may be None)."""
+    count = len(plans)
+    VP = C.c_void_p
+    pl = (VP * count)(*[p.handle.value for p in plans])
+    rh = (VP * count)(*[r.data_ptr() for r in rhos])
+    ph = (VP * count)(*[(x.data_ptr() if x is not None else None) for x in phis]) if phis is not None else None
+    ee = (VP * count)(*[(x.data_ptr() if x is not None else None) for x in Es]) if Es is not None else None
+    st = lib().vgf_solve_batched(pl, count, rh, ph, ee, _stream(stream))
+    _check(st, "vgf_solve_batched")
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class VGFSolve(torch.autograd.Function):
+        """(phi, E) = solve(rho); backward applies the hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, rho, plan):
+            ctx.plan = plan
+            phi, E = plan.solve(rho.contiguous())
+            return phi, E
+
+        @staticmethod
+        def backward(ctx, g_phi, g_E):
+            plan = ctx.plan
+            gp = g_phi.contiguous() if (g_phi is not None and "phi" in plan.outputs) else None
+            ge = g_E.contiguous() if (g_E is not None and "E" in plan.outputs) else None
+            if gp is None and ge is None:
+                return None, None
+            return plan.adjoint(gp, ge), None
+
+    return VGFSolve
+
+
+_VGFSolve = None
+
+
+def VGFSolve():
+    global _VGFSolve
+    if _VGFSolve is None:
+        _VGFSolve = _autograd_function()
+    return _VGFSolve
+
+
+def solve(rho, plan):
+    """Differentiable solve: returns (phi, E) with autograd through the adjoint."""
+    return VGFSolve().apply(rho, plan)

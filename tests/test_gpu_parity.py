@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs. FP64 must agree to rel-L2 <= 1e-12 per field, FP32 to
+<= 1e-5 (the FP32 run gets the FP32-rounded rho, and the oracle the same
+values widened to FP64)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_common import (FP32_TOL, FP64_TOL, check_fields, gpu_solve, need_gpu, oracle_kernel,
+                        oracle_solve, rel_l2, rounded_input, say)
+from paper_2103_08531_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def make_plan(n, h, method="vgf", precision="f64", outputs=("phi", "E"), L=None):
+    torch, vgf = need_gpu()
+    return vgf.Plan(n, h, method=method, precision=precision, outputs=outputs, L=L)
+
+
+KERNEL_CASES = [((8, 8, 8), "vgf"), ((12, 12, 12), "he"), ((32, 32, 32), "vgf"), ((32, 32, 32), "he"),
+                ((16, 24, 32), "vgf"), ((16, 16), "vgf"), ((64, 48), "he"), ((512, 512), "vgf")]
+
+
+@pytest.mark.parametrize("n,method", KERNEL_CASES)
+def test_precompute_kernel_and_spectrum(n, method):
+    h = tuple(2.0 / (x - 1) for x in n)
+    say("precompute", n, method)
+    plan = make_plan(n, h, method)
+    L = plan.L
+    w_o = oracle_kernel(method, n, h, L)
+    w_g = plan.kernel()
+    err = np.max(np.abs(w_g - w_o)) / np.max(np.abs(w_o))
+    say("  kernel max rel %.3e" % err)
+    assert err <= FP64_TOL
+    s_o, _ = orc.kernel_spectrum(n, w_o)
+    s_g = plan.spectrum()
+    err = np.max(np.abs(s_g - s_o)) / np.max(np.abs(s_o))
+    say("  spectrum max rel %.3e" % err)
+    assert err <= FP64_TOL
+    plan.close()
+
+
+DIRECT_CASES = [((8, 8, 8), "vgf"), ((12, 12, 12), "he"), ((8, 12, 16), "vgf"), ((16, 16), "vgf"),
+                ((24, 16), "he"), ((48, 32), "vgf")]
+
+
+@pytest.mark.parametrize("n,method", DIRECT_CASES)
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_small_grids_against_direct_sums(n, method, precision):
+    """Random rho (no structure to hide behind) against the plain convolution
+    sums and the cot-stencil field, computed without any FFT."""
+    h = tuple(0.1 + 0.03 * a for a in range(len(n)))
+    say("direct", n, method, precision)
+    plan = make_plan(n, h, method, precision)
+    rho = rounded_input(W.random_field(42, n), precision)
+    phi_g, E_g = gpu_solve(plan, rho)
+    w = oracle_kernel(method, n, h, plan.L)
+    phi_o = orc.conv_direct(n, w, rho)
+    Wp = orc.periodic_kernel(n, w)
+    E_o = np.stack([orc.conv_periodic(n, orc.field_kernel(n, h, Wp, a), rho) for a in range(len(n))])
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "direct %s %s %s" % (n, method, precision))
+    plan.close()
+
+
+@pytest.mark.parametrize("method", ["vgf", "he"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gaussian_3d_32(method, precision):
+    """3D N=32 on [-1,1]^3, unit Gaussian sigma=0.1 at the origin."""
+    ch = W.gaussian_3d_32()
+    say("gaussian_3d_32", method, precision)
+    plan = make_plan(ch.n, ch.h, method, precision)
+    rho = rounded_input(ch.rho(), precision)
+    phi_g, E_g = gpu_solve(plan, rho)
+    phi_o, E_o = oracle_solve(method, ch.n, ch.h, plan.L, rho)
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "cfg1 %s %s" % (method, precision))
+    pa, Ea = orc.gauss_mixture_grid(ch.n, ch.x0, ch.h, ch.centers, ch.sigmas, ch.weights)
+    ea = rel_l2(phi_g, pa)
+    say("  vs analytic phi %.3e E %.3e" % (ea, rel_l2(E_g, Ea)))
+    if method == "vgf":
+        assert ea < 1e-8
+    else:
+        assert 5e-3 < ea < 5e-2
+    plan.close()
+
+
+@pytest.mark.parametrize("method", ["vgf", "he"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_mixture_2d_512(method, precision):
+    """2D N=512 on [-1,1]^2, 8 seeded Gaussians, phi and E."""
+    ch = W.mixture_2d_512(seed=0)
+    say("mixture_2d_512", method, precision)
+    plan = make_plan(ch.n, ch.h, method, precision)
+    rho = rounded_input(ch.rho(), precision)
+    phi_g, E_g = gpu_solve(plan, rho)
+    phi_o, E_o = oracle_solve(method, ch.n, ch.h, plan.L, rho)
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "cfg2 %s %s" % (method, precision))
+    plan.close()
+
+
+SIZE_CASES = [(2, 96), (2, 192), (2, 384), (3, 24), (3, 48), (3, 64)]
+
+
+@pytest.mark.parametrize("dim,N", SIZE_CASES)
+def test_fft_lengths(dim, N):
+    """Every radix mix (8/4/2/3) of the supported lengths, ragged column tiles."""
+    n = (N,) * dim
+    h = (2.0 / (N - 1),) * dim
+    rng = np.random.default_rng(N)
+    c = rng.uniform(-0.4, 0.4, (3, dim))
+    s = np.repeat(rng.uniform(0.08, 0.2, 3)[:, None], dim, axis=1)
+    rho = W.gaussian_density(n, (-1.0,) * dim, h, c, s, np.array([1.0, -0.5, 0.7]))
+    say("lengths", dim, N)
+    for precision, tol in (("f64", FP64_TOL), ("f32", FP32_TOL)):
+        plan = make_plan(n, h, "vgf", precision)
+        r = rounded_input(rho, precision)
+        phi_g, E_g = gpu_solve(plan, r)
+        phi_o, E_o = oracle_solve("vgf", n, h, plan.L, r)
+        check_fields(phi_g, E_g, phi_o, E_o, tol, "len %dD %d %s" % (dim, N, precision))
+        plan.close()
+
+
+def test_rectangular_grid():
+    n = (16, 24, 32)
+    lo = (-0.9, -1.0, -1.1)
+    h = tuple(-2 * l / (m - 1) for l, m in zip(lo, n))
+    c = np.array([[0.03, -0.02, 0.05]])
+    s = np.full((1, 3), 0.12)
+    rho = W.gaussian_density(n, lo, h, c, s, np.ones(1))
+    for precision, tol in (("f64", FP64_TOL), ("f32", FP32_TOL)):
+        plan = make_plan(n, h, "vgf", precision)
+        r = rounded_input(rho, precision)
+        phi_g, E_g = gpu_solve(plan, r)
+        phi_o, E_o = oracle_solve("vgf", n, h, plan.L, r)
+        check_fields(phi_g, E_g, phi_o, E_o, tol, "rect %s" % precision)
+        plan.close()
+
+
+@pytest.mark.parametrize("outputs", [("phi",), ("E",)])
+def test_output_subsets(outputs):
+    torch, vgf = need_gpu()
+    ch = W.gaussian_3d_32()
+    plan = make_plan(ch.n, ch.h, "vgf", "f64", outputs=outputs)
+    rho = ch.rho()
+    phi_g, E_g = gpu_solve(plan, rho)
+    phi_o, E_o = oracle_solve("vgf", ch.n, ch.h, plan.L, rho)
+    if outputs == ("phi",):
+        assert E_g is None
+        check_fields(phi_g, None, phi_o, None, FP64_TOL, "phi-only")
+        with pytest.raises(vgf.VGFError) as ei:
+            r = torch.from_numpy(rho).cuda()
+            E = torch.empty((3,) + ch.n, dtype=torch.float64, device="cuda")
+            vgf.lib()  # the C call itself must refuse the E output
+            import ctypes as C
+            st = vgf.lib().vgf_solve(plan.handle, C.c_void_p(r.data_ptr()), None,
+                                     C.c_void_p(E.data_ptr()), None)
+            vgf._check(st, "vgf_solve")
+        assert ei.value.status == -6
+    else:
+        assert phi_g is None
+        check_fields(None, E_g, None, E_o, FP64_TOL, "E-only")
+    plan.close()
+
+
+def test_repeat_solves_are_bitwise_identical():
+    torch, vgf = need_gpu()
+    ch = W.mixture_2d_512(seed=1)
+    plan = make_plan(ch.n, ch.h, "vgf", "f32")
+    a = gpu_solve(plan, ch.rho())
+    b = gpu_solve(plan, ch.rho())
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [(16, 16, 16), (8, 12, 16), (32, 24)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint(n, precision):
+    """<K x, y> + sum_a <K_a x, z_a> = <x, K^T y + sum_a K_a^T z_a>, and the
+    GPU adjoint against the oracle's adjoint."""
+    torch, vgf = need_gpu()
+    dim = len(n)
+    h = tuple(0.11 + 0.02 * a for a in range(dim))
+    plan = make_plan(n, h, "vgf", precision)
+    x = rounded_input(W.random_field(1, n), precision)
+    y = rounded_input(W.random_field(2, n), precision)
+    z = rounded_input(W.random_field(3, (dim,) + n), precision)
+    phi_g, E_g = gpu_solve(plan, x)
+    dt = plan.dtype
+    g = plan.adjoint(torch.from_numpy(y).to("cuda", dt), torch.from_numpy(z).to("cuda", dt))
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    lhs = np.vdot(phi_g, y) + np.vdot(E_g, z)
+    rhs = np.vdot(x, g)
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    say("adjoint %s %s dot lhs %.16e rhs %.16e" % (n, precision, lhs, rhs))
+    assert abs(lhs - rhs) <= tol * (np.linalg.norm(phi_g) * np.linalg.norm(y) + np.linalg.norm(E_g) * np.linalg.norm(z))
+    w = orc.vgf_kernel(n, h, plan.L)
+    g_o = orc.adjoint_fft2n(n, h, w, y, z)
+    e = rel_l2(g, g_o)
+    say("  vs oracle adjoint %.3e" % e)
+    assert e <= tol
+    # phi-only and E-only adjoints
+    g1 = plan.adjoint(torch.from_numpy(y).to("cuda", dt), None).double().cpu().numpy()
+    assert rel_l2(g1, orc.adjoint_fft2n(n, h, w, y, None)) <= tol
+    g2 = plan.adjoint(None, torch.from_numpy(z).to("cuda", dt)).double().cpu().numpy()
+    assert rel_l2(g2, orc.adjoint_fft2n(n, h, w, None, z)) <= tol
+    plan.close()
+
+
+def test_batched_matches_single():
+    torch, vgf = need_gpu()
+    charges = W.batch_3d_mixed(seed=0, count=6, sizes=(32, 48, 64))
+    plans = {}
+    for ch in charges:
+        if ch.n not in plans:
+            plans[ch.n] = make_plan(ch.n, ch.h, "vgf", "f32")
+    rhos = [torch.from_numpy(ch.rho()).to("cuda", torch.float32) for ch in charges]
+    pl = [plans[ch.n] for ch in charges]
+    phis = [torch.empty(ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    Es = [torch.empty((3,) + ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    vgf.solve_batched(pl, rhos, phis, Es)
+    torch.cuda.synchronize()
+    for ch, r, p, E, plan in zip(charges, rhos, phis, Es, pl):
+        p1, E1 = plan.solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(p, p1) and torch.equal(E, E1)
+        phi_o, E_o = oracle_solve("vgf", ch.n, ch.h, plan.L, rounded_input(ch.rho(), "f32"))
+        check_fields(p.double().cpu().numpy(), E.double().cpu().numpy(), phi_o, E_o, FP32_TOL,
+                     "batched %s" % (ch.n,))
+    for p in plans.values():
+        p.close()
