@@ -1,0 +1,200 @@
+"""Benchmark: 3D VGF solves/s at N=256^3, FP32 and FP64, with the HBM roofline.
+
+Workload (synthetic, seeded): beam_3d_256 -- 3D grid of 256^3 points on
+[-1,1]^3, one unit anisotropic Gaussian sigma = (0.05, 0.05, 0.3) whose
+centroid is drawn uniformly in the ball of radius 0.05 (seed 0). One step is
+one VGF solve on a fixed plan: pruned R2C along axis 2, C2C along axis 1, the
+fused axis-0 pass (forward FFT, spectral multiply by the kernel spectrum and
+by -i k_a times it, four inverse FFTs), inverse C2C along axis 1 and C2R
+along axis 2, producing phi and E (the one-time FP64 kernel precompute runs
+at plan creation and is not part of a step). rho is resident in HBM before
+the timed region.
+
+Printed JSON line (one, rank 0):
+  value        FP32 solves/s (whole job, one GPU)
+  fp64         the same for FP64 solves
+  roofline     for the dominant kernel (the fused axis-0 pass): algorithmic
+               bytes per launch (read the axis-1 spectrum, read the kernel
+               spectrum octant, write one complex array per field) divided by
+               its mean duration measured with HIP events recorded by the
+               library on the solve stream during the timed region, against
+               the MI355X's 8 TB/s HBM peak
+  pass_model   the whole solve against the same peak, using one HBM read and
+               write per axis pass of the pruned arrays
+  cpu_baseline the FP64 CPU oracle's 2N FFT path on the same input, timed on
+               the host cores for one solve (its values also give the stated
+               rel-L2 of the GPU results)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "3D VGF solves/s at N=256^3 FP32 vs FP64 + HBM GB/s, at stated rel-L2 error"
+
+
+def pass_bytes(n, prec_bytes, nf):
+    """Algorithmic HBM bytes per solve of each pass (one read + one write of
+    the pruned arrays; the kernel spectrum octant is read once)."""
+    N0, N1, N2 = n
+    P1, H = 2 * N1, N2 + 1
+    rb, cb = prec_bytes, 2 * prec_bytes
+    x1 = N0 * N1 * H * cb
+    x2 = N0 * P1 * H * cb
+    spec = (N0 + 1) * (N1 + 1) * (N2 + 1) * rb
+    real = N0 * N1 * N2 * rb
+    return {
+        "r2c": real + x1,
+        "c2c_fwd": x1 + x2,
+        "fused_axis0": x2 + spec + nf * x2,
+        "c2c_inv": nf * (x2 + x1),
+        "c2r": nf * (x1 + real),
+    }
+
+
+def run_precision(vgf, torch, ch, rho64, precision, steps, warmup):
+    dt = torch.float32 if precision == "f32" else torch.float64
+    plan = vgf.Plan(ch.n, ch.h, method="vgf", precision=precision)
+    rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
+    phi = torch.empty(ch.n, dtype=dt, device="cuda")
+    E = torch.empty((3,) + ch.n, dtype=dt, device="cuda")
+    for _ in range(warmup):
+        plan.solve(rho, phi, E)
+    torch.cuda.synchronize()
+    plan.profile_begin(steps)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.solve(rho, phi, E)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    passes, nsolves = plan.profile_end()
+    wall_ms = (t1 - t0) * 1e3 / steps
+    ev_ms = ev0.elapsed_time(ev1) / steps
+    out = {"phi": phi.double().cpu().numpy(), "E": E.double().cpu().numpy()}
+    L = plan.L
+    plan.close()
+    del rho, phi, E
+    torch.cuda.empty_cache()
+    return {"wall_ms": wall_ms, "event_ms": ev_ms, "passes": passes, "nsolves": nsolves,
+            "out": out, "L": L}
+
+
+def rel_l2(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
+
+
+def cpu_baseline(ch, rho64, L, results):
+    """FP64 oracle, 2N FFT path, one full solve (phi + E) on the host cores."""
+    import oracle as orc
+    w = orc.vgf_kernel(ch.n, ch.h, L)  # plan-time precompute: not timed
+    t0 = time.perf_counter()
+    phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, w, rho64)
+    t = time.perf_counter() - t0
+    acc = {}
+    for prec, r in results.items():
+        acc[prec] = {"phi": rel_l2(r["out"]["phi"], phi_o),
+                     "E": rel_l2(r["out"]["E"], E_o)}
+    base = {"value": 1.0 / t, "unit": "solves/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": "one full 256^3 FP64 solve (phi + E) by the oracle's naive 2N FFT path, "
+                      "including its FFT of the kernel; kernel precompute excluded; %.1f s" % t}
+    return base, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the solve path runs on a single MI355X "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2103_08531_amd import vgf, workloads
+    torch.cuda.set_device(0)
+    ch = workloads.beam_3d_256(seed=args.seed)
+    rho64 = ch.rho()
+
+    results = {}
+    for prec in ("f32", "f64"):
+        results[prec] = run_precision(vgf, torch, ch, rho64, prec, args.steps, args.warmup)
+        print("[bench] %s: %.3f ms/solve (events %.3f), passes %s" % (
+            prec, results[prec]["wall_ms"], results[prec]["event_ms"],
+            {k: round(v, 4) for k, v in results[prec]["passes"].items()}), file=sys.stderr, flush=True)
+
+    nf = 4
+    line = {}
+    f32 = results["f32"]
+    f64 = results["f64"]
+    pb32 = pass_bytes(ch.n, 4, nf)
+    pb64 = pass_bytes(ch.n, 8, nf)
+    dom = "fused_axis0"
+    dom_ms = f32["passes"][dom]
+    achieved = pb32[dom] / (dom_ms * 1e-3) / 1e9
+    total32 = sum(pb32.values())
+    total64 = sum(pb64.values())
+
+    line = {
+        "metric": METRIC,
+        "value": 1e3 / f32["wall_ms"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["wall_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "beam_3d_256", "grid": list(ch.n), "domain": "[-1,1]^3",
+                   "method": "vgf", "outputs": "phi+E", "sigma": [0.05, 0.05, 0.3],
+                   "seed": args.seed, "L": f32["L"], "parallelism": "single GPU"},
+        "fp64": {"value": 1e3 / f64["wall_ms"], "unit": "solves/s", "ms_per_step": f64["wall_ms"],
+                 "dtype": "f64"},
+        "roofline": {"bound": "hbm", "kernel": "k_fused (axis-0 forward, multiply, 4 inverse)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": pb32[dom], "mean_launch_ms": dom_ms,
+                     "fp64": {"achieved": pb64[dom] / (f64["passes"][dom] * 1e-3) / 1e9,
+                              "mean_launch_ms": f64["passes"][dom],
+                              "frac": pb64[dom] / (f64["passes"][dom] * 1e-3) / 1e9 / HBM_PEAK_GBS}},
+        "pass_model": {"bytes_per_solve_f32": total32, "bytes_per_solve_f64": total64,
+                       "frac_f32": total32 / (f32["wall_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "frac_f64": total64 / (f64["wall_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "pass_ms_f32": f32["passes"], "pass_ms_f64": f64["passes"],
+                       "pass_gbs_f32": {k: pb32[k] / (f32["passes"][k] * 1e-3) / 1e9 for k in pb32},
+                       "pass_gbs_f64": {k: pb64[k] / (f64["passes"][k] * 1e-3) / 1e9 for k in pb64}},
+        "accuracy": {"f32_vs_f64_gpu": {"phi": rel_l2(f32["out"]["phi"], f64["out"]["phi"]),
+                                        "E": rel_l2(f32["out"]["E"], f64["out"]["E"])}},
+    }
+    if not args.no_cpu_baseline:
+        base, acc = cpu_baseline(ch, rho64, f64["L"], results)
+        line["cpu_baseline"] = base
+        line["accuracy"]["vs_oracle"] = acc
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,6 +127,20 @@ vgf_status vgf_plan_get_kernel(vgf_plan plan, double* host_out);
  * Synchronous. */
 vgf_status vgf_plan_get_spectrum(vgf_plan plan, double* host_out);
 
+/* Per-pass timing (tracing support for benchmarks and profiling).
+ * vgf_plan_profile_begin creates max_solves * 6 HIP events (host call, not
+ * stream-ordered); each following vgf_solve on this plan, up to max_solves,
+ * records one event before its first pass and one after each pass, on the
+ * solve's own stream. vgf_plan_profile_end waits for the recorded events,
+ * writes the mean duration in milliseconds of each pass to pass_ms (3D: r2c,
+ * c2c forward, fused axis-0, c2c inverse, c2r; 2D: r2c, fused axis-0, c2r),
+ * the number of passes to *npasses and the number of timed solves to
+ * *nsolves, destroys the events and stops recording. pass_ms must hold 8
+ * doubles. begin while already recording returns INVALID_ARG; end without
+ * begin returns INVALID_ARG. */
+vgf_status vgf_plan_profile_begin(vgf_plan plan, int max_solves);
+vgf_status vgf_plan_profile_end(vgf_plan plan, double* pass_ms, int* npasses, int* nsolves);
+
 /* The last HIP error code recorded by a call on this plan (hipSuccess if
  * none). */
 int vgf_plan_hip_error(vgf_plan plan);

@@ -52,6 +52,11 @@ struct vgf_plan_s {
   size_t off_x1 = 0, off_x2 = 0, off_y = 0, off_z = 0;
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
+
+  // per-pass timing (vgf_plan_profile_begin / _end)
+  bool profiling = false;
+  int prof_cap = 0, prof_used = 0, prof_npass = 0;
+  std::vector<hipEvent_t> prof_events;  // prof_cap x kMaxMarks
 };
 
 namespace {
@@ -109,6 +114,7 @@ void release(vgf_plan p) {
   f(p->spec64);
   for (int a = 0; a < 3; ++a) f(p->tw[a]);
   f(p->ws);
+  for (hipEvent_t ev : p->prof_events) (void)hipEventDestroy(ev);
   delete p;
 }
 
@@ -227,6 +233,26 @@ vgf_status hip_status(vgf_plan p, hipError_t e) {
   return VGF_ERR_HIP;
 }
 
+constexpr int kMaxMarks = 6;
+
+// Records the pass boundaries of one solve when the plan is profiling.
+struct Marks {
+  vgf_plan p;
+  hipStream_t s;
+  hipEvent_t* ev = nullptr;
+  int n = 0;
+  Marks(vgf_plan p_, hipStream_t s_) : p(p_), s(s_) {
+    if (p->profiling && p->prof_used < p->prof_cap)
+      ev = &p->prof_events[(size_t)p->prof_used++ * kMaxMarks];
+  }
+  void mark() {
+    if (ev && n < kMaxMarks) (void)hipEventRecord(ev[n++], s);
+  }
+  ~Marks() {
+    if (ev) p->prof_npass = n - 1;
+  }
+};
+
 template <typename T> struct Bufs {
   cplx<T>* x1;
   cplx<T>* x2;
@@ -269,19 +295,25 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   if (E)
     for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
   hipError_t e;
+  Marks mk(p, s);
+  mk.mark();
   if (d == 3) {
     const int64_t P1 = p->P[1];
     g.out_fs = N0 * P1 * H;
     e = vgf::launch_r2c<T>((int)p->P[2], rho, b.x1, N0 * N1, tw(2), s);
     if (e != hipSuccess) return hip_status(p, e);
+    mk.mark();
     vgf::StridedArgs fa{H, H, H, N1 * H, P1 * H, 0, 0, (int)N0, 1};
     e = vgf::launch_c2c<T>((int)P1, -1, b.x1, b.x2, fa, tw(1), s);
     if (e != hipSuccess) return hip_status(p, e);
+    mk.mark();
     e = vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s);
     if (e != hipSuccess) return hip_status(p, e);
+    mk.mark();
     vgf::StridedArgs ia{H, H, H, P1 * H, N1 * H, N0 * P1 * H, N0 * N1 * H, (int)N0, g.nf};
     e = vgf::launch_c2c<T>((int)P1, 1, b.y, b.z, ia, tw(1), s);
     if (e != hipSuccess) return hip_status(p, e);
+    mk.mark();
     const int64_t zfs = N0 * N1 * H;
     int f0 = 0;
     if (phi) {
@@ -293,12 +325,15 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
       e = vgf::launch_c2r<T>((int)p->P[2], b.z + f0 * zfs, E, N0 * N1, d, zfs, vol, tw(2), s);
       if (e != hipSuccess) return hip_status(p, e);
     }
+    mk.mark();
   } else {
     g.out_fs = N0 * H;
     e = vgf::launch_r2c<T>((int)p->P[1], rho, b.x1, N0, tw(1), s);
     if (e != hipSuccess) return hip_status(p, e);
+    mk.mark();
     e = vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s);
     if (e != hipSuccess) return hip_status(p, e);
+    mk.mark();
     const int64_t yfs = N0 * H;
     int f0 = 0;
     if (phi) {
@@ -310,6 +345,7 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
       e = vgf::launch_c2r<T>((int)p->P[1], b.y + f0 * yfs, E, N0, d, yfs, vol, tw(1), s);
       if (e != hipSuccess) return hip_status(p, e);
     }
+    mk.mark();
   }
   return VGF_OK;
 }
@@ -563,6 +599,49 @@ vgf_status vgf_plan_get_spectrum(vgf_plan p, double* host_out) {
   size_t cnt = 1;
   for (int a = 0; a < p->dim; ++a) cnt *= (size_t)(p->n[a] + 1);
   return hip_status(p, hipMemcpy(host_out, p->spec64, cnt * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+vgf_status vgf_plan_profile_begin(vgf_plan p, int max_solves) {
+  if (!p || max_solves <= 0 || p->profiling) return VGF_ERR_INVALID_ARG;
+  p->prof_events.assign((size_t)max_solves * kMaxMarks, nullptr);
+  for (size_t i = 0; i < p->prof_events.size(); ++i) {
+    hipError_t e = hipEventCreate(&p->prof_events[i]);
+    if (e != hipSuccess) {
+      for (size_t k = 0; k < i; ++k) (void)hipEventDestroy(p->prof_events[k]);
+      p->prof_events.clear();
+      return hip_status(p, e);
+    }
+  }
+  p->prof_cap = max_solves;
+  p->prof_used = 0;
+  p->prof_npass = 0;
+  p->profiling = true;
+  return VGF_OK;
+}
+
+vgf_status vgf_plan_profile_end(vgf_plan p, double* pass_ms, int* npasses, int* nsolves) {
+  if (!p || !pass_ms || !npasses || !nsolves || !p->profiling) return VGF_ERR_INVALID_ARG;
+  hipError_t err = hipSuccess;
+  const int np = p->prof_npass;
+  for (int k = 0; k < 8; ++k) pass_ms[k] = 0.0;
+  for (int sIdx = 0; sIdx < p->prof_used && err == hipSuccess; ++sIdx) {
+    hipEvent_t* ev = &p->prof_events[(size_t)sIdx * kMaxMarks];
+    err = hipEventSynchronize(ev[np]);
+    for (int k = 0; k < np && err == hipSuccess; ++k) {
+      float ms = 0.f;
+      err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      pass_ms[k] += ms;
+    }
+  }
+  if (err == hipSuccess && p->prof_used > 0)
+    for (int k = 0; k < np; ++k) pass_ms[k] /= p->prof_used;
+  *npasses = np;
+  *nsolves = p->prof_used;
+  for (hipEvent_t ev : p->prof_events) (void)hipEventDestroy(ev);
+  p->prof_events.clear();
+  p->profiling = false;
+  p->prof_cap = p->prof_used = 0;
+  return hip_status(p, err);
 }
 
 int vgf_plan_hip_error(vgf_plan p) { return p ? (int)p->last_err : (int)hipErrorInvalidValue; }

@@ -23,7 +23,9 @@ OUT_PHI, OUT_E = 1, 2
 EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batched",
            "vgf_plan_get_L", "vgf_plan_workspace_bytes", "vgf_plan_get_kernel",
            "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
-           "vgf_status_string"]
+           "vgf_status_string", "vgf_plan_profile_begin", "vgf_plan_profile_end"]
+PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused_axis0", "c2c_inv", "c2r"],
+              2: ["r2c", "fused_axis0", "c2r"]}
 
 
 class VGFError(RuntimeError):
@@ -65,6 +67,10 @@ def lib():
         L.vgf_plan_hip_error.argtypes = [vp]
         L.vgf_plan_destroy.restype = None
         L.vgf_plan_destroy.argtypes = [vp]
+        L.vgf_plan_profile_begin.restype = C.c_int
+        L.vgf_plan_profile_begin.argtypes = [vp, C.c_int]
+        L.vgf_plan_profile_end.restype = C.c_int
+        L.vgf_plan_profile_end.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.vgf_status_string.restype = C.c_char_p
         L.vgf_status_string.argtypes = [C.c_int]
         _lib = L
@@ -194,6 +200,18 @@ class Plan:
                                      _stream(stream))
         _check(st, "vgf_solve_adjoint")
         return g_rho
+
+    def profile_begin(self, max_solves):
+        _check(lib().vgf_plan_profile_begin(self.handle, int(max_solves)), "vgf_plan_profile_begin")
+
+    def profile_end(self):
+        """{pass name: mean ms} over the solves recorded since profile_begin, and their count."""
+        ms = (C.c_double * 8)()
+        npass, nsol = C.c_int(), C.c_int()
+        _check(lib().vgf_plan_profile_end(self.handle, ms, C.byref(npass), C.byref(nsol)),
+               "vgf_plan_profile_end")
+        names = PASS_NAMES[self.dim]
+        return {names[k]: ms[k] for k in range(min(npass.value, len(names)))}, nsol.value
 
     def close(self):
         if self._h is not None:

@@ -50,7 +50,7 @@ DIRECT_CASES = [((8, 8, 8), "vgf"), ((12, 12, 12), "he"), ((8, 12, 16), "vgf"), 
 def test_small_grids_against_direct_sums(n, method, precision):
     """Random rho (no structure to hide behind) against the plain convolution
     sums and the cot-stencil field, computed without any FFT."""
-    h = tuple(0.1 + 0.03 * a for a in range(len(n)))
+    h = tuple((2.0 + 0.2 * a) / (x - 1) for a, x in enumerate(n))
     say("direct", n, method, precision)
     plan = make_plan(n, h, method, precision)
     rho = rounded_input(W.random_field(42, n), precision)
@@ -80,7 +80,8 @@ def test_gaussian_3d_32(method, precision):
     ea = rel_l2(phi_g, pa)
     say("  vs analytic phi %.3e E %.3e" % (ea, rel_l2(E_g, Ea)))
     if method == "vgf":
-        assert ea < 1e-8
+        # discretisation error 3e-9; FP32 rounding (~1e-7) dominates in FP32
+        assert ea < (1e-8 if precision == "f64" else 1e-6)
     else:
         assert 5e-3 < ea < 5e-2
     plan.close()
@@ -182,7 +183,7 @@ def test_adjoint(n, precision):
     GPU adjoint against the oracle's adjoint."""
     torch, vgf = need_gpu()
     dim = len(n)
-    h = tuple(0.11 + 0.02 * a for a in range(dim))
+    h = tuple((2.0 + 0.15 * a) / (x - 1) for a, x in enumerate(n))
     plan = make_plan(n, h, "vgf", precision)
     x = rounded_input(W.random_field(1, n), precision)
     y = rounded_input(W.random_field(2, n), precision)
