@@ -253,6 +253,11 @@ struct Marks {
   }
 };
 
+// 2 pi / (P_a h_a): wavenumber of one frequency step along axis a
+double wavenumber_step(vgf_plan p, int a) {
+  return (double)(2.0L * kPiL / ((long double)p->P[a] * (long double)p->h[a]));
+}
+
 template <typename T> struct Bufs {
   cplx<T>* x1;
   cplx<T>* x2;
@@ -275,12 +280,34 @@ template <typename T> vgf::FusedGeom<T> fused_geom(vgf_plan p) {
   g.n2 = d == 3 ? (int)p->n[2] : 0;
   g.h_last = (int)p->H;
   g.ncols = d == 3 ? p->P[1] * p->H : p->H;
-  g.ks0 = (T)(double)(2.0L * kPiL / ((long double)p->P[0] * (long double)p->h[0]));
-  g.ks1 = (T)(double)(2.0L * kPiL / ((long double)p->P[1] * (long double)p->h[1]));
-  g.ks2 = d == 3 ? (T)(double)(2.0L * kPiL / ((long double)p->P[2] * (long double)p->h[2])) : T(0);
+  g.ks0 = (T)wavenumber_step(p, 0);
   return g;
 }
 
+template <typename T> vgf::Deriv<T> deriv1(vgf_plan p, int axis, int code) {
+  vgf::Deriv<T> d{};
+  d.n = 1;
+  d.code[0] = code;
+  d.ks = (T)wavenumber_step(p, axis);
+  return d;
+}
+
+template <typename T> vgf::Deriv<T> deriv2(vgf_plan p, int axis, int code0, int code1) {
+  vgf::Deriv<T> d = deriv1<T>(p, axis, code0);
+  d.n = 2;
+  d.code[1] = code1;
+  return d;
+}
+
+#define VGF_RUN(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_status(p, e_);    \
+  } while (0)
+
+// Forward solve. Each pass applies the derivative factor of its own axis:
+// the axis-0 pass yields the spectra of phi (Yp) and E_0 (Y0); the last
+// two axes derive E_1 and E_2 from phi's spectrum as they invert.
 template <typename T>
 vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   const int d = p->dim;
@@ -291,120 +318,144 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
   vgf::FusedGeom<T> g = fused_geom<T>(p);
   g.nf = 0;
-  if (phi) g.fields[g.nf++] = 0;
-  if (E)
-    for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
-  hipError_t e;
+  g.fields[g.nf++] = 0;
+  if (E) g.fields[g.nf++] = 1;
   Marks mk(p, s);
   mk.mark();
   if (d == 3) {
     const int64_t P1 = p->P[1];
-    g.out_fs = N0 * P1 * H;
-    e = vgf::launch_r2c<T>((int)p->P[2], rho, b.x1, N0 * N1, tw(2), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    const int64_t yfs = N0 * P1 * H, zfs = N0 * N1 * H;
+    g.out_fs = yfs;
+    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0 * N1, deriv1<T>(p, 2, 0)};
+    VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
     mk.mark();
-    vgf::StridedArgs fa{H, H, H, N1 * H, P1 * H, 0, 0, (int)N0, 1};
-    e = vgf::launch_c2c<T>((int)P1, -1, b.x1, b.x2, fa, tw(1), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    const vgf::StridedGeom fg{H, H, H, N1 * H, P1 * H, (int)N0};
+    vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
     mk.mark();
-    e = vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s));
     mk.mark();
-    vgf::StridedArgs ia{H, H, H, P1 * H, N1 * H, N0 * P1 * H, N0 * N1 * H, (int)N0, g.nf};
-    e = vgf::launch_c2c<T>((int)P1, 1, b.y, b.z, ia, tw(1), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    // Yp -> Zp (phi, and E_2 later) and Z1 = -i k_1 Zp; Y0 -> Z0
+    const vgf::StridedGeom ig{H, H, H, P1 * H, N1 * H, (int)N0};
+    cplx<T>* zp = b.z;
+    cplx<T>* z1 = b.z + zfs;
+    cplx<T>* z0 = b.z + 2 * zfs;
+    vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia, tw(1), s));
+    if (E) {
+      vgf::C2CInvArgs<T> ia0{b.y + yfs, {z0, nullptr}, ig, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia0, tw(1), s));
+    }
     mk.mark();
-    const int64_t zfs = N0 * N1 * H;
-    int f0 = 0;
-    if (phi) {
-      e = vgf::launch_c2r<T>((int)p->P[2], b.z, phi, N0 * N1, 1, 0, 0, tw(2), s);
-      if (e != hipSuccess) return hip_status(p, e);
-      f0 = 1;
+    const int64_t lines = N0 * N1;
+    if (phi && E) {
+      vgf::C2RArgs<T> ca{zp, {phi, E + 2 * vol}, lines, deriv2<T>(p, 2, 0, -1)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
+    } else if (phi) {
+      vgf::C2RArgs<T> ca{zp, {phi, nullptr}, lines, deriv1<T>(p, 2, 0)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
+    } else {
+      vgf::C2RArgs<T> ca{zp, {E + 2 * vol, nullptr}, lines, deriv1<T>(p, 2, -1)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
     }
     if (E) {
-      e = vgf::launch_c2r<T>((int)p->P[2], b.z + f0 * zfs, E, N0 * N1, d, zfs, vol, tw(2), s);
-      if (e != hipSuccess) return hip_status(p, e);
+      vgf::C2RArgs<T> c1{z1, {E + vol, nullptr}, lines, deriv1<T>(p, 2, 0)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], c1, tw(2), s));
+      vgf::C2RArgs<T> c0{z0, {E, nullptr}, lines, deriv1<T>(p, 2, 0)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], c0, tw(2), s));
     }
     mk.mark();
   } else {
-    g.out_fs = N0 * H;
-    e = vgf::launch_r2c<T>((int)p->P[1], rho, b.x1, N0, tw(1), s);
-    if (e != hipSuccess) return hip_status(p, e);
-    mk.mark();
-    e = vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s);
-    if (e != hipSuccess) return hip_status(p, e);
-    mk.mark();
     const int64_t yfs = N0 * H;
-    int f0 = 0;
-    if (phi) {
-      e = vgf::launch_c2r<T>((int)p->P[1], b.y, phi, N0, 1, 0, 0, tw(1), s);
-      if (e != hipSuccess) return hip_status(p, e);
-      f0 = 1;
+    g.out_fs = yfs;
+    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
+    mk.mark();
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s));
+    mk.mark();
+    if (phi && E) {
+      vgf::C2RArgs<T> ca{b.y, {phi, E + vol}, N0, deriv2<T>(p, 1, 0, -1)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
+    } else if (phi) {
+      vgf::C2RArgs<T> ca{b.y, {phi, nullptr}, N0, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
+    } else {
+      vgf::C2RArgs<T> ca{b.y, {E + vol, nullptr}, N0, deriv1<T>(p, 1, -1)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
     }
     if (E) {
-      e = vgf::launch_c2r<T>((int)p->P[1], b.y + f0 * yfs, E, N0, d, yfs, vol, tw(1), s);
-      if (e != hipSuccess) return hip_status(p, e);
+      vgf::C2RArgs<T> c0{b.y + yfs, {E, nullptr}, N0, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], c0, tw(1), s));
     }
     mk.mark();
   }
   return VGF_OK;
 }
 
+// Adjoint: the mirror image of solve_t. Forward passes sum their inputs
+// after multiplying by +i k of their own axis (the conjugate of -i k), the
+// axis-0 pass multiplies by the (real) kernel spectrum and +i k_0, and the
+// inverse passes are plain.
 template <typename T>
 vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H;
+  const int64_t vol = prod(p->n, d);
   Bufs<T> b = bufs<T>(p);
   const T* spec = (const T*)p->spec;
   auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
   vgf::FusedGeom<T> g = fused_geom<T>(p);
   g.nf = 0;
-  if (g_phi) g.fields[g.nf++] = 0;
-  if (g_E)
-    for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
-  hipError_t e;
+  g.fields[g.nf++] = 0;
+  if (g_E) g.fields[g.nf++] = 1;
+  const int last = d - 1;
+  // A = R2C(g_phi) + i k_last R2C(g_E[last])
+  vgf::R2CArgs<T> ra{};
+  ra.nlines = d == 3 ? N0 * N1 : N0;
+  ra.d.ks = (T)wavenumber_step(p, last);
+  ra.d.n = 0;
+  if (g_phi) { ra.in[ra.d.n] = g_phi; ra.d.code[ra.d.n++] = 0; }
+  if (g_E) { ra.in[ra.d.n] = g_E + last * vol; ra.d.code[ra.d.n++] = 1; }
   if (d == 3) {
     const int64_t P1 = p->P[1];
-    const int64_t lines = N0 * N1, zfs = N0 * N1 * H, yfs = N0 * P1 * H;
-    // forward half-transforms of every incoming gradient into the Z region
-    int f0 = 0;
-    if (g_phi) {
-      e = vgf::launch_r2c<T>((int)p->P[2], g_phi, b.z, lines, tw(2), s);
-      if (e != hipSuccess) return hip_status(p, e);
-      f0 = 1;
-    }
+    const int64_t yfs = N0 * P1 * H, zfs = N0 * N1 * H;
+    cplx<T>* za = b.z;
+    cplx<T>* zb1 = b.z + zfs;
+    cplx<T>* zb0 = b.z + 2 * zfs;
+    ra.out = za;
+    VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
     if (g_E) {
-      e = vgf::launch_r2c<T>((int)p->P[2], g_E, b.z + f0 * zfs, d * lines, tw(2), s);
-      if (e != hipSuccess) return hip_status(p, e);
+      vgf::R2CArgs<T> r1{{g_E + vol, nullptr}, zb1, N0 * N1, deriv1<T>(p, 2, 0)};
+      VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], r1, tw(2), s));
+      vgf::R2CArgs<T> r0{{g_E, nullptr}, zb0, N0 * N1, deriv1<T>(p, 2, 0)};
+      VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], r0, tw(2), s));
     }
-    vgf::StridedArgs fa{H, H, H, N1 * H, P1 * H, zfs, yfs, (int)N0, g.nf};
-    e = vgf::launch_c2c<T>((int)P1, -1, b.z, b.y, fa, tw(1), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    const vgf::StridedGeom fg{H, H, H, N1 * H, P1 * H, (int)N0};
+    vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
+    if (g_E) {
+      vgf::C2CFwdArgs<T> f0{{zb0, nullptr}, b.y + yfs, fg, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, f0, tw(1), s));
+    }
     g.in_fs = yfs;
-    e = vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x2, g, spec, tw(0), s);
-    if (e != hipSuccess) return hip_status(p, e);
-    vgf::StridedArgs ia{H, H, H, P1 * H, N1 * H, 0, 0, (int)N0, 1};
-    e = vgf::launch_c2c<T>((int)P1, 1, b.x2, b.x1, ia, tw(1), s);
-    if (e != hipSuccess) return hip_status(p, e);
-    e = vgf::launch_c2r<T>((int)p->P[2], b.x1, g_rho, lines, 1, 0, 0, tw(2), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x2, g, spec, tw(0), s));
+    const vgf::StridedGeom ig{H, H, H, P1 * H, N1 * H, (int)N0};
+    vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia, tw(1), s));
+    vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0 * N1, deriv1<T>(p, 2, 0)};
+    VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
   } else {
     const int64_t yfs = N0 * H;
-    int f0 = 0;
-    if (g_phi) {
-      e = vgf::launch_r2c<T>((int)p->P[1], g_phi, b.y, N0, tw(1), s);
-      if (e != hipSuccess) return hip_status(p, e);
-      f0 = 1;
-    }
+    ra.out = b.y;
+    VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
     if (g_E) {
-      e = vgf::launch_r2c<T>((int)p->P[1], g_E, b.y + f0 * yfs, d * N0, tw(1), s);
-      if (e != hipSuccess) return hip_status(p, e);
+      vgf::R2CArgs<T> r0{{g_E, nullptr}, b.y + yfs, N0, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], r0, tw(1), s));
     }
     g.in_fs = yfs;
-    e = vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x1, g, spec, tw(0), s);
-    if (e != hipSuccess) return hip_status(p, e);
-    e = vgf::launch_c2r<T>((int)p->P[1], b.x1, g_rho, N0, 1, 0, 0, tw(1), s);
-    if (e != hipSuccess) return hip_status(p, e);
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x1, g, spec, tw(0), s));
+    vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
   }
   return VGF_OK;
 }
@@ -485,15 +536,19 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
     oct *= (n[a] + 1);
     vol *= n[a];
   }
+  // Y holds the axis-0 outputs (phi's spectrum, and E_0's when E is
+  // requested); Z the axis-1 outputs (phi, E_1, E_0). The adjoint reuses
+  // the same regions in the mirrored order.
+  const size_t ny = (outputs & VGF_OUT_E) ? 2 : 1, nz = (outputs & VGF_OUT_E) ? 3 : 1;
   size_t x1 = 0, x2 = 0, y = 0, z = 0;
   if (dim == 3) {
     x1 = (size_t)(N0 * N1 * H);
     x2 = (size_t)(N0 * p->P[1] * H);
-    y = (size_t)p->nf_max * x2;
-    z = (size_t)p->nf_max * x1;
+    y = ny * x2;
+    z = nz * x1;
   } else {
     x1 = (size_t)(N0 * H);
-    y = (size_t)p->nf_max * x1;
+    y = ny * x1;
   }
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
   p->off_x1 = 0;

@@ -23,38 +23,79 @@ inline bool supported_fft_len(int64_t P) {
   }
 }
 
-// Strided line transform geometry: element pos of column col, batch b,
-// field f is at base + f*fs + b*bs + pos*ls + col.
-struct StridedArgs {
+// Geometry of a batch of lines along a strided axis: element pos of
+// column col (contiguous), batch b is at base + b*bs + pos*ls + col.
+struct StridedGeom {
   int64_t ncols;
   int64_t ls_in, ls_out;
   int64_t bs_in, bs_out;
-  int64_t fs_in, fs_out;
-  int nbatch, nfields;
+  int nbatch;
 };
 
-// Geometry of the axis-0 (outermost) fused pass.
+// Spectral derivative factors along the transformed axis. A forward pass
+// sums up to two inputs, each multiplied after its transform; an inverse
+// pass expands one input into up to two outputs, each multiplied before its
+// transform. code 0: factor 1; -1: factor -i k; +1: factor +i k, where
+// k = ks * s and s is the signed frequency of the position on the 2N axis
+// (the Nyquist index gets s = 0).
+template <typename T> struct Deriv {
+  int n;
+  int code[2];
+  T ks;
+};
+
+template <typename T> struct R2CArgs {
+  const T* in[2];
+  cplx<T>* out;
+  int64_t nlines;
+  Deriv<T> d;
+};
+
+template <typename T> struct C2RArgs {
+  const cplx<T>* in;
+  T* out[2];
+  int64_t nlines;
+  Deriv<T> d;
+};
+
+template <typename T> struct C2CFwdArgs {
+  const cplx<T>* in[2];
+  cplx<T>* out;
+  StridedGeom g;
+  Deriv<T> d;
+};
+
+template <typename T> struct C2CInvArgs {
+  const cplx<T>* in;
+  cplx<T>* out[2];
+  StridedGeom g;
+  Deriv<T> d;
+};
+
+// Geometry of the axis-0 (outermost) fused pass. Forward: one input, outputs
+// fields[f] in {0: times the kernel spectrum, 1: times -i k_0 and the kernel
+// spectrum}, at out + f*out_fs. Adjoint: inputs fields[f] at in + f*in_fs,
+// summed with the conjugate factors, one output.
 template <typename T> struct FusedGeom {
   int64_t ncols;     // columns of the inner plane: P1*H2 (3D) or H1 (2D)
-  int64_t out_fs;    // field stride of the output (forward)
-  int64_t in_fs;     // field stride of the input (adjoint)
+  int64_t out_fs;
+  int64_t in_fs;
   int dim;
   int n0, n1, n2;    // points per axis (n2 unused in 2D)
   int h_last;        // N_last + 1
-  T ks0, ks1, ks2;   // 2 pi / (P_a h_a)
-  int nf;            // number of fields
-  int fields[4];     // 0: phi, 1 + a: E_a
+  T ks0;             // 2 pi / (P_0 h_0)
+  int nf;
+  int fields[2];
 };
 
 template <typename T>
-hipError_t launch_r2c(int P, const T* in, cplx<T>* out, int64_t nlines, const cplx<T>* tw,
-                      hipStream_t s);
+hipError_t launch_r2c(int P, const R2CArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_c2r(int P, const cplx<T>* in, T* out, int64_t nlines, int nf, int64_t in_fs,
-                      int64_t out_fs, const cplx<T>* tw, hipStream_t s);
+hipError_t launch_c2r(int P, const C2RArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_c2c(int P, int sign, const cplx<T>* in, cplx<T>* out, const StridedArgs& sa,
-                      const cplx<T>* tw, hipStream_t s);
+hipError_t launch_c2c_fwd(int P, const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_c2c_inv(int P, const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_fused(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,
                         const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
