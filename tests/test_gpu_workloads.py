@@ -1,0 +1,148 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times, against the FP64 oracle.
+
+beam_3d_256     3D 256^3 VGF, phi + E, FP64 (<= 1e-12) and FP32 (<= 1e-5):
+                full grids against the oracle's 2N FFT path, plus sampled
+                potentials against the FFT-free direct sums.
+batch_3d_mixed  64 right-hand sides of uneven N in {32,48,64,96,128}, FP32:
+                every one against the oracle, and batched == one at a time.
+diff_3d_128     8 right-hand sides at 128^3, FP32, E only: the gradient of
+                sum ||E(rho) - E_target||^2 through the hand-written adjoint
+                (torch.autograd) against the FP64 oracle gradient and against
+                central finite differences (eps = 1e-3 relative)."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_common import (FP32_TOL, FP64_TOL, check_fields, gpu_solve, need_gpu, oracle_kernel,
+                        rel_l2, rounded_input, say)
+from paper_2103_08531_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def beam():
+    ch = W.beam_3d_256(seed=0)
+    rho = ch.rho()
+    return ch, rho
+
+
+@pytest.fixture(scope="module")
+def beam_kernel(beam):
+    ch, rho = beam
+    L = orc.default_L(ch.n, ch.h)  # 1.1 x the box diameter, the library's default
+    say("oracle kernel 256^3 ...")
+    return L, orc.vgf_kernel(ch.n, ch.h, L)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_beam_3d_256(beam, beam_kernel, precision):
+    torch, vgf = need_gpu()
+    ch, rho64 = beam
+    L, w = beam_kernel
+    say("beam_3d_256", precision)
+    plan = vgf.Plan(ch.n, ch.h, method="vgf", precision=precision)
+    assert abs(plan.L - L) < 1e-12 * L
+    rho = rounded_input(rho64, precision)
+    phi_g, E_g = gpu_solve(plan, rho)
+    plan.close()
+    say("  oracle 2N path 256^3 ...")
+    phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, w, rho)
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "beam %s" % precision)
+    # sampled points against the direct discrete convolution (no FFT at all)
+    rng = np.random.default_rng(5)
+    idx = [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(6)]
+    idx += [(128, 128, 128), (0, 0, 0), (255, 255, 255)]
+    scale = np.max(np.abs(phi_o))
+    for i in idx:
+        ref = orc.conv_direct_point(ch.n, w, rho, i)
+        err = abs(phi_g[i] - ref) / scale
+        assert err <= (1e-13 if precision == "f64" else 1e-6), (i, err)
+    say("  sampled direct sums ok")
+    if precision == "f64":
+        # against the untruncated analytic potential on a stride-8 subsample:
+        # limited by the charge outside the box (sigma_z = 0.3 on [-1, 1])
+        sub = tuple(slice(0, 256, 8) for _ in range(3))
+        n_s = (32, 32, 32)
+        h_s = tuple(8 * x for x in ch.h)
+        pa, Ea = orc.gauss_mixture_grid(n_s, ch.x0, h_s, ch.centers, ch.sigmas, ch.weights, iso=False)
+        ea = rel_l2(phi_g[sub], pa)
+        say("  vs analytic (stride 8): phi %.3e E %.3e" % (ea, rel_l2(E_g[(slice(None),) + sub], Ea)))
+        assert ea < 5e-3
+
+
+def test_batch_3d_mixed():
+    torch, vgf = need_gpu()
+    charges = W.batch_3d_mixed(seed=0, count=64)
+    plans = {}
+    kernels = {}
+    for ch in charges:
+        if ch.n not in plans:
+            plans[ch.n] = vgf.Plan(ch.n, ch.h, method="vgf", precision="f32")
+            kernels[ch.n] = orc.vgf_kernel(ch.n, ch.h, plans[ch.n].L)
+    rhos = [torch.from_numpy(ch.rho()).to("cuda", torch.float32) for ch in charges]
+    pl = [plans[ch.n] for ch in charges]
+    phis = [torch.empty(ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    Es = [torch.empty((3,) + ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    say("batch of 64, sizes", sorted(set(c.n[0] for c in charges)))
+    vgf.solve_batched(pl, rhos, phis, Es)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for b, (ch, r, p, E, plan) in enumerate(zip(charges, rhos, phis, Es, pl)):
+        p1, E1 = plan.solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(p, p1) and torch.equal(E, E1), b
+        rho = rounded_input(ch.rho(), "f32")
+        phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, kernels[ch.n], rho)
+        errs = check_fields(p.double().cpu().numpy(), E.double().cpu().numpy(), phi_o, E_o,
+                            FP32_TOL, "batch[%d] N=%d" % (b, ch.n[0]))
+        worst = max(worst, max(errs.values()))
+    say("batch worst rel-L2 %.3e" % worst)
+    for p in plans.values():
+        p.close()
+
+
+def test_diff_3d_128():
+    torch, vgf = need_gpu()
+    rhs, target = W.diff_3d_128(seed=0)
+    n, h = rhs[0].n, rhs[0].h
+    plan = vgf.Plan(n, h, method="vgf", precision="f32", outputs=("E",))
+    _, E_t = orc.gauss_mixture_grid(target.n, target.x0, target.h, target.centers, target.sigmas,
+                                    target.weights, want_phi=False)
+    w = orc.vgf_kernel(n, h, plan.L)
+    Et_dev = torch.from_numpy(E_t).to("cuda", torch.float32)
+
+    def loss_of(rho_dev):
+        _, E = vgf.solve(rho_dev, plan)
+        return torch.sum((E.double() - Et_dev.double()) ** 2)
+
+    for b, ch in enumerate(rhs):
+        rho_np = rounded_input(ch.rho(), "f32")
+        rho = torch.from_numpy(rho_np).to("cuda", torch.float32).requires_grad_(True)
+        loss = loss_of(rho)
+        loss.backward()
+        grad = rho.grad.double().cpu().numpy()
+        # FP64 oracle gradient: 2 K_E^T (E(rho) - E_target)
+        _, E_o = orc.solve_fft2n(n, h, w, rho_np, want_phi=False)
+        g_o = orc.adjoint_fft2n(n, h, w, None, 2.0 * (E_o - E_t))
+        e = rel_l2(grad, g_o)
+        say("diff[%d] grad vs oracle %.3e" % (b, e))
+        assert e <= FP32_TOL
+        # central finite differences along seeded directions (loss is quadratic)
+        if b < 2:
+            U = W.fd_directions(b, n, 4, rho_np)
+            eps = 1e-3
+            for k in range(U.shape[0]):
+                rp = (rho_np + eps * U[k]).astype(np.float32)
+                rm = (rho_np - eps * U[k]).astype(np.float32)
+                with torch.no_grad():
+                    lp = loss_of(torch.from_numpy(rp).cuda()).item()
+                    lm = loss_of(torch.from_numpy(rm).cuda()).item()
+                # the loss is quadratic: L(a) - L(b) = <grad L((a+b)/2), a - b>
+                fd = (lp - lm) / 2.0
+                an = float(np.vdot(grad, (rp.astype(np.float64) - rm.astype(np.float64)) / 2.0))
+                say("  fd dir %d: fd %.8e adjoint %.8e" % (k, fd, an))
+                assert abs(fd - an) <= 1e-3 * abs(an) + 1e-6 * loss.item()
+    plan.close()
