@@ -36,7 +36,8 @@ struct vgf_plan_s {
   int64_t n[3] = {1, 1, 1};
   double h[3] = {1, 1, 1};
   int64_t P[3] = {1, 1, 1};
-  int64_t H = 1;  // N_last + 1
+  int64_t H = 1;   // N_last + 1: values of a half-spectrum line
+  int64_t Hs = 1;  // H padded to 128 bytes: row stride of the workspace arrays
   vgf_method method = VGF_METHOD_VGF;
   vgf_precision prec = VGF_F64;
   double L = 0.0;
@@ -279,7 +280,8 @@ template <typename T> vgf::FusedGeom<T> fused_geom(vgf_plan p) {
   g.n1 = (int)p->n[1];
   g.n2 = d == 3 ? (int)p->n[2] : 0;
   g.h_last = (int)p->H;
-  g.ncols = d == 3 ? p->P[1] * p->H : p->H;
+  g.hs = (int)p->Hs;
+  g.ncols = d == 3 ? p->P[1] * p->Hs : p->Hs;
   g.ks0 = (T)wavenumber_step(p, 0);
   return g;
 }
@@ -311,7 +313,7 @@ template <typename T> vgf::Deriv<T> deriv2(vgf_plan p, int axis, int code0, int 
 template <typename T>
 vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   const int d = p->dim;
-  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
   Bufs<T> b = bufs<T>(p);
   const T* spec = (const T*)p->spec;
@@ -324,19 +326,19 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   mk.mark();
   if (d == 3) {
     const int64_t P1 = p->P[1];
-    const int64_t yfs = N0 * P1 * H, zfs = N0 * N1 * H;
+    const int64_t yfs = N0 * P1 * Hs, zfs = N0 * N1 * Hs;
     g.out_fs = yfs;
-    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0 * N1, deriv1<T>(p, 2, 0)};
+    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
     mk.mark();
-    const vgf::StridedGeom fg{H, H, H, N1 * H, P1 * H, (int)N0};
+    const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
     mk.mark();
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s));
     mk.mark();
     // Yp -> Zp (phi, and E_2 later) and Z1 = -i k_1 Zp; Y0 -> Z0
-    const vgf::StridedGeom ig{H, H, H, P1 * H, N1 * H, (int)N0};
+    const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     cplx<T>* zp = b.z;
     cplx<T>* z1 = b.z + zfs;
     cplx<T>* z0 = b.z + 2 * zfs;
@@ -349,42 +351,42 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
     mk.mark();
     const int64_t lines = N0 * N1;
     if (phi && E) {
-      vgf::C2RArgs<T> ca{zp, {phi, E + 2 * vol}, lines, deriv2<T>(p, 2, 0, -1)};
+      vgf::C2RArgs<T> ca{zp, {phi, E + 2 * vol}, lines, Hs, deriv2<T>(p, 2, 0, -1)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
     } else if (phi) {
-      vgf::C2RArgs<T> ca{zp, {phi, nullptr}, lines, deriv1<T>(p, 2, 0)};
+      vgf::C2RArgs<T> ca{zp, {phi, nullptr}, lines, Hs, deriv1<T>(p, 2, 0)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
     } else {
-      vgf::C2RArgs<T> ca{zp, {E + 2 * vol, nullptr}, lines, deriv1<T>(p, 2, -1)};
+      vgf::C2RArgs<T> ca{zp, {E + 2 * vol, nullptr}, lines, Hs, deriv1<T>(p, 2, -1)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
     }
     if (E) {
-      vgf::C2RArgs<T> c1{z1, {E + vol, nullptr}, lines, deriv1<T>(p, 2, 0)};
+      vgf::C2RArgs<T> c1{z1, {E + vol, nullptr}, lines, Hs, deriv1<T>(p, 2, 0)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], c1, tw(2), s));
-      vgf::C2RArgs<T> c0{z0, {E, nullptr}, lines, deriv1<T>(p, 2, 0)};
+      vgf::C2RArgs<T> c0{z0, {E, nullptr}, lines, Hs, deriv1<T>(p, 2, 0)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], c0, tw(2), s));
     }
     mk.mark();
   } else {
-    const int64_t yfs = N0 * H;
+    const int64_t yfs = N0 * Hs;
     g.out_fs = yfs;
-    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0, deriv1<T>(p, 1, 0)};
+    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0, Hs, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
     mk.mark();
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s));
     mk.mark();
     if (phi && E) {
-      vgf::C2RArgs<T> ca{b.y, {phi, E + vol}, N0, deriv2<T>(p, 1, 0, -1)};
+      vgf::C2RArgs<T> ca{b.y, {phi, E + vol}, N0, Hs, deriv2<T>(p, 1, 0, -1)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
     } else if (phi) {
-      vgf::C2RArgs<T> ca{b.y, {phi, nullptr}, N0, deriv1<T>(p, 1, 0)};
+      vgf::C2RArgs<T> ca{b.y, {phi, nullptr}, N0, Hs, deriv1<T>(p, 1, 0)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
     } else {
-      vgf::C2RArgs<T> ca{b.y, {E + vol, nullptr}, N0, deriv1<T>(p, 1, -1)};
+      vgf::C2RArgs<T> ca{b.y, {E + vol, nullptr}, N0, Hs, deriv1<T>(p, 1, -1)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
     }
     if (E) {
-      vgf::C2RArgs<T> c0{b.y + yfs, {E, nullptr}, N0, deriv1<T>(p, 1, 0)};
+      vgf::C2RArgs<T> c0{b.y + yfs, {E, nullptr}, N0, Hs, deriv1<T>(p, 1, 0)};
       VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], c0, tw(1), s));
     }
     mk.mark();
@@ -399,7 +401,7 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
 template <typename T>
 vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
   const int d = p->dim;
-  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
   Bufs<T> b = bufs<T>(p);
   const T* spec = (const T*)p->spec;
@@ -412,25 +414,26 @@ vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStre
   // A = R2C(g_phi) + i k_last R2C(g_E[last])
   vgf::R2CArgs<T> ra{};
   ra.nlines = d == 3 ? N0 * N1 : N0;
+  ra.hs = Hs;
   ra.d.ks = (T)wavenumber_step(p, last);
   ra.d.n = 0;
   if (g_phi) { ra.in[ra.d.n] = g_phi; ra.d.code[ra.d.n++] = 0; }
   if (g_E) { ra.in[ra.d.n] = g_E + last * vol; ra.d.code[ra.d.n++] = 1; }
   if (d == 3) {
     const int64_t P1 = p->P[1];
-    const int64_t yfs = N0 * P1 * H, zfs = N0 * N1 * H;
+    const int64_t yfs = N0 * P1 * Hs, zfs = N0 * N1 * Hs;
     cplx<T>* za = b.z;
     cplx<T>* zb1 = b.z + zfs;
     cplx<T>* zb0 = b.z + 2 * zfs;
     ra.out = za;
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
     if (g_E) {
-      vgf::R2CArgs<T> r1{{g_E + vol, nullptr}, zb1, N0 * N1, deriv1<T>(p, 2, 0)};
+      vgf::R2CArgs<T> r1{{g_E + vol, nullptr}, zb1, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
       VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], r1, tw(2), s));
-      vgf::R2CArgs<T> r0{{g_E, nullptr}, zb0, N0 * N1, deriv1<T>(p, 2, 0)};
+      vgf::R2CArgs<T> r0{{g_E, nullptr}, zb0, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
       VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], r0, tw(2), s));
     }
-    const vgf::StridedGeom fg{H, H, H, N1 * H, P1 * H, (int)N0};
+    const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
     if (g_E) {
@@ -439,22 +442,22 @@ vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStre
     }
     g.in_fs = yfs;
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x2, g, spec, tw(0), s));
-    const vgf::StridedGeom ig{H, H, H, P1 * H, N1 * H, (int)N0};
+    const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia, tw(1), s));
-    vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0 * N1, deriv1<T>(p, 2, 0)};
+    vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
     VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
   } else {
-    const int64_t yfs = N0 * H;
+    const int64_t yfs = N0 * Hs;
     ra.out = b.y;
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
     if (g_E) {
-      vgf::R2CArgs<T> r0{{g_E, nullptr}, b.y + yfs, N0, deriv1<T>(p, 1, 0)};
+      vgf::R2CArgs<T> r0{{g_E, nullptr}, b.y + yfs, N0, Hs, deriv1<T>(p, 1, 0)};
       VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], r0, tw(1), s));
     }
     g.in_fs = yfs;
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x1, g, spec, tw(0), s));
-    vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0, deriv1<T>(p, 1, 0)};
+    vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0, Hs, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
   }
   return VGF_OK;
@@ -523,6 +526,10 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
     p->P[a] = 2 * n[a];
   }
   p->H = n[dim - 1] + 1;
+  {
+    const int64_t align = prec == VGF_F32 ? 16 : 8;  // complex values per 128 bytes
+    p->Hs = (p->H + align - 1) / align * align;
+  }
   p->method = method;
   p->prec = prec;
   p->L = Lp;
@@ -530,7 +537,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->nf_max = ((outputs & VGF_OUT_PHI) ? 1 : 0) + ((outputs & VGF_OUT_E) ? dim : 0);
 
   const size_t rb = prec == VGF_F32 ? 4 : 8, cb = 2 * rb;
-  const int64_t N0 = n[0], N1 = n[1], H = p->H;
+  const int64_t N0 = n[0], N1 = n[1], H = p->Hs;
   int64_t oct = 1, vol = 1;
   for (int a = 0; a < dim; ++a) {
     oct *= (n[a] + 1);

@@ -176,7 +176,8 @@ struct Stage {
     return w;
   }
 
-  // first stage (Ns = 1, no twiddles); ld(pos) returns the input at pos.
+  // first stage (Ns = 1, no twiddles); ld(j, r) returns the input at
+  // position j + r*NB (r is a compile-time constant at every call).
   // PRUNE: inputs at positions >= P/2 are zero and are not read.
   template <bool PRUNE, class Load>
   __device__ __forceinline__ static void load_first(Regs& g, int q, Load&& ld) {
@@ -189,7 +190,7 @@ struct Stage {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (PRUNE && r >= R / 2) g.v[t][r] = C{T(0), T(0)};
-        else g.v[t][r] = ld(in_pos(j, r));
+        else g.v[t][r] = ld(j, r);
       }
     }
   }
@@ -226,8 +227,8 @@ struct Stage {
     }
   }
 
-  // last stage outputs (Ns = P/R, so positions are j + r*NB); st(pos, value).
-  // PRUNE: only positions < P/2 are stored.
+  // last stage outputs (Ns = P/R, so positions are j + r*NB); st(j, r, value)
+  // with r a compile-time constant. PRUNE: only positions < P/2 are stored.
   template <bool PRUNE, class Store>
   __device__ __forceinline__ static void store_last(const Regs& g, int q, Store&& st) {
     static_assert(LAST, "store_last is the last stage");
@@ -239,11 +240,28 @@ struct Stage {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (PRUNE && r >= R / 2) continue;
-        st(out_pos(j, r), g.v[t][r]);
+        st(j, r, g.v[t][r]);
       }
     }
   }
 };
+
+#ifndef VGF_MINW_DIV
+#define VGF_MINW_DIV 2
+#endif
+
+// Waves per SIMD that the LDS footprint of a workgroup allows (160 KiB of
+// LDS per CU, 4 SIMDs): the register budget is tied to this occupancy so the
+// compiler does not trade it away for registers.
+constexpr int lds_waves_per_simd(int lds_bytes, int threads) {
+  int wg = lds_bytes > 0 ? (160 * 1024) / lds_bytes : 8;
+  if (wg > 8) wg = 8;
+  if (wg < 1) wg = 1;
+  int w = wg * ((threads + 63) / 64) / 4 / VGF_MINW_DIV;
+  if (w < 1) w = 1;
+  if (w > 8) w = 8;
+  return w;
+}
 
 template <int B, int E> struct StaticFor {
   template <class F> __device__ __forceinline__ static void run(F&& f) {

@@ -46,15 +46,17 @@ template <typename T> struct Deriv {
 
 template <typename T> struct R2CArgs {
   const T* in[2];
-  cplx<T>* out;
+  cplx<T>* out;    // lines of N+1 values at stride hs
   int64_t nlines;
+  int64_t hs;
   Deriv<T> d;
 };
 
 template <typename T> struct C2RArgs {
-  const cplx<T>* in;
+  const cplx<T>* in;  // lines of N+1 values at stride hs
   T* out[2];
   int64_t nlines;
+  int64_t hs;
   Deriv<T> d;
 };
 
@@ -77,12 +79,13 @@ template <typename T> struct C2CInvArgs {
 // spectrum}, at out + f*out_fs. Adjoint: inputs fields[f] at in + f*in_fs,
 // summed with the conjugate factors, one output.
 template <typename T> struct FusedGeom {
-  int64_t ncols;     // columns of the inner plane: P1*H2 (3D) or H1 (2D)
+  int64_t ncols;     // columns of the inner plane: P1*hs (3D) or hs (2D)
   int64_t out_fs;
   int64_t in_fs;
   int dim;
   int n0, n1, n2;    // points per axis (n2 unused in 2D)
-  int h_last;        // N_last + 1
+  int h_last;        // N_last + 1 (valid values along the last axis)
+  int hs;            // padded stride of the last axis (>= h_last)
   T ks0;             // 2 pi / (P_0 h_0)
   int nf;
   int fields[2];

@@ -31,6 +31,12 @@
 #include "vgf_fft.hpp"
 #include "vgf_internal.hpp"
 
+// Complex values per thread in the Stockham kernels: 8 (one radix-8
+// butterfly per stage) measured fastest at 256^3 in both precisions.
+#ifndef VGF_EPT
+#define VGF_EPT 8
+#endif
+
 namespace vgf {
 
 // Tile shape for length P: NL lines (contiguous columns) per workgroup, 16
@@ -43,11 +49,14 @@ template <typename T, int P> struct Tile {
     return nl;
   }
   static constexpr int NL = pick_nl();
-  static constexpr int EPT = 16;
+  static constexpr int EPT = VGF_EPT;
   static constexpr int NQ = (P + EPT - 1) / EPT;  // threads per line
   static constexpr int NT = NL * NQ;
   static_assert(NT <= 1024, "workgroup too large");
   static_assert(n_stages(P) >= 2, "transform needs at least two stages");
+  // LDS of the strided kernels (tile + twiddles) and of r2c/c2r (padded tile)
+  static constexpr int MINW = lds_waves_per_simd((P * NL + P) * CB, NT);
+  static constexpr int MINW_T = lds_waves_per_simd((P * (NL + 1) + P) * CB, NT);
 };
 
 // signed frequency of index k on a length-2N axis, Nyquist index N -> 0
@@ -71,8 +80,8 @@ __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw,
 // ---------------------------------------------------------------------------
 // k_r2c: out = sum_t m_t(k) R2C(in_t), lines of N = P/2 reals -> N+1 complex
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT)) void k_r2c(R2CArgs<T> a,
+template <typename T, int P, int NTERM>
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_T)) void k_r2c(R2CArgs<T> a,
                                                          const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   using TL = Tile<T, P>;
@@ -89,7 +98,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_r2c(R2CArgs<T> a,
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) acc[s] = C{T(0), T(0)};
 
-  for (int term = 0; term < a.d.n; ++term) {
+#pragma unroll
+  for (int term = 0; term < NTERM; ++term) {
     const T* __restrict__ in = a.in[term];
     const int code = a.d.code[term];
     if (term > 0) __syncthreads();
@@ -102,7 +112,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_r2c(R2CArgs<T> a,
     __syncthreads();
     using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
     typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int pos) { return lds[pos * LP + l]; });
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return lds[S0::in_pos(j, r) * LP + l]; });
     S0::butterflies(g0, q);
     __syncthreads();
     S0::lds_out(g0, lds, l, q);
@@ -136,15 +146,15 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_r2c(R2CArgs<T> a,
     if (idx >= 2 * NL * H) continue;
     const int ll = idx / H, k = idx - ll * H;
     const int64_t line = line0 + ll;
-    if (line < a.nlines) a.out[line * H + k] = acc[s];
+    if (line < a.nlines) a.out[line * a.hs + k] = acc[s];
   }
 }
 
 // ---------------------------------------------------------------------------
 // k_c2r: out_o = first N reals of C2R(m_o(k) in), lines of N+1 complex
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2r(C2RArgs<T> a,
+template <typename T, int P, int NOUT>
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_T)) void k_c2r(C2RArgs<T> a,
                                                          const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   using TL = Tile<T, P>;
@@ -166,11 +176,12 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2r(C2RArgs<T> a,
     if (idx >= NL * H) continue;
     const int c = idx / H, k = idx - c * H;
     const int64_t la = line0 + 2 * c, lb = la + 1;
-    if (la < a.nlines) xs[s] = a.in[la * H + k];
-    if (lb < a.nlines) ys[s] = a.in[lb * H + k];
+    if (la < a.nlines) xs[s] = a.in[la * a.hs + k];
+    if (lb < a.nlines) ys[s] = a.in[lb * a.hs + k];
   }
 
-  for (int o = 0; o < a.d.n; ++o) {
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
     const int code = a.d.code[o];
     T* __restrict__ out = a.out[o];
     if (o > 0) __syncthreads();
@@ -193,7 +204,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2r(C2RArgs<T> a,
     __syncthreads();
     using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
     typename S0::Regs g0;
-    S0::template load_first<false>(g0, q, [&](int pos) { return lds[pos * LP + l]; });
+    S0::template load_first<false>(g0, q, [&](int j, int r) { return lds[S0::in_pos(j, r) * LP + l]; });
     S0::butterflies(g0, q);
     __syncthreads();
     S0::lds_out(g0, lds, l, q);
@@ -202,7 +213,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2r(C2RArgs<T> a,
     typename SL::Regs gl;
     middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
     __syncthreads();
-    SL::template store_last<true>(gl, q, [&](int pos, C v) { lds[pos * LP + l] = v; });
+    SL::template store_last<true>(gl, q, [&](int j, int r, C v) { lds[SL::out_pos(j, r) * LP + l] = v; });
     __syncthreads();
     for (int idx = tid; idx < 2 * NL * N; idx += NT) {
       const int ll = idx / N, pos = idx - ll * N;
@@ -215,34 +226,74 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2r(C2RArgs<T> a,
 }
 
 // ---------------------------------------------------------------------------
+// Addressing of the strided passes. Every array the solve path touches holds
+// fewer than 2^31 elements, so element offsets are 32-bit and added to a
+// workgroup-uniform base. Element (row, col) is at base + col + row*ls; a
+// stage's rows are j + r*NB with r a compile-time constant, so the per-r
+// part r*NB*ls is uniform. Lanes past the last column load the last column
+// (in bounds, never stored).
+// ---------------------------------------------------------------------------
+struct ColIO {
+  uint32_t col;   // clamped column
+  uint32_t ls;    // row stride (elements)
+  bool valid;
+  __device__ __forceinline__ ColIO(int64_t c, int64_t ncols, int64_t ls_) {
+    valid = c < ncols;
+    col = (uint32_t)(valid ? c : ncols - 1);
+    ls = (uint32_t)ls_;
+  }
+  // offset of row j + r*NB
+  template <int NB>
+  __device__ __forceinline__ uint32_t off(int j, int r) const {
+    return col + (uint32_t)j * ls + (uint32_t)(r * NB) * ls;
+  }
+};
+
+// wavenumber factor of position j + r*NB on a length-P axis (P = 2N), with
+// the Nyquist position N -> 0. For an even radix the rows j + r*NB cross N
+// exactly at r = R/2 (and equal it only for j = 0), which r, a compile-time
+// constant at every call, decides; odd radices compare at run time.
+template <typename T, int R, int NB>
+__device__ __forceinline__ T axis_k(T ks, int j, int r) {
+  constexpr int P = R * NB, N = P / 2;
+  if constexpr (R % 2 == 0) {
+    T k = ks * (T)(j + r * NB - (r >= R / 2 ? P : 0));
+    if (r == R / 2 && j == 0) k = T(0);
+    return k;
+  } else {
+    const int pos = j + r * NB;
+    return ks * (T)(pos < N ? pos : (pos == N ? 0 : pos - P));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_c2c_fwd: out = sum_t m_t(pos) FFT(in_t) along a strided axis, pruned input
 // grid = (ceil(ncols/NL), nbatch)
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2c_fwd(C2CFwdArgs<T> a,
+template <typename T, int P, int NTERM>
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_fwd(C2CFwdArgs<T> a,
                                                              const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   using TL = Tile<T, P>;
-  constexpr int NL = TL::NL, NT = TL::NT, LP = NL, N = P / 2;
+  constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const int64_t col = (int64_t)blockIdx.x * NL + l;
-  const bool valid = col < a.g.ncols;
   stage_twiddles<C, P, NT>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
+  const ColIO ci((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_in);
+  const ColIO co((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_out);
   typename SL::Regs acc;
 
-  for (int term = 0; term < a.d.n; ++term) {
-    const C* src = a.in[term] + blockIdx.y * a.g.bs_in + col;
+#pragma unroll
+  for (int term = 0; term < NTERM; ++term) {
+    const C* __restrict__ src = a.in[term] + blockIdx.y * a.g.bs_in;
     const int code = a.d.code[term];
     if (term > 0) __syncthreads();
     typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int pos) {
-      return valid ? src[pos * a.g.ls_in] : C{T(0), T(0)};
-    });
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
     S0::butterflies(g0, q);
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
@@ -254,84 +305,117 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2c_fwd(C2CFwdArgs<T> a,
       const int j = q + t * SL::NQ;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
-        const C v = deriv(gl.v[t][r], code, a.d.ks * (T)signed_freq_zn(SL::out_pos(j, r), N));
+        C v = gl.v[t][r];
+        if (code != 0) v = deriv(v, code, axis_k<T, SL::R, SL::NB>(a.d.ks, j, r));
         if (term == 0) acc.v[t][r] = v;
         else { acc.v[t][r].x += v.x; acc.v[t][r].y += v.y; }
       }
     }
   }
-  C* dst = a.out + blockIdx.y * a.g.bs_out + col;
-  SL::template store_last<false>(acc, q, [&](int pos, C v) {
-    if (valid) dst[pos * a.g.ls_out] = v;
-  });
+  if (!co.valid) return;
+  C* __restrict__ dst = a.out + blockIdx.y * a.g.bs_out;
+  SL::template store_last<false>(acc, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
 }
 
 // ---------------------------------------------------------------------------
 // k_c2c_inv: out_o = first P/2 of IFFT(m_o(pos) in) along a strided axis
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT)) void k_c2c_inv(C2CInvArgs<T> a,
+template <typename T, int P, int NOUT>
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_inv(C2CInvArgs<T> a,
                                                              const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
   using TL = Tile<T, P>;
-  constexpr int NL = TL::NL, NT = TL::NT, LP = NL, N = P / 2;
+  constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const int64_t col = (int64_t)blockIdx.x * NL + l;
-  const bool valid = col < a.g.ncols;
-  stage_twiddles<C, P, NT>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
   using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
-  const C* src = a.in + blockIdx.y * a.g.bs_in + col;
+  const ColIO ci((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_in);
+  const ColIO co((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_out);
+  const C* __restrict__ src = a.in + blockIdx.y * a.g.bs_in;
   typename S0::Regs gin;
-  S0::template load_first<false>(gin, q, [&](int pos) {
-    return valid ? src[pos * a.g.ls_in] : C{T(0), T(0)};
-  });
+  S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
+  stage_twiddles<C, P, NT>(twl, tw, tid);
 
-  for (int o = 0; o < a.d.n; ++o) {
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
     const int code = a.d.code[o];
     if (o > 0) __syncthreads();
     typename S0::Regs g0;
+    if (code == 0) {
+      g0 = gin;
+    } else {
 #pragma unroll
-    for (int t = 0; t < S0::NTASK; ++t) {
-      if (!S0::active(t, q)) continue;
-      const int j = q + t * S0::NQ;
+      for (int t = 0; t < S0::NTASK; ++t) {
+        if (!S0::active(t, q)) continue;
+        const int j = q + t * S0::NQ;
 #pragma unroll
-      for (int r = 0; r < S0::R; ++r)
-        g0.v[t][r] = deriv(gin.v[t][r], code, a.d.ks * (T)signed_freq_zn(S0::in_pos(j, r), N));
+        for (int r = 0; r < S0::R; ++r)
+          g0.v[t][r] = deriv(gin.v[t][r], code, axis_k<T, S0::R, S0::NB>(a.d.ks, j, r));
+      }
     }
     S0::butterflies(g0, q);
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
     typename SL::Regs gl;
     middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
-    C* dst = a.out[o] + blockIdx.y * a.g.bs_out + col;
-    SL::template store_last<true>(gl, q, [&](int pos, C v) {
-      if (valid) dst[pos * a.g.ls_out] = v;
-    });
+    if (co.valid) {
+      C* __restrict__ dst = a.out[o] + blockIdx.y * a.g.bs_out;
+      SL::template store_last<true>(gl, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
+    }
   }
 }
 
-// Column coordinates of the axis-0 lines: in 3D column c of the [P1][H2]
-// plane is (k1, k2); in 2D it is k1 in [0, H1).
-template <typename T> struct ColCoord {
-  int f1, k2;  // folded axis-1 index, axis-2 index
-  __device__ __forceinline__ ColCoord(const FusedGeom<T>& g, int64_t col) {
+// Kernel-spectrum addressing for the axis-0 lines: column c of the inner
+// plane (3D: (k1, k2) of [P1][H2]; 2D: k1 of [H1]) reads the octant at
+// [f0][f1][k2] with f_a = min(k_a, 2N_a - k_a). Row j + r*NB folds for
+// r >= R/2 (compile time), so the index is a per-lane base plus a uniform
+// per-r term.
+// Columns of the axis-0 pass: the last axis is stored at a padded stride
+// hs >= h_last, so a column is valid only if its last-axis index is below
+// h_last; other lanes compute on in-bounds padding and store nothing.
+template <typename T> struct FusedCol {
+  ColIO io;
+  uint32_t colpart;  // octant offset of (f1, k2) (3D) or f1 (2D)
+  __device__ __forceinline__ FusedCol(const FusedGeom<T>& g, int64_t c) : io(c, g.ncols, g.ncols) {
+    const int64_t cc = io.col;
     if (g.dim == 3) {
-      const int k1 = (int)(col / g.h_last);
-      k2 = (int)(col - (int64_t)k1 * g.h_last);
-      f1 = k1 <= g.n1 ? k1 : 2 * g.n1 - k1;
+      const int k1 = (int)(cc / g.hs);
+      int k2 = (int)(cc - (int64_t)k1 * g.hs);
+      if (k2 >= g.h_last) {
+        io.valid = false;
+        k2 = g.h_last - 1;
+      }
+      const int f1 = k1 <= g.n1 ? k1 : 2 * g.n1 - k1;
+      colpart = (uint32_t)(f1 * (g.n2 + 1) + k2);
     } else {
-      f1 = (int)col;
-      k2 = 0;
+      int k1 = (int)cc;
+      if (k1 >= g.h_last) {
+        io.valid = false;
+        k1 = g.h_last - 1;
+      }
+      colpart = (uint32_t)k1;
     }
   }
-  __device__ __forceinline__ int64_t spec_index(const FusedGeom<T>& g, int k0) const {
-    const int f0 = k0 <= g.n0 ? k0 : 2 * g.n0 - k0;
-    if (g.dim == 3) return ((int64_t)f0 * (g.n1 + 1) + f1) * (g.n2 + 1) + k2;
-    return (int64_t)f0 * (g.n1 + 1) + f1;
+};
+
+template <typename T> struct SpecIdx {
+  uint32_t lo, hi, plane;  // lo = colpart + j*plane, hi = colpart + (P0 - j)*plane
+  __device__ __forceinline__ SpecIdx(const FusedGeom<T>& g, uint32_t colpart, int j) {
+    plane = g.dim == 3 ? (uint32_t)((g.n1 + 1) * (g.n2 + 1)) : (uint32_t)(g.n1 + 1);
+    lo = colpart + (uint32_t)j * plane;
+    hi = colpart + (uint32_t)(2 * g.n0 - j) * plane;
+  }
+  template <int R, int NB>
+  __device__ __forceinline__ uint32_t at(int j, int r) const {
+    if constexpr (R % 2 == 0) {
+      return r < R / 2 ? lo + (uint32_t)(r * NB) * plane : hi - (uint32_t)(r * NB) * plane;
+    } else {  // odd radix: the fold point N falls inside a stripe of rows
+      constexpr int N = R * NB / 2;
+      return j + r * NB <= N ? lo + (uint32_t)(r * NB) * plane : hi - (uint32_t)(r * NB) * plane;
+    }
   }
 };
 
@@ -340,7 +424,7 @@ template <typename T> struct ColCoord {
 // (pruned out). in: [N0][ncols]; output f at out + f*out_fs, [N0][ncols].
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused(const cplx<T>* __restrict__ in,
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused(const cplx<T>* __restrict__ in,
                                                            cplx<T>* __restrict__ out,
                                                            FusedGeom<T> g,
                                                            const T* __restrict__ spec,
@@ -352,51 +436,55 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused(const cplx<T>* __res
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const int64_t col = (int64_t)blockIdx.x * NL + l;
-  const bool valid = col < g.ncols;
-  const C* src = in + col;
+  const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
+  const ColIO& cio = fc.io;
   stage_twiddles<C, P, NT>(twl, tw, tid);
 
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   typename S0::Regs g0;
-  S0::template load_first<true>(g0, q, [&](int pos) {
-    return valid ? src[pos * g.ncols] : C{T(0), T(0)};
-  });
-  S0::butterflies(g0, q);
-  S0::lds_out(g0, lds, l, q);
-  __syncthreads();
+  S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
-  typename SL::Regs rh;  // forward spectrum, natural order positions j + r*NB
-  middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
-
   using IS0 = Stage<T, P, NT, NL, LP, 1, 0>;
   using ISL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
-
-  const ColCoord<T> cc(g, valid ? col : 0);
+  // kernel spectrum at this thread's forward-output rows (natural order j + r*NB)
   T sv[SL::NTASK][SL::R];
 #pragma unroll
   for (int t = 0; t < SL::NTASK; ++t) {
     if (!SL::active(t, q)) continue;
     const int j = q + t * SL::NQ;
+    const SpecIdx<T> si(g, fc.colpart, j);
 #pragma unroll
-    for (int r = 0; r < SL::R; ++r) sv[t][r] = valid ? spec[cc.spec_index(g, SL::in_pos(j, r))] : T(0);
+    for (int r = 0; r < SL::R; ++r) sv[t][r] = spec[si.template at<SL::R, SL::NB>(j, r)];
   }
+  S0::butterflies(g0, q);
+  S0::lds_out(g0, lds, l, q);
+  __syncthreads();
+  typename SL::Regs rh;  // forward spectrum times the kernel spectrum
+  middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t)
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) {
+      rh.v[t][r].x *= sv[t][r];
+      rh.v[t][r].y *= sv[t][r];
+    }
 
   for (int fi = 0; fi < g.nf; ++fi) {
-    const int code = g.fields[fi];
     typename IS0::Regs v;
+    if (g.fields[fi] == 0) {
 #pragma unroll
-    for (int t = 0; t < SL::NTASK; ++t) {
-      if (!SL::active(t, q)) continue;
-      const int j = q + t * SL::NQ;
+      for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
-      for (int r = 0; r < SL::R; ++r) {
-        const C x = rh.v[t][r];
-        const T s = sv[t][r];
-        const C m = C{x.x * s, x.y * s};
-        v.v[t][r] = code == 0 ? m
-                              : deriv(m, -1, g.ks0 * (T)signed_freq_zn(SL::in_pos(j, r), g.n0));
+        for (int r = 0; r < SL::R; ++r) v.v[t][r] = rh.v[t][r];
+    } else {
+#pragma unroll
+      for (int t = 0; t < SL::NTASK; ++t) {
+        if (!SL::active(t, q)) continue;
+        const int j = q + t * SL::NQ;
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r)
+          v.v[t][r] = deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks0, j, r));
       }
     }
     IS0::butterflies(v, q);
@@ -405,10 +493,10 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused(const cplx<T>* __res
     __syncthreads();
     typename ISL::Regs o;
     middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
-    C* dst = out + fi * g.out_fs + col;
-    ISL::template store_last<true>(o, q, [&](int pos, C val) {
-      if (valid) dst[pos * g.ncols] = val;
-    });
+    if (cio.valid) {
+      C* __restrict__ dst = out + fi * g.out_fs;
+      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
+    }
   }
 }
 
@@ -416,7 +504,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused(const cplx<T>* __res
 // k_fused_adj: acc = sum_f conj(m_f) * FFT(in_f); out = pruned inverse of acc
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused_adj(const cplx<T>* __restrict__ in,
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_adj(const cplx<T>* __restrict__ in,
                                                                cplx<T>* __restrict__ out,
                                                                FusedGeom<T> g,
                                                                const T* __restrict__ spec,
@@ -428,8 +516,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused_adj(const cplx<T>* _
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const int64_t col = (int64_t)blockIdx.x * NL + l;
-  const bool valid = col < g.ncols;
+  const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
+  const ColIO& cio = fc.io;
   stage_twiddles<C, P, NT>(twl, tw, tid);
 
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
@@ -438,26 +526,17 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused_adj(const cplx<T>* _
   using ISL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
 
-  const ColCoord<T> cc(g, valid ? col : 0);
-  T sv[SL::NTASK][SL::R];
   typename IS0::Regs acc;
 #pragma unroll
-  for (int t = 0; t < SL::NTASK; ++t) {
-    const int j = q + t * SL::NQ;
+  for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
-    for (int r = 0; r < SL::R; ++r) {
-      acc.v[t][r] = C{T(0), T(0)};
-      sv[t][r] = (SL::active(t, q) && valid) ? spec[cc.spec_index(g, SL::in_pos(j, r))] : T(0);
-    }
-  }
+    for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
 
   for (int fi = 0; fi < g.nf; ++fi) {
     const int code = g.fields[fi];
-    const C* src = in + fi * g.in_fs + col;
+    const C* __restrict__ src = in + fi * g.in_fs;
     typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int pos) {
-      return valid ? src[pos * g.ncols] : C{T(0), T(0)};
-    });
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
     S0::butterflies(g0, q);
     __syncthreads();
     S0::lds_out(g0, lds, l, q);
@@ -470,13 +549,24 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused_adj(const cplx<T>* _
       const int j = q + t * SL::NQ;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
-        const C x = rh.v[t][r];
-        const T s = sv[t][r];
-        C m = C{x.x * s, x.y * s};
-        if (code != 0) m = deriv(m, 1, g.ks0 * (T)signed_freq_zn(SL::in_pos(j, r), g.n0));
+        C m = rh.v[t][r];
+        if (code != 0) m = deriv(m, 1, axis_k<T, SL::R, SL::NB>(g.ks0, j, r));
         acc.v[t][r].x += m.x;
         acc.v[t][r].y += m.y;
       }
+    }
+  }
+  // the kernel spectrum is real: apply it once to the sum
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t) {
+    if (!SL::active(t, q)) continue;
+    const int j = q + t * SL::NQ;
+    const SpecIdx<T> si(g, fc.colpart, j);
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) {
+      const T sv = spec[si.template at<SL::R, SL::NB>(j, r)];
+      acc.v[t][r].x *= sv;
+      acc.v[t][r].y *= sv;
     }
   }
   IS0::butterflies(acc, q);
@@ -485,10 +575,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT)) void k_fused_adj(const cplx<T>* _
   __syncthreads();
   typename ISL::Regs o;
   middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
-  C* dst = out + col;
-  ISL::template store_last<true>(o, q, [&](int pos, C val) {
-    if (valid) dst[pos * g.ncols] = val;
-  });
+  if (cio.valid)
+    ISL::template store_last<true>(o, q, [&](int j, int r, C val) { out[cio.off<ISL::NB>(j, r)] = val; });
 }
 
 // ---------------------------------------------------------------------------
@@ -502,7 +590,10 @@ hipError_t launch_r2c_p(const R2CArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
   using TL = Tile<T, P>;
   const int64_t blocks = (a.nlines + 2 * TL::NL - 1) / (2 * TL::NL);
   if (blocks == 0 || a.d.n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_r2c<T, P>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+  if (a.d.n == 2)
+    hipLaunchKernelGGL((k_r2c<T, P, 2>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL((k_r2c<T, P, 1>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 
@@ -511,7 +602,10 @@ hipError_t launch_c2r_p(const C2RArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
   using TL = Tile<T, P>;
   const int64_t blocks = (a.nlines + 2 * TL::NL - 1) / (2 * TL::NL);
   if (blocks == 0 || a.d.n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_c2r<T, P>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+  if (a.d.n == 2)
+    hipLaunchKernelGGL((k_c2r<T, P, 2>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL((k_c2r<T, P, 1>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 
@@ -520,8 +614,11 @@ hipError_t launch_c2c_fwd_p(const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream
   using TL = Tile<T, P>;
   const int64_t bx = (a.g.ncols + TL::NL - 1) / TL::NL;
   if (bx == 0 || a.g.nbatch == 0 || a.d.n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_c2c_fwd<T, P>), dim3((unsigned)bx, (unsigned)a.g.nbatch), dim3(TL::NT), 0,
-                     s, a, tw);
+  const dim3 grid((unsigned)bx, (unsigned)a.g.nbatch);
+  if (a.d.n == 2)
+    hipLaunchKernelGGL((k_c2c_fwd<T, P, 2>), grid, dim3(TL::NT), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL((k_c2c_fwd<T, P, 1>), grid, dim3(TL::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 
@@ -530,8 +627,11 @@ hipError_t launch_c2c_inv_p(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream
   using TL = Tile<T, P>;
   const int64_t bx = (a.g.ncols + TL::NL - 1) / TL::NL;
   if (bx == 0 || a.g.nbatch == 0 || a.d.n == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_c2c_inv<T, P>), dim3((unsigned)bx, (unsigned)a.g.nbatch), dim3(TL::NT), 0,
-                     s, a, tw);
+  const dim3 grid((unsigned)bx, (unsigned)a.g.nbatch);
+  if (a.d.n == 2)
+    hipLaunchKernelGGL((k_c2c_inv<T, P, 2>), grid, dim3(TL::NT), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL((k_c2c_inv<T, P, 1>), grid, dim3(TL::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 

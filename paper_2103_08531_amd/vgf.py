@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvgf.so")
+# VGF_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("VGF_LIB") or os.path.join(HERE, "libvgf.so")
 
 OK = 0
 STATUS = {0: "VGF_OK", -1: "VGF_ERR_INVALID_ARG", -2: "VGF_ERR_UNSUPPORTED_SIZE",
