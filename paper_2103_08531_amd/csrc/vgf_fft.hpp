@@ -295,4 +295,42 @@ __device__ __forceinline__ void middle_and_last(
   SL::butterflies(last, q);
 }
 
+// Ping-pong variant for kernels that run one workgroup per CU anyway: LDS
+// phases alternate between two tiles, so each stage boundary needs a single
+// barrier (between the writes and the reads of one phase); a tile is written
+// again only two phases after it was read, with a barrier in between.
+template <typename C, int TILE> struct PingPong {
+  C* base;  // 2 * TILE elements
+  int off;  // 0 or TILE
+  __device__ __forceinline__ C* now() const { return base + off; }
+  __device__ __forceinline__ void flip() { off = TILE - off; }
+};
+
+// Stage 0 (already butterflied, in registers) -> LDS -> remaining stages; the
+// last stage's results end in `last`. Uses one barrier per LDS phase.
+template <typename T, int P, int NT, int NL, int LP, int SIGN>
+__device__ __forceinline__ void transform_pp(
+    const typename Stage<T, P, NT, NL, LP, SIGN, 0>::Regs& g0,
+    typename Stage<T, P, NT, NL, LP, SIGN, n_stages(P) - 1>::Regs& last, PingPong<cplx<T>, P * LP>& pp,
+    const cplx<T>* tw, int l, int q) {
+  constexpr int NSTG = n_stages(P);
+  using S0 = Stage<T, P, NT, NL, LP, SIGN, 0>;
+  S0::lds_out(g0, pp.now(), l, q);
+  __syncthreads();
+  StaticFor<1, NSTG - 1>::run([&](auto sI) {
+    constexpr int s = decltype(sI)::value;
+    using St = Stage<T, P, NT, NL, LP, SIGN, s>;
+    typename St::Regs g;
+    St::lds_in(g, pp.now(), tw, l, q);
+    St::butterflies(g, q);
+    pp.flip();
+    St::lds_out(g, pp.now(), l, q);
+    __syncthreads();
+  });
+  using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1>;
+  SL::lds_in(last, pp.now(), tw, l, q);
+  SL::butterflies(last, q);
+  pp.flip();
+}
+
 }  // namespace vgf

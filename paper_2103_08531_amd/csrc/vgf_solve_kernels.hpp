@@ -57,6 +57,7 @@ template <typename T, int P> struct Tile {
   // LDS of the strided kernels (tile + twiddles) and of r2c/c2r (padded tile)
   static constexpr int MINW = lds_waves_per_simd((P * NL + P) * CB, NT);
   static constexpr int MINW_T = lds_waves_per_simd((P * (NL + 1) + P) * CB, NT);
+  static constexpr int MINW_PP = lds_waves_per_simd((2 * P * NL + P) * CB, NT);
 };
 
 // signed frequency of index k on a length-2N axis, Nyquist index N -> 0
@@ -422,81 +423,109 @@ template <typename T> struct SpecIdx {
 // ---------------------------------------------------------------------------
 // k_fused: forward (pruned in) -> per output field: multiply, inverse
 // (pruned out). in: [N0][ncols]; output f at out + f*out_fs, [N0][ncols].
+// Persistent: workgroup b takes tiles b, b + gridDim.x, ... and issues the
+// next tile's loads (column data and kernel-spectrum values) before the
+// barrier-separated transforms of the current tile, so HBM traffic overlaps
+// the FFT arithmetic of the same CU.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused(const cplx<T>* __restrict__ in,
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_PP)) void k_fused(const cplx<T>* __restrict__ in,
                                                            cplx<T>* __restrict__ out,
                                                            FusedGeom<T> g,
                                                            const T* __restrict__ spec,
-                                                           const cplx<T>* __restrict__ tw) {
+                                                           const cplx<T>* __restrict__ tw,
+                                                           int ntiles) {
   using C = cplx<T>;
   using TL = Tile<T, P>;
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
-  __shared__ C lds[P * LP];
-  __shared__ C twl[P];
-  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
-  const ColIO& cio = fc.io;
-  stage_twiddles<C, P, NT>(twl, tw, tid);
-
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
-  typename S0::Regs g0;
-  S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
   using IS0 = Stage<T, P, NT, NL, LP, 1, 0>;
   using ISL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
-  // kernel spectrum at this thread's forward-output rows (natural order j + r*NB)
-  T sv[SL::NTASK][SL::R];
+  __shared__ C lds[2 * P * LP];
+  __shared__ C twl[P];
+  PingPong<C, P * LP> pp;
+  pp.base = lds;
+  pp.off = 0;
+  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  stage_twiddles<C, P, NT>(twl, tw, tid);
+
+  // loads of one tile: the stage-0 inputs and the kernel spectrum at this
+  // thread's forward-output rows (natural order j + r*NB)
+  auto load_tile = [&](const FusedCol<T>& fc, typename S0::Regs& g0, T (&sv)[SL::NTASK][SL::R]) {
+    const ColIO& cio = fc.io;
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
 #pragma unroll
-  for (int t = 0; t < SL::NTASK; ++t) {
-    if (!SL::active(t, q)) continue;
-    const int j = q + t * SL::NQ;
-    const SpecIdx<T> si(g, fc.colpart, j);
+    for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
+      const int j = q + t * SL::NQ;
+      const SpecIdx<T> si(g, fc.colpart, j);
 #pragma unroll
-    for (int r = 0; r < SL::R; ++r) sv[t][r] = spec[si.template at<SL::R, SL::NB>(j, r)];
-  }
-  S0::butterflies(g0, q);
-  S0::lds_out(g0, lds, l, q);
-  __syncthreads();
-  typename SL::Regs rh;  // forward spectrum times the kernel spectrum
-  middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
+      for (int r = 0; r < SL::R; ++r) sv[t][r] = spec[si.template at<SL::R, SL::NB>(j, r)];
+    }
+  };
+
+  FusedCol<T> fcn(g, (int64_t)tile * NL + l);
+  typename S0::Regs g0n;
+  T svn[SL::NTASK][SL::R];
+  load_tile(fcn, g0n, svn);
+
+  for (;;) {
+    const FusedCol<T> fc = fcn;
+    typename S0::Regs g0 = g0n;
+    T sv[SL::NTASK][SL::R];
 #pragma unroll
-  for (int t = 0; t < SL::NTASK; ++t)
+    for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
-    for (int r = 0; r < SL::R; ++r) {
-      rh.v[t][r].x *= sv[t][r];
-      rh.v[t][r].y *= sv[t][r];
+      for (int r = 0; r < SL::R; ++r) sv[t][r] = svn[t][r];
+    const int next = tile + (int)gridDim.x;
+    if (next < ntiles) {
+      fcn = FusedCol<T>(g, (int64_t)next * NL + l);
+      load_tile(fcn, g0n, svn);
     }
 
-  for (int fi = 0; fi < g.nf; ++fi) {
-    typename IS0::Regs v;
-    if (g.fields[fi] == 0) {
+    S0::butterflies(g0, q);
+    typename SL::Regs rh;  // forward spectrum times the kernel spectrum
+    transform_pp<T, P, NT, NL, LP, -1>(g0, rh, pp, twl, l, q);
 #pragma unroll
-      for (int t = 0; t < SL::NTASK; ++t)
+    for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
-        for (int r = 0; r < SL::R; ++r) v.v[t][r] = rh.v[t][r];
-    } else {
+      for (int r = 0; r < SL::R; ++r) {
+        rh.v[t][r].x *= sv[t][r];
+        rh.v[t][r].y *= sv[t][r];
+      }
+
+    for (int fi = 0; fi < g.nf; ++fi) {
+      typename IS0::Regs v;
+      if (g.fields[fi] == 0) {
 #pragma unroll
-      for (int t = 0; t < SL::NTASK; ++t) {
-        if (!SL::active(t, q)) continue;
-        const int j = q + t * SL::NQ;
+        for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
-        for (int r = 0; r < SL::R; ++r)
-          v.v[t][r] = deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks0, j, r));
+          for (int r = 0; r < SL::R; ++r) v.v[t][r] = rh.v[t][r];
+      } else {
+#pragma unroll
+        for (int t = 0; t < SL::NTASK; ++t) {
+          if (!SL::active(t, q)) continue;
+          const int j = q + t * SL::NQ;
+#pragma unroll
+          for (int r = 0; r < SL::R; ++r)
+            v.v[t][r] = deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks0, j, r));
+        }
+      }
+      IS0::butterflies(v, q);
+      typename ISL::Regs o;
+      transform_pp<T, P, NT, NL, LP, 1>(v, o, pp, twl, l, q);
+      if (fc.io.valid) {
+        C* __restrict__ dst = out + fi * g.out_fs;
+        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[fc.io.template off<ISL::NB>(j, r)] = val; });
       }
     }
-    IS0::butterflies(v, q);
-    __syncthreads();
-    IS0::lds_out(v, lds, l, q);
-    __syncthreads();
-    typename ISL::Regs o;
-    middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
-    if (cio.valid) {
-      C* __restrict__ dst = out + fi * g.out_fs;
-      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
-    }
+    if (next >= ntiles) break;
+    tile = next;
   }
 }
 
@@ -641,10 +670,24 @@ hipError_t launch_fused_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const F
   using TL = Tile<T, P>;
   const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
   if (bx == 0 || g.nf == 0) return hipSuccess;
-  if (adjoint)
+  if (adjoint) {
     hipLaunchKernelGGL((k_fused_adj<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, spec, tw);
-  else
-    hipLaunchKernelGGL((k_fused<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, spec, tw);
+  } else {
+    // one persistent workgroup per resident slot
+    static int slots = 0;
+    if (slots == 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fused<T, P>, TL::NT, 0) !=
+              hipSuccess)
+        return hipGetLastError();
+      slots = cus * (per_cu > 0 ? per_cu : 1);
+    }
+    const int grid = (int)(bx < slots ? bx : slots);
+    hipLaunchKernelGGL((k_fused<T, P>), dim3((unsigned)grid), dim3(TL::NT), 0, s, in, out, g, spec, tw,
+                       (int)bx);
+  }
   return hipGetLastError();
 }
 
