@@ -152,7 +152,19 @@ template <int S, typename C> struct Dft<8, S, C> {
 // ---------------------------------------------------------------------------
 // one Stockham stage of a workgroup-wide batched transform
 // ---------------------------------------------------------------------------
-template <typename T, int P, int NT, int NL, int LP, int SIGN, int S>
+// LDS layouts of a tile of NL lines: 0 = [position][line] with row pitch LP
+// (strided axes: adjacent lines are adjacent columns in HBM); 1 = [line][position]
+// with one pad slot every 8 positions and line pitch LP (contiguous axes,
+// one wavefront per line group; the pad keeps radix-8 scatters free of bank
+// conflicts).
+template <int LAYOUT, int LP>
+__device__ __forceinline__ int lds_index(int pos, int l) {
+  if constexpr (LAYOUT == 0) return pos * LP + l;
+  else return l * LP + pos + (pos >> 3);
+}
+template <int P> constexpr int line_pitch() { return P + P / 8; }
+
+template <typename T, int P, int NT, int NL, int LP, int SIGN, int S, int LAYOUT = 0>
 struct Stage {
   using C = cplx<T>;
   static constexpr int R = radix_at<SIGN>(P, S);
@@ -208,7 +220,7 @@ struct Stage {
       if (!active(t, q)) continue;
       const int j = q + t * NQ;
 #pragma unroll
-      for (int r = 0; r < R; ++r) g.v[t][r] = lds[in_pos(j, r) * LP + l];
+      for (int r = 0; r < R; ++r) g.v[t][r] = lds[lds_index<LAYOUT, LP>(in_pos(j, r), l)];
       if constexpr (NS > 1) {
         const int base = (j % NS) * (P / (NS * R));
 #pragma unroll
@@ -223,7 +235,7 @@ struct Stage {
       if (!active(t, q)) continue;
       const int j = q + t * NQ;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[out_pos(j, r) * LP + l] = g.v[t][r];
+      for (int r = 0; r < R; ++r) lds[lds_index<LAYOUT, LP>(out_pos(j, r), l)] = g.v[t][r];
     }
   }
 
@@ -272,25 +284,39 @@ template <int B, int E> struct StaticFor {
   }
 };
 
+// Ordering of LDS accesses among the lanes of one wavefront (the lines of a
+// wave-local tile are touched by that wave only).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE> __device__ __forceinline__ void tile_sync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
+
 // Runs stages [1, n_stages - 1) of a transform through the LDS tile. On entry
 // stage 0's outputs are in LDS (and a barrier has been passed); on exit the
-// last stage's twiddled-and-transformed results are in `last`.
-template <typename T, int P, int NT, int NL, int LP, int SIGN>
+// last stage's twiddled-and-transformed results are in `last`. WAVE: the
+// tile belongs to one wavefront, which orders its own LDS accesses.
+template <typename T, int P, int NT, int NL, int LP, int SIGN, int LAYOUT = 0, bool WAVE = false>
 __device__ __forceinline__ void middle_and_last(
-    typename Stage<T, P, NT, NL, LP, SIGN, n_stages(P) - 1>::Regs& last, cplx<T>* lds,
+    typename Stage<T, P, NT, NL, LP, SIGN, n_stages(P) - 1, LAYOUT>::Regs& last, cplx<T>* lds,
     const cplx<T>* tw, int l, int q) {
   constexpr int NSTG = n_stages(P);
   StaticFor<1, NSTG - 1>::run([&](auto sI) {
     constexpr int s = decltype(sI)::value;
-    using St = Stage<T, P, NT, NL, LP, SIGN, s>;
+    using St = Stage<T, P, NT, NL, LP, SIGN, s, LAYOUT>;
     typename St::Regs g;
     St::lds_in(g, lds, tw, l, q);
     St::butterflies(g, q);
-    __syncthreads();
+    tile_sync<WAVE>();
     St::lds_out(g, lds, l, q);
-    __syncthreads();
+    tile_sync<WAVE>();
   });
-  using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1>;
+  using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1, LAYOUT>;
   SL::lds_in(last, lds, tw, l, q);
   SL::butterflies(last, q);
 }

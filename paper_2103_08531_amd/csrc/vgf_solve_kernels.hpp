@@ -79,75 +79,100 @@ __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw,
 }
 
 // ---------------------------------------------------------------------------
+// Contiguous-axis passes (r2c / c2r): each wavefront owns whole line pairs.
+// NQ lanes share one pair (two real lines packed as one complex line), lanes
+// run along the line, so HBM accesses are contiguous per lane group and every
+// FFT exchange stays inside the wavefront (LDS tile per wave, wave-level
+// ordering only). Twiddles are staged once per workgroup.
+// ---------------------------------------------------------------------------
+template <int P> constexpr int wave_nq() {
+  int nq = 1;
+  while (nq * 2 <= P / 8 && nq * 2 <= 64) nq *= 2;
+  return nq;
+}
+template <typename T, int P> struct TileW {
+  static constexpr int NQ = wave_nq<P>();  // lanes per line pair
+  static constexpr int LPW = 64 / NQ;      // line pairs per wavefront
+  static constexpr int WPB = 4;            // wavefronts per workgroup
+  static constexpr int NT = 64 * WPB;
+  static constexpr int LP = line_pitch<P>();
+  static constexpr int PAIRS = LPW * WPB;  // line pairs per workgroup
+  static_assert(n_stages(P) >= 2, "transform needs at least two stages");
+};
+
+// ---------------------------------------------------------------------------
 // k_r2c: out = sum_t m_t(k) R2C(in_t), lines of N = P/2 reals -> N+1 complex
 // ---------------------------------------------------------------------------
 template <typename T, int P, int NTERM>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_T)) void k_r2c(R2CArgs<T> a,
-                                                         const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__((TileW<T, P>::NT)) void k_r2c(R2CArgs<T> a,
+                                                          const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  using TL = Tile<T, P>;
-  constexpr int NL = TL::NL, NT = TL::NT, LP = NL + 1, N = P / 2, H = N + 1;
+  using TW = TileW<T, P>;
+  constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2, H = N + 1;
   constexpr int NSTG = n_stages(P);
-  constexpr int NSLOT = (2 * NL * H + NT - 1) / NT;
-  __shared__ C lds[P * LP];
+  constexpr int NSLOT = (H + NQ - 1) / NQ;
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
+  __shared__ C tiles[TW::WPB * LPW * LP];
   __shared__ C twl[P];
-  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const int64_t line0 = (int64_t)blockIdx.x * (2 * NL);
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = lane / NQ, q = lane % NQ;
+  C* tile = tiles + w * LPW * LP;
+  const int64_t pair = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
+  const int64_t la = 2 * pair, lb = la + 1;
+  const bool va = la < a.nlines, vb = lb < a.nlines;
+  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
 
-  C acc[NSLOT];
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) acc[s] = C{T(0), T(0)};
-
+  C acc_a[NSLOT], acc_b[NSLOT];
 #pragma unroll
   for (int term = 0; term < NTERM; ++term) {
-    const T* __restrict__ in = a.in[term];
+    const T* __restrict__ xa = a.in[term] + (va ? la : 0) * N;
+    const T* __restrict__ xb = a.in[term] + (vb ? lb : 0) * N;
     const int code = a.d.code[term];
-    if (term > 0) __syncthreads();
-    for (int idx = tid; idx < 2 * NL * N; idx += NT) {
-      const int ll = idx / N, pos = idx - ll * N;
-      const int64_t line = line0 + ll;
-      const T val = line < a.nlines ? in[line * N + pos] : T(0);
-      reinterpret_cast<T*>(&lds[pos * LP + (ll >> 1)])[ll & 1] = val;
-    }
-    __syncthreads();
-    using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
     typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int j, int r) { return lds[S0::in_pos(j, r) * LP + l]; });
+    S0::template load_first<true>(g0, q, [&](int j, int r) {
+      const int pos = S0::in_pos(j, r);
+      return C{va ? xa[pos] : T(0), vb ? xb[pos] : T(0)};
+    });
     S0::butterflies(g0, q);
-    __syncthreads();
-    S0::lds_out(g0, lds, l, q);
-    __syncthreads();
-    using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
+    wave_sync();
+    S0::lds_out(g0, tile, l, q);
+    wave_sync();
     typename SL::Regs gl;
-    middle_and_last<T, P, NT, NL, LP, -1>(gl, lds, twl, l, q);
-    __syncthreads();
-    SL::lds_out(gl, lds, l, q);
-    __syncthreads();
+    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(gl, tile, twl, l, q);
+    wave_sync();
+    SL::lds_out(gl, tile, l, q);
+    wave_sync();
     // Z = X + iY  ->  X[k] = (Z[k] + conj Z[P-k]) / 2,  Y[k] = -i (Z[k] - conj Z[P-k]) / 2
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
-      const int idx = tid + s * NT;
-      if (idx >= 2 * NL * H) continue;
-      const int ll = idx / H, k = idx - ll * H;
-      const int c = ll >> 1;
-      const C z = lds[k * LP + c];
-      const C zm = lds[((P - k) % P) * LP + c];
-      C o;
-      if ((ll & 1) == 0) o = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-      else o = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
-      o = deriv(o, code, a.d.ks * (T)signed_freq_zn(k, N));
-      acc[s].x += o.x;
-      acc[s].y += o.y;
+      const int k = q + NQ * s;
+      if (k >= H) continue;
+      const C z = tile[lds_index<1, LP>(k, l)];
+      const C zm = tile[lds_index<1, LP>((P - k) % P, l)];
+      C xk = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+      C yk = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
+      if (code != 0) {
+        const T kk = a.d.ks * (T)(k < N ? k : 0);
+        xk = deriv(xk, code, kk);
+        yk = deriv(yk, code, kk);
+      }
+      if (term == 0) {
+        acc_a[s] = xk;
+        acc_b[s] = yk;
+      } else {
+        acc_a[s].x += xk.x; acc_a[s].y += xk.y;
+        acc_b[s].x += yk.x; acc_b[s].y += yk.y;
+      }
     }
   }
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    const int idx = tid + s * NT;
-    if (idx >= 2 * NL * H) continue;
-    const int ll = idx / H, k = idx - ll * H;
-    const int64_t line = line0 + ll;
-    if (line < a.nlines) a.out[line * a.hs + k] = acc[s];
+    const int k = q + NQ * s;
+    if (k >= H) continue;
+    if (va) a.out[la * a.hs + k] = acc_a[s];
+    if (vb) a.out[lb * a.hs + k] = acc_b[s];
   }
 }
 
@@ -155,74 +180,76 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_T)) void k_r2c(
 // k_c2r: out_o = first N reals of C2R(m_o(k) in), lines of N+1 complex
 // ---------------------------------------------------------------------------
 template <typename T, int P, int NOUT>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_T)) void k_c2r(C2RArgs<T> a,
-                                                         const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__((TileW<T, P>::NT)) void k_c2r(C2RArgs<T> a,
+                                                          const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  using TL = Tile<T, P>;
-  constexpr int NL = TL::NL, NT = TL::NT, LP = NL + 1, N = P / 2, H = N + 1;
+  using TW = TileW<T, P>;
+  constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2, H = N + 1;
   constexpr int NSTG = n_stages(P);
-  constexpr int NSLOT = (NL * H + NT - 1) / NT;
-  __shared__ C lds[P * LP];
+  constexpr int NSLOT = (H + NQ - 1) / NQ;
+  using S0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
+  using SL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  __shared__ C tiles[TW::WPB * LPW * LP];
   __shared__ C twl[P];
-  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  const int64_t line0 = (int64_t)blockIdx.x * (2 * NL);
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = lane / NQ, q = lane % NQ;
+  C* tile = tiles + w * LPW * LP;
+  const int64_t pair = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
+  const int64_t la = 2 * pair, lb = la + 1;
+  const bool va = la < a.nlines, vb = lb < a.nlines;
 
-  // this thread's (line pair, k) slots of the input
+  // this lane's k-slots of the two half-spectra
   C xs[NSLOT], ys[NSLOT];
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    const int idx = tid + s * NT;
+    const int k = q + NQ * s;
     xs[s] = ys[s] = C{T(0), T(0)};
-    if (idx >= NL * H) continue;
-    const int c = idx / H, k = idx - c * H;
-    const int64_t la = line0 + 2 * c, lb = la + 1;
-    if (la < a.nlines) xs[s] = a.in[la * a.hs + k];
-    if (lb < a.nlines) ys[s] = a.in[lb * a.hs + k];
+    if (k >= H) continue;
+    if (va) xs[s] = a.in[la * a.hs + k];
+    if (vb) ys[s] = a.in[lb * a.hs + k];
   }
+  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int code = a.d.code[o];
-    T* __restrict__ out = a.out[o];
-    if (o > 0) __syncthreads();
     // Z[k] = X[k] + i Y[k], Z[P-k] = conj X[k] + i conj Y[k]; the imaginary
     // parts of X, Y at k = 0 and k = N are dropped (real by symmetry).
+    wave_sync();
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
-      const int idx = tid + s * NT;
-      if (idx >= NL * H) continue;
-      const int c = idx / H, k = idx - c * H;
-      const T kk = a.d.ks * (T)signed_freq_zn(k, N);
-      const C X = deriv(xs[s], code, kk), Y = deriv(ys[s], code, kk);
+      const int k = q + NQ * s;
+      if (k >= H) continue;
+      C X = xs[s], Y = ys[s];
+      if (code != 0) {
+        const T kk = a.d.ks * (T)(k < N ? k : 0);
+        X = deriv(X, code, kk);
+        Y = deriv(Y, code, kk);
+      }
       if (k == 0 || k == N) {
-        lds[k * LP + c] = C{X.x, Y.x};
+        tile[lds_index<1, LP>(k, l)] = C{X.x, Y.x};
       } else {
-        lds[k * LP + c] = C{X.x - Y.y, X.y + Y.x};
-        lds[(P - k) * LP + c] = C{X.x + Y.y, Y.x - X.y};
+        tile[lds_index<1, LP>(k, l)] = C{X.x - Y.y, X.y + Y.x};
+        tile[lds_index<1, LP>(P - k, l)] = C{X.x + Y.y, Y.x - X.y};
       }
     }
-    __syncthreads();
-    using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
+    wave_sync();
     typename S0::Regs g0;
-    S0::template load_first<false>(g0, q, [&](int j, int r) { return lds[S0::in_pos(j, r) * LP + l]; });
+    S0::template load_first<false>(g0, q, [&](int j, int r) { return tile[lds_index<1, LP>(S0::in_pos(j, r), l)]; });
     S0::butterflies(g0, q);
-    __syncthreads();
-    S0::lds_out(g0, lds, l, q);
-    __syncthreads();
-    using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
+    wave_sync();
+    S0::lds_out(g0, tile, l, q);
+    wave_sync();
     typename SL::Regs gl;
-    middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
-    __syncthreads();
-    SL::template store_last<true>(gl, q, [&](int j, int r, C v) { lds[SL::out_pos(j, r) * LP + l] = v; });
-    __syncthreads();
-    for (int idx = tid; idx < 2 * NL * N; idx += NT) {
-      const int ll = idx / N, pos = idx - ll * N;
-      const int64_t line = line0 + ll;
-      if (line >= a.nlines) continue;
-      const C z = lds[pos * LP + (ll >> 1)];
-      out[line * N + pos] = (ll & 1) ? z.y : z.x;
-    }
+    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(gl, tile, twl, l, q);
+    T* __restrict__ oa = a.out[o] + (va ? la : 0) * N;
+    T* __restrict__ ob = a.out[o] + (vb ? lb : 0) * N;
+    SL::template store_last<true>(gl, q, [&](int j, int r, C v) {
+      const int pos = SL::out_pos(j, r);
+      if (va) oa[pos] = v.x;
+      if (vb) ob[pos] = v.y;
+    });
   }
 }
 
@@ -616,25 +643,27 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
 
 template <typename T, int P>
 hipError_t launch_r2c_p(const R2CArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
-  using TL = Tile<T, P>;
-  const int64_t blocks = (a.nlines + 2 * TL::NL - 1) / (2 * TL::NL);
+  using TW = TileW<T, P>;
+  const int64_t pairs = (a.nlines + 1) / 2;
+  const int64_t blocks = (pairs + TW::PAIRS - 1) / TW::PAIRS;
   if (blocks == 0 || a.d.n == 0) return hipSuccess;
   if (a.d.n == 2)
-    hipLaunchKernelGGL((k_r2c<T, P, 2>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_r2c<T, P, 2>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, a, tw);
   else
-    hipLaunchKernelGGL((k_r2c<T, P, 1>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_r2c<T, P, 1>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t launch_c2r_p(const C2RArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
-  using TL = Tile<T, P>;
-  const int64_t blocks = (a.nlines + 2 * TL::NL - 1) / (2 * TL::NL);
+  using TW = TileW<T, P>;
+  const int64_t pairs = (a.nlines + 1) / 2;
+  const int64_t blocks = (pairs + TW::PAIRS - 1) / TW::PAIRS;
   if (blocks == 0 || a.d.n == 0) return hipSuccess;
   if (a.d.n == 2)
-    hipLaunchKernelGGL((k_c2r<T, P, 2>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_c2r<T, P, 2>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, a, tw);
   else
-    hipLaunchKernelGGL((k_c2r<T, P, 1>), dim3((unsigned)blocks), dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_c2r<T, P, 1>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 
