@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the solves, copy 256 MiB device-to-device once (a plain copy "
+                         "kernel of known size, to scale HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -208,6 +211,14 @@ def main():
         "accuracy": {"f32_vs_f64_gpu": {"phi": rel_l2(f32["out"]["phi"], f64["out"]["phi"]),
                                         "E": rel_l2(f32["out"]["E"], f64["out"]["E"])}},
     }
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         base, acc = cpu_baseline(ch, rho64, f64["L"], results)
         line["cpu_baseline"] = base

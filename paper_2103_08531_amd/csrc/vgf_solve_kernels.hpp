@@ -41,9 +41,10 @@ namespace vgf {
 
 // Tile shape for length P: NL lines (contiguous columns) per workgroup, 16
 // complex values per thread, LDS tile <= 64 KiB.
-template <typename T, int P> struct Tile {
+template <typename T, int P, int NL_FORCE = 0> struct Tile {
   static constexpr int CB = (int)sizeof(cplx<T>);
   static constexpr int pick_nl() {
+    if (NL_FORCE > 0) return NL_FORCE;
     int nl = sizeof(T) == 4 ? 16 : 8;
     while (nl > 1 && P * nl * CB > 65536) nl /= 2;
     return nl;
@@ -396,6 +397,17 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_in
   }
 }
 
+// Tile of the fused axis-0 pass (columns per workgroup may differ from the
+// other strided passes: it holds two LDS tiles and more registers).
+#ifndef VGF_FUSED_NL32
+#define VGF_FUSED_NL32 0
+#endif
+#ifndef VGF_FUSED_NL64
+#define VGF_FUSED_NL64 0
+#endif
+template <typename T, int P>
+using TileF = Tile<T, P, (sizeof(T) == 4 ? VGF_FUSED_NL32 : VGF_FUSED_NL64)>;
+
 // Kernel-spectrum addressing for the axis-0 lines: column c of the inner
 // plane (3D: (k1, k2) of [P1][H2]; 2D: k1 of [H1]) reads the octant at
 // [f0][f1][k2] with f_a = min(k_a, 2N_a - k_a). Row j + r*NB folds for
@@ -456,14 +468,14 @@ template <typename T> struct SpecIdx {
 // the FFT arithmetic of the same CU.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_PP)) void k_fused(const cplx<T>* __restrict__ in,
+__global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_fused(const cplx<T>* __restrict__ in,
                                                            cplx<T>* __restrict__ out,
                                                            FusedGeom<T> g,
                                                            const T* __restrict__ spec,
                                                            const cplx<T>* __restrict__ tw,
                                                            int ntiles) {
   using C = cplx<T>;
-  using TL = Tile<T, P>;
+  using TL = TileF<T, P>;
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
@@ -477,8 +489,35 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_PP)) void k_fus
   pp.base = lds;
   pp.off = 0;
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  int tile = blockIdx.x;
-  if (tile >= ntiles) return;
+  // Tile order. Workgroups are dealt round-robin over the 8 XCDs (separate
+  // L2s), so XCD x = b % 8 walks its own contiguous chunk of tiles. In 3D the
+  // rows k1 of the [P1][hs] plane are visited as 0, N1, 1, P1-1, 2, P1-2, ...:
+  // rows k1 and P1-k1 read the same kernel-spectrum octant rows, and
+  // neighbouring tiles share 128-byte lines of it, so both reuses land in the
+  // same L2 shortly after the first touch.
+  const bool pairs = g.dim == 3 && g.hs % NL == 0;
+  const int tiles_per_row = pairs ? g.hs / NL : ntiles;
+  const int nrows = ntiles / tiles_per_row;
+  const bool xcd = (gridDim.x % 8) == 0 && gridDim.x >= 8;
+  const int per_xcd = xcd ? (int)gridDim.x / 8 : (int)gridDim.x;
+  const int chunk = xcd ? (ntiles + 7) / 8 : ntiles;
+  const int chunk0 = xcd ? (int)(blockIdx.x % 8) * chunk : 0;
+  const int chunk1 = chunk0 + chunk < ntiles ? chunk0 + chunk : ntiles;
+  int u = chunk0 + (xcd ? (int)blockIdx.x / 8 : (int)blockIdx.x);
+  if (u >= chunk1) return;
+  auto tile_of = [&](int uu) -> int {
+    if (!pairs) return uu;
+    const int row = uu / tiles_per_row, blk = uu - row * tiles_per_row;
+    int k1;
+    if (row == 0) k1 = 0;
+    else if (row == 1) k1 = nrows / 2;
+    else {
+      const int m = (row - 2) / 2 + 1;
+      k1 = (row % 2 == 0) ? m : nrows - m;
+    }
+    return k1 * tiles_per_row + blk;
+  };
+  int tile = tile_of(u);
   stage_twiddles<C, P, NT>(twl, tw, tid);
 
   // loads of one tile: the stage-0 inputs and the kernel spectrum at this
@@ -509,8 +548,10 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_PP)) void k_fus
     for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) sv[t][r] = svn[t][r];
-    const int next = tile + (int)gridDim.x;
-    if (next < ntiles) {
+    const int unext = u + per_xcd;
+    const bool more = unext < chunk1;
+    const int next = more ? tile_of(unext) : 0;
+    if (more) {
       fcn = FusedCol<T>(g, (int64_t)next * NL + l);
       load_tile(fcn, g0n, svn);
     }
@@ -551,7 +592,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW_PP)) void k_fus
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[fc.io.template off<ISL::NB>(j, r)] = val; });
       }
     }
-    if (next >= ntiles) break;
+    if (!more) break;
+    u = unext;
     tile = next;
   }
 }
@@ -696,12 +738,16 @@ hipError_t launch_c2c_inv_p(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream
 template <typename T, int P>
 hipError_t launch_fused_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
                           const T* spec, const cplx<T>* tw, hipStream_t s) {
-  using TL = Tile<T, P>;
-  const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
-  if (bx == 0 || g.nf == 0) return hipSuccess;
+  if (g.nf == 0) return hipSuccess;
   if (adjoint) {
+    using TL = Tile<T, P>;
+    const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
+    if (bx == 0) return hipSuccess;
     hipLaunchKernelGGL((k_fused_adj<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, spec, tw);
   } else {
+    using TL = TileF<T, P>;
+    const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
+    if (bx == 0) return hipSuccess;
     // one persistent workgroup per resident slot
     static int slots = 0;
     if (slots == 0) {
