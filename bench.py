@@ -24,8 +24,21 @@ Printed JSON line (one, rank 0):
   cpu_baseline the FP64 CPU oracle's 2N FFT path on the same input, timed on
                the host cores for one solve (its values also give the stated
                rel-L2 of the GPU results)
+
+roofline.traffic is the dominant kernel's HBM bytes per launch from two
+rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
+same counter reads for a plain 256 MiB device-to-device copy in the same run
+(--copy-calibration). `--digest-counters FETCH_CSV FETCH_OUT WRITE_CSV WRITE_OUT` turns the two
+counter files (with the two profiled runs' outputs, which must carry the
+current source hash) into profiles/k_fused_beam_3d_256_traffic.{json,md},
+stamped with a hash of the library sources; a bench run reports the traffic
+only while the sources still hash the same, else null. `--digest-trace STATS_CSV` turns a
+`rocprofv3 --kernel-trace --stats` summary into
+profiles/vgf_solve_beam_3d_256_kernel_trace.md.
 """
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +52,194 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "3D VGF solves/s at N=256^3 FP32 vs FP64 + HBM GB/s, at stated rel-L2 error"
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_JSON = os.path.join(PROFILES, "k_fused_beam_3d_256_traffic.json")
+TRACE_MD = os.path.join(PROFILES, "vgf_solve_beam_3d_256_kernel_trace.md")
+CALIB_BYTES = 256 * 1024 * 1024
+# pass name -> kernel name prefix in rocprofv3 output (256^3: P = 512)
+PASS_KERNELS = {"r2c": "k_r2c", "c2c_fwd": "k_c2c_fwd", "fused_axis0": "k_fused<",
+                "c2c_inv": "k_c2c_inv", "c2r": "k_c2r"}
+
+
+def kernel_source_hash():
+    """sha256 over the library's sources and build flags: counter data taken
+    from other sources no longer describe the kernels that run."""
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_2103_08531_amd")
+    csrc = os.path.join(pkg, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(pkg, "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def _short_name(kname):
+    name = kname.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0]
+    return name.replace("vgf::", "")
+
+
+def _read_counter(path, counter):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def _bench_line(path):
+    """The JSON line a bench run printed (its output may hold other lines)."""
+    for ln in reversed(open(path).read().splitlines()):
+        if ln.startswith("{"):
+            return json.loads(ln)
+    raise SystemExit("no bench output line in %s" % path)
+
+
+def digest_counters(fetch_csv, fetch_out, write_csv, write_out):
+    """Per-kernel HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by the factor that maps the counter's reading for
+    the calibration copy (the last copyBuffer dispatch of the run) to its
+    known 256 MiB. Both profiled bench runs must have run these sources."""
+    src = kernel_source_hash()
+    for path in (fetch_out, write_out):
+        if _bench_line(path).get("source_hash") != src:
+            raise SystemExit("%s was measured on other sources than these" % path)
+    out = {"source_hash": src, "calibration_bytes": CALIB_BYTES, "kernels": {}}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _read_counter(path, counter)
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not copies:
+            raise SystemExit("no calibration copy in %s (run bench.py with --copy-calibration)" % path)
+        kib = float(copies[-1]["Counter_Value"])
+        factor = CALIB_BYTES / 1024.0 / kib
+        out[counter.lower() + "_calibration"] = {"copy_kib": kib, "factor": factor}
+        for r in rows:
+            if "vgf::" not in r["Kernel_Name"]:
+                continue
+            name = _short_name(r["Kernel_Name"])
+            per.setdefault(name, {}).setdefault(counter, []).append(float(r["Counter_Value"]))
+    ff = out["fetch_size_calibration"]["factor"]
+    fw = out["write_size_calibration"]["factor"]
+    for name, d in per.items():
+        if "FETCH_SIZE" not in d or "WRITE_SIZE" not in d:
+            continue
+        fk = sum(d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
+        wk = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
+        out["kernels"][name] = {"dispatches": len(d["FETCH_SIZE"]), "fetch_kib": fk, "write_kib": wk,
+                                "read_bytes": fk * 1024 * ff, "write_bytes": wk * 1024 * fw,
+                                "traffic_bytes": fk * 1024 * ff + wk * 1024 * fw}
+    return out
+
+
+def load_traffic():
+    """The committed counter digest, if it still describes these sources."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return d if d.get("source_hash") == kernel_source_hash() else None
+
+
+def traffic_of(traffic, pass_name, prec):
+    """Scaled HBM bytes per launch of a pass's kernel (256^3, P = 512)."""
+    if traffic is None:
+        return None
+    t = "float" if prec == "f32" else "double"
+    hits = [v for k, v in traffic["kernels"].items()
+            if k.startswith(PASS_KERNELS[pass_name]) and ("<%s, 512" % t) in k]
+    if len(hits) != 1:
+        return None
+    return hits[0]["traffic_bytes"]
+
+
+def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
+    d = digest_counters(fetch_csv, fetch_out, write_csv, write_out)
+    d["command"] = command
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+        f.write("\n")
+    kb = {"float": kernel_bytes((256, 256, 256), 4), "double": kernel_bytes((256, 256, 256), 8)}
+    md = [ "# HBM traffic per launch: VGF solve kernels, beam_3d_256 (3D 256^3, phi+E), FP32 and FP64", "",
+          "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 run each, averaged over "
+          "the dispatches of each kernel. Each is scaled by the factor that maps its reading for a plain "
+          "256 MiB device-to-device copy in the same run to 256 MiB (FETCH_SIZE counts each 128-byte read "
+          "request as 64 bytes, so its factor is about 2; WRITE_SIZE reads true).", "",
+          "Commands:", "", "```", command, "```", "",
+          "| counter | copy reads (KiB) | factor |", "|---|---|---|",
+          "| FETCH_SIZE | %.1f | %.4f |" % (d["fetch_size_calibration"]["copy_kib"],
+                                         d["fetch_size_calibration"]["factor"]),
+          "| WRITE_SIZE | %.1f | %.4f |" % (d["write_size_calibration"]["copy_kib"],
+                                         d["write_size_calibration"]["factor"]), "",
+          "| kernel | launches | read MB | write MB | traffic MB | algorithmic MB | traffic / algorithmic |",
+          "|---|---|---|---|---|---|---|"]
+    for name in sorted(d["kernels"]):
+        v = d["kernels"][name]
+        alg = None
+        for pname, prefix in PASS_KERNELS.items():
+            for t in ("float", "double"):
+                if name.startswith(prefix) and ("<%s, 512" % t) in name:
+                    alg = kb[t][pname]
+        # c2c_inv and c2r run as several launches (fields split between them): see the per-pass table
+        ratio = "%.3f" % (v["traffic_bytes"] / alg) if alg and not name.startswith(("k_c2c_inv", "k_c2r")) else "-"
+        md.append("| %s | %d | %.1f | %.1f | %.1f | %s | %s |" % (
+            name, v["dispatches"], v["read_bytes"] / 1e6, v["write_bytes"] / 1e6, v["traffic_bytes"] / 1e6,
+            "%.1f" % (alg / 1e6) if alg and ratio != "-" else "-", ratio))
+    md += ["", "Per solve and pass (launches of a pass summed; solves = launches of k_fused):", "",
+           "| pass | precision | traffic MB | algorithmic MB | traffic / algorithmic |", "|---|---|---|---|---|"]
+    for t, prec in (("float", "FP32"), ("double", "FP64")):
+        ks = {k: v for k, v in d["kernels"].items() if ("<%s, 512" % t) in k}
+        nsolve = max([v["dispatches"] for k, v in ks.items() if k.startswith("k_fused<")] or [0])
+        if not nsolve:
+            continue
+        for pname, prefix in PASS_KERNELS.items():
+            tot = sum(v["traffic_bytes"] * v["dispatches"] for k, v in ks.items() if k.startswith(prefix)) / nsolve
+            md.append("| %s | %s | %.1f | %.1f | %.3f |" % (pname, prec, tot / 1e6, kb[t][pname] / 1e6,
+                                                           tot / kb[t][pname]))
+    md += ["", "Source hash (sha256 of the library sources and build flags the counters describe): `%s`"
+           % d["source_hash"], ""]
+    with open(TRAFFIC_JSON[:-5] + ".md", "w") as f:
+        f.write("\n".join(md))
+    print(TRAFFIC_JSON)
+
+
+def write_trace_profile(trace_csv, bench_json, command):
+    """Per-kernel durations from a rocprofv3 --kernel-trace run, next to the
+    per-pass means the same bench run measured live with HIP events."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    agg = {}
+    for r in rows:
+        name = _short_name(r["Kernel_Name"])
+        if name.startswith("at::") or "elementwise" in name:
+            name = "torch " + name[:40]
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        a = agg.setdefault(name, {"d": [], "wg": r["Workgroup_Size_X"], "grid": r["Grid_Size_X"],
+                                  "lds": r["LDS_Block_Size"], "vgpr": r["VGPR_Count"],
+                                  "agpr": r["Accum_VGPR_Count"], "scratch": r["Scratch_Size"]})
+        a["d"].append(dur)
+    md = ["# Kernel trace: VGF solve, beam_3d_256 (3D 256^3, phi+E), FP32 and FP64", "",
+          "rocprofv3 kernel trace of one bench run (plan precompute, warm-up and timed solves of both "
+          "precisions). Durations in microseconds.", "", "Command:", "", "```", command, "```", "",
+          "| kernel | calls | mean us | min us | max us | total ms | grid | wg | LDS B | VGPR | AGPR | scratch |",
+          "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for name, a in sorted(agg.items(), key=lambda kv: -sum(kv[1]["d"])):
+        d = a["d"]
+        md.append("| %s | %d | %.1f | %.1f | %.1f | %.3f | %s | %s | %s | %s | %s | %s |" % (
+            name, len(d), sum(d) / len(d), min(d), max(d), sum(d) / 1e3, a["grid"], a["wg"], a["lds"],
+            a["vgpr"], a["agpr"], a["scratch"]))
+    if bench_json:
+        line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        md += ["", "Per-pass mean durations the same run measured live (HIP events on the solve stream, "
+               "timed solves only), in microseconds:", "",
+               "| pass | FP32 | FP64 |", "|---|---|---|"]
+        for k in line["passes"]["ms_f32"]:
+            md.append("| %s | %.1f | %.1f |" % (k, 1e3 * line["passes"]["ms_f32"][k],
+                                               1e3 * line["passes"]["ms_f64"][k]))
+    md.append("")
+    with open(TRACE_MD, "w") as f:
+        f.write("\n".join(md))
+    print(TRACE_MD)
 
 
 def pass_model_bytes(n, prec_bytes, nf=4):
@@ -141,7 +342,19 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the solves, copy 256 MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
+    ap.add_argument("--digest-counters", nargs=4, metavar=("FETCH_CSV", "FETCH_OUT", "WRITE_CSV", "WRITE_OUT"),
+                    help="write the traffic profile from two rocprofv3 counter_collection.csv files and "
+                         "the outputs of the two profiled bench runs")
+    ap.add_argument("--digest-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
+                    help="write the kernel-trace profile from a rocprofv3 kernel_trace.csv file")
+    ap.add_argument("--command", default="", help="the profiling command, recorded in the profile")
     args = ap.parse_args()
+    if args.digest_counters:
+        write_traffic_profile(*args.digest_counters, command=args.command)
+        return
+    if args.digest_trace:
+        write_trace_profile(args.digest_trace[0], args.digest_trace[1], args.command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the solve path runs on a single MI355X "
@@ -173,6 +386,9 @@ def main():
     achieved = kb32[dom] / (dom_ms * 1e-3) / 1e9
     dom64 = max(f64["passes"], key=lambda k: f64["passes"][k])
     ach64 = kb64[dom64] / (f64["passes"][dom64] * 1e-3) / 1e9
+    traffic = load_traffic()
+    tr32 = traffic_of(traffic, dom, "f32")
+    tr64 = traffic_of(traffic, dom64, "f64")
 
     line = {
         "metric": METRIC,
@@ -187,6 +403,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "source_hash": kernel_source_hash(),
         "config": {"workload": "beam_3d_256", "grid": list(ch.n), "domain": "[-1,1]^3",
                    "method": "vgf", "outputs": "phi+E", "sigma": [0.05, 0.05, 0.3],
                    "seed": args.seed, "L": f32["L"], "parallelism": "single GPU"},
@@ -194,11 +411,12 @@ def main():
                  "dtype": "f64"},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": tr32,
+                     "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": kb32[dom], "mean_launch_ms": dom_ms,
                      "fp64": {"kernel": dom64, "achieved": ach64, "mean_launch_ms": f64["passes"][dom64],
                               "algorithmic_bytes_per_launch": kb64[dom64],
-                              "frac": ach64 / HBM_PEAK_GBS}},
+                              "frac": ach64 / HBM_PEAK_GBS, "traffic": tr64}},
         "pass_model": {"bytes_per_solve_f32": pm32, "bytes_per_solve_f64": pm64,
                        "frac_f32": pm32 / (f32["wall_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "frac_f64": pm64 / (f64["wall_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
