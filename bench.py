@@ -24,6 +24,9 @@ Printed JSON line (one, rank 0):
   cpu_baseline the FP64 CPU oracle's 2N FFT path on the same input, timed on
                the host cores for one solve (its values also give the stated
                rel-L2 of the GPU results)
+  batch        batch_3d_mixed (64 FP32 grids of uneven N): one solve per
+               entry vs one launch per pass and grid size vs the same as one
+               replayed hipGraph, in ms per batch and solves/s
 
 roofline.traffic is the dominant kernel's HBM bytes per launch from two
 rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
@@ -311,6 +314,65 @@ def run_precision(vgf, torch, ch, rho64, precision, steps, warmup):
             "out": out, "L": L}
 
 
+def run_batch(vgf, torch, workloads, steps, warmup, seed):
+    """batch_3d_mixed: 64 FP32 right-hand sides of uneven N in
+    {32, 48, 64, 96, 128}, phi + E, three ways on the same plans and buffers:
+    one vgf_solve per entry (its passes launched one entry at a time), one
+    launch per pass and per grid size (vgf_batch, direct launches), and the
+    same launches replayed as one captured hipGraph."""
+    charges = workloads.batch_3d_mixed(seed=seed, count=64)
+    plans = {}
+    for ch in charges:
+        if ch.n not in plans:
+            plans[ch.n] = vgf.Plan(ch.n, ch.h, method="vgf", precision="f32")
+    pl = [plans[ch.n] for ch in charges]
+    rhos = [torch.from_numpy(ch.rho()).to("cuda", torch.float32) for ch in charges]
+    phis = [torch.empty(ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    Es = [torch.empty((3,) + ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    grouped = vgf.Batch(pl, graph=False)
+    graphed = vgf.Batch(pl, graph=True)
+
+    def single():
+        for p, r, ph, E in zip(pl, rhos, phis, Es):
+            p.solve(r, ph, E)
+
+    runs = {"single": single, "grouped": lambda: grouped.solve(rhos, phis, Es),
+            "graph": lambda: graphed.solve(rhos, phis, Es)}
+    out = {}
+    for name, fn in runs.items():
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        out[name] = {"ms_per_batch": wall, "event_ms_per_batch": e0.elapsed_time(e1) / steps,
+                     "solves_per_s": len(charges) * 1e3 / wall}
+    moved = sum(sum(kernel_bytes(ch.n, 4).values()) for ch in charges)
+    sizes = {}
+    for ch in charges:
+        sizes[str(ch.n[0])] = sizes.get(str(ch.n[0]), 0) + 1
+    res = {"workload": "batch_3d_mixed", "entries": len(charges), "precision": "f32",
+           "outputs": "phi+E", "sizes": sizes, "groups": graphed.groups, "modes": out,
+           "moved_bytes_per_batch": moved,
+           "graph_gbs": moved / (out["graph"]["ms_per_batch"] * 1e-3) / 1e9,
+           "speedup_graph_vs_single": out["single"]["ms_per_batch"] / out["graph"]["ms_per_batch"]}
+    grouped.close()
+    graphed.close()
+    for p in plans.values():
+        p.close()
+    del rhos, phis, Es
+    torch.cuda.empty_cache()
+    return res
+
+
 def rel_l2(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
 
@@ -339,6 +401,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch_3d_mixed comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the solves, copy 256 MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -373,6 +436,12 @@ def main():
         print("[bench] %s: %.3f ms/solve (events %.3f), passes %s" % (
             prec, results[prec]["wall_ms"], results[prec]["event_ms"],
             {k: round(v, 4) for k, v in results[prec]["passes"].items()}), file=sys.stderr, flush=True)
+
+    batch = None
+    if not args.no_batch:
+        batch = run_batch(vgf, torch, workloads, args.steps, args.warmup, args.seed)
+        print("[bench] batch_3d_mixed: %s" % {k: round(v["ms_per_batch"], 3) for k, v in batch["modes"].items()},
+              file=sys.stderr, flush=True)
 
     f32 = results["f32"]
     f64 = results["f64"]
@@ -429,6 +498,7 @@ def main():
         "accuracy": {"f32_vs_f64_gpu": {"phi": rel_l2(f32["out"]["phi"], f64["out"]["phi"]),
                                         "E": rel_l2(f32["out"]["E"], f64["out"]["E"])}},
     }
+    line["batch"] = batch
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

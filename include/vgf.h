@@ -102,13 +102,67 @@ vgf_status vgf_solve(vgf_plan plan, const void* rho, void* phi, void* E, hipStre
 vgf_status vgf_solve_adjoint(vgf_plan plan, const void* g_phi, const void* g_E, void* g_rho,
                              hipStream_t stream);
 
-/* Many independent solves, possibly on different plans (grids), enqueued as
- * one unit: rho[i], phi[i], E[i] follow vgf_solve for plans[i] (phi and E
- * arrays may be NULL, or hold NULL entries). The same plan may appear more
- * than once: its solves are then serialised on its workspace. Enqueued on
- * `stream`; on the first invalid entry nothing is enqueued. */
+/* Many independent solves, possibly on different plans (grids), enqueued one
+ * after another, each exactly as vgf_solve: rho[i], phi[i], E[i] follow
+ * vgf_solve for plans[i] (phi and E arrays may be NULL, or hold NULL
+ * entries). The same plan may appear more than once: its solves are then
+ * serialised on its workspace. Enqueued on `stream`; on the first invalid
+ * entry nothing is enqueued. (vgf_batch_* below runs the same solves with one
+ * launch per pass and per grid, and as one captured graph.) */
 vgf_status vgf_solve_batched(const vgf_plan* plans, int count, const void* const* rho,
                              void* const* phi, void* const* E, hipStream_t stream);
+
+/* ---- Batches: one precompute per grid, then many right-hand sides per call
+ * (Sec. II: the kernel spectrum is computed once per grid and reused for
+ * every density; Eq. 3 is applied to each right-hand side independently). ----
+ *
+ * A batch fixes, at creation, the plan of each of its `count` entries;
+ * entries may use different plans (grids of uneven size, either precision).
+ * Entries sharing a plan handle form a group: every pass of a group is one
+ * launch over all of its entries, each entry with its own workspace (owned
+ * by the batch), so the group's entries run concurrently. Groups are
+ * independent. With VGF_BATCH_GRAPH the first vgf_batch_solve (and any
+ * later one that asks for a different set of outputs) captures all launches
+ * into one hipGraph, the groups as parallel branches, and every solve
+ * replays it with one graph launch on `stream`.
+ *
+ * The plans must outlive the batch. A batch, like a plan, serves one stream at
+ * a time (its workspaces are shared by its solves); batches do not use the
+ * plans' own workspaces, so plans stay usable for vgf_solve meanwhile on the
+ * same stream. Memory: vgf_batch_workspace_bytes. */
+typedef struct vgf_batch_s* vgf_batch;
+enum { VGF_BATCH_GRAPH = 1u };
+
+/* plans[0..count): the plan of each entry (non-NULL, count >= 1). flags: 0 or
+ * VGF_BATCH_GRAPH. Allocates the group workspaces (VGF_ERR_OUT_OF_MEMORY
+ * beyond VGF_MAX_WORKSPACE). Enqueues nothing. */
+vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, unsigned flags);
+
+/* Solves every entry i: rho[i] -> phi[i], E[i], with the layout, dtype and
+ * output rules of vgf_solve for the entry's plan. phi (or E) is either NULL,
+ * meaning no entry gets that output, or holds a non-NULL buffer for every
+ * entry (VGF_ERR_INVALID_ARG otherwise); at least one of them is non-NULL.
+ * Pointers may differ from call to call: the batch refreshes its device
+ * pointer tables on `stream` (a small kernel, no host staging) before the
+ * passes when they change. Stream-ordered and asynchronous; nothing is
+ * enqueued when an argument is invalid. Results equal vgf_solve's bit for bit
+ * (same kernels, same arithmetic order). */
+vgf_status vgf_batch_solve(vgf_batch batch, const void* const* rho, void* const* phi, void* const* E,
+                           hipStream_t stream);
+
+/* Device bytes held by the batch (group workspaces and pointer tables). */
+vgf_status vgf_batch_workspace_bytes(vgf_batch batch, size_t* bytes);
+
+/* Number of groups (distinct plans, split further when a group would exceed
+ * 65535 / n0 entries); 0 for NULL. */
+int vgf_batch_groups(vgf_batch batch);
+
+/* The hipError_t behind the batch's last VGF_ERR_HIP. */
+int vgf_batch_hip_error(vgf_batch batch);
+
+/* Waits for nothing: destroy only after the batch's work has completed.
+ * NULL is a no-op. */
+void vgf_batch_destroy(vgf_batch batch);
 
 /* The truncation radius the plan uses (0 for HE). */
 vgf_status vgf_plan_get_L(vgf_plan plan, double* L);

@@ -51,6 +51,7 @@ struct vgf_plan_s {
   void* tw[3] = {nullptr, nullptr, nullptr};  // per-axis twiddles exp(-2 pi i e / P_a)
   void* ws = nullptr;            // solve workspace
   size_t off_x1 = 0, off_x2 = 0, off_y = 0, off_z = 0;
+  size_t ws_bytes = 0;           // solve workspace (a multiple of 256 bytes)
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
 
@@ -242,8 +243,8 @@ struct Marks {
   hipStream_t s;
   hipEvent_t* ev = nullptr;
   int n = 0;
-  Marks(vgf_plan p_, hipStream_t s_) : p(p_), s(s_) {
-    if (p->profiling && p->prof_used < p->prof_cap)
+  Marks(vgf_plan p_, hipStream_t s_, bool on = true) : p(p_), s(s_) {
+    if (on && p->profiling && p->prof_used < p->prof_cap)
       ev = &p->prof_events[(size_t)p->prof_used++ * kMaxMarks];
   }
   void mark() {
@@ -307,91 +308,142 @@ template <typename T> vgf::Deriv<T> deriv2(vgf_plan p, int axis, int code0, int 
     if (e_ != hipSuccess) return hip_status(p, e_);    \
   } while (0)
 
+// The arrays of the entries (right-hand sides of one plan) that one launch
+// of each pass covers. One entry: direct pointers and the plan workspace.
+// Several: device tables of per-entry base pointers (rho, phi, E) and
+// workspaces es elements apart.
+template <typename T> struct Entries {
+  int count = 1;
+  char* ws = nullptr;
+  int64_t es = 0;  // cplx<T> elements between the workspaces of two entries
+  const T* rho = nullptr;
+  T* phi = nullptr;
+  T* E = nullptr;
+  const T* const* rho_tab = nullptr;
+  T* const* phi_tab = nullptr;
+  T* const* E_tab = nullptr;
+  bool want_phi = false, want_E = false;
+};
+
+// output o of a c2r launch: phi (field < 0) or E_field
+template <typename T>
+void c2r_out(vgf::C2RArgs<T>& ca, int o, const Entries<T>& en, int field, int64_t vol) {
+  if (!en.phi_tab && !en.E_tab) {
+    ca.out[o] = field < 0 ? en.phi : en.E + field * vol;
+  } else {
+    ca.out[o] = nullptr;
+    ca.out_tab[o] = field < 0 ? en.phi_tab : en.E_tab;
+    ca.out_off[o] = field < 0 ? 0 : field * vol;
+  }
+}
+
 // Forward solve. Each pass applies the derivative factor of its own axis:
 // the axis-0 pass yields the spectra of phi (Yp) and E_0 (Y0); the last
 // two axes derive E_1 and E_2 from phi's spectrum as they invert.
 template <typename T>
-vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
+vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks) {
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
-  Bufs<T> b = bufs<T>(p);
+  const bool want_phi = en.want_phi, want_E = en.want_E;
+  char* base = en.ws;
+  Bufs<T> b{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2), (cplx<T>*)(base + p->off_y),
+            (cplx<T>*)(base + p->off_z)};
   const T* spec = (const T*)p->spec;
   auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
   vgf::FusedGeom<T> g = fused_geom<T>(p);
   g.nf = 0;
   g.fields[g.nf++] = 0;
-  if (E) g.fields[g.nf++] = 1;
-  Marks mk(p, s);
+  if (want_E) g.fields[g.nf++] = 1;
+  g.nentry = en.count;
+  g.in_es = g.out_es = en.es;
+  Marks mk(p, s, marks);
   mk.mark();
+  const int64_t lpe = d == 3 ? N0 * N1 : N0;  // contiguous lines per entry
+  vgf::R2CArgs<T> ra{};
+  ra.nlines = lpe * en.count;
+  ra.lpe = lpe;
+  ra.hs = Hs;
+  ra.out = b.x1;
+  ra.out_es = en.es;
+  ra.d = deriv1<T>(p, d - 1, 0);
+  if (en.rho_tab) ra.in_tab[0] = en.rho_tab;
+  else ra.in[0] = en.rho;
+  // c2r launches: one complex input, up to two outputs
+  auto c2r = [&](const cplx<T>* in, int f0, int code0, int f1, int code1) -> hipError_t {
+    vgf::C2RArgs<T> ca{};
+    ca.in = in;
+    ca.in_es = en.es;
+    ca.nlines = lpe * en.count;
+    ca.lpe = lpe;
+    ca.hs = Hs;
+    ca.d = f1 == -2 ? deriv1<T>(p, d - 1, code0) : deriv2<T>(p, d - 1, code0, code1);
+    c2r_out(ca, 0, en, f0, vol);
+    if (f1 != -2) c2r_out(ca, 1, en, f1, vol);
+    return vgf::launch_c2r<T>((int)p->P[d - 1], ca, tw(d - 1), s);
+  };
   if (d == 3) {
     const int64_t P1 = p->P[1];
     const int64_t yfs = N0 * P1 * Hs, zfs = N0 * N1 * Hs;
     g.out_fs = yfs;
-    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
     mk.mark();
-    const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
+    vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
+    fg.nentry = en.count;
+    fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
     mk.mark();
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s));
     mk.mark();
     // Yp -> Zp (phi, and E_2 later) and Z1 = -i k_1 Zp; Y0 -> Z0
-    const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
+    vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
+    ig.nentry = en.count;
+    ig.es_in = ig.es_out = en.es;
     cplx<T>* zp = b.z;
     cplx<T>* z1 = b.z + zfs;
     cplx<T>* z0 = b.z + 2 * zfs;
-    vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
+    vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia, tw(1), s));
-    if (E) {
+    if (want_E) {
       vgf::C2CInvArgs<T> ia0{b.y + yfs, {z0, nullptr}, ig, deriv1<T>(p, 1, 0)};
       VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia0, tw(1), s));
     }
     mk.mark();
-    const int64_t lines = N0 * N1;
-    if (phi && E) {
-      vgf::C2RArgs<T> ca{zp, {phi, E + 2 * vol}, lines, Hs, deriv2<T>(p, 2, 0, -1)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
-    } else if (phi) {
-      vgf::C2RArgs<T> ca{zp, {phi, nullptr}, lines, Hs, deriv1<T>(p, 2, 0)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
-    } else {
-      vgf::C2RArgs<T> ca{zp, {E + 2 * vol, nullptr}, lines, Hs, deriv1<T>(p, 2, -1)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
-    }
-    if (E) {
-      vgf::C2RArgs<T> c1{z1, {E + vol, nullptr}, lines, Hs, deriv1<T>(p, 2, 0)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], c1, tw(2), s));
-      vgf::C2RArgs<T> c0{z0, {E, nullptr}, lines, Hs, deriv1<T>(p, 2, 0)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], c0, tw(2), s));
+    if (want_phi && want_E) VGF_RUN(c2r(zp, -1, 0, 2, -1));
+    else if (want_phi) VGF_RUN(c2r(zp, -1, 0, -2, 0));
+    else VGF_RUN(c2r(zp, 2, -1, -2, 0));
+    if (want_E) {
+      VGF_RUN(c2r(z1, 1, 0, -2, 0));
+      VGF_RUN(c2r(z0, 0, 0, -2, 0));
     }
     mk.mark();
   } else {
     const int64_t yfs = N0 * Hs;
     g.out_fs = yfs;
-    vgf::R2CArgs<T> ra{{rho, nullptr}, b.x1, N0, Hs, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
     mk.mark();
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s));
     mk.mark();
-    if (phi && E) {
-      vgf::C2RArgs<T> ca{b.y, {phi, E + vol}, N0, Hs, deriv2<T>(p, 1, 0, -1)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
-    } else if (phi) {
-      vgf::C2RArgs<T> ca{b.y, {phi, nullptr}, N0, Hs, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
-    } else {
-      vgf::C2RArgs<T> ca{b.y, {E + vol, nullptr}, N0, Hs, deriv1<T>(p, 1, -1)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
-    }
-    if (E) {
-      vgf::C2RArgs<T> c0{b.y + yfs, {E, nullptr}, N0, Hs, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], c0, tw(1), s));
-    }
+    if (want_phi && want_E) VGF_RUN(c2r(b.y, -1, 0, 1, -1));
+    else if (want_phi) VGF_RUN(c2r(b.y, -1, 0, -2, 0));
+    else VGF_RUN(c2r(b.y, 1, -1, -2, 0));
+    if (want_E) VGF_RUN(c2r(b.y + yfs, 0, 0, -2, 0));
     mk.mark();
   }
   return VGF_OK;
+}
+
+template <typename T>
+vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
+  Entries<T> en;
+  en.ws = (char*)p->ws;
+  en.rho = rho;
+  en.phi = phi;
+  en.E = E;
+  en.want_phi = phi != nullptr;
+  en.want_E = E != nullptr;
+  return enqueue_solve<T>(p, en, s, true);
 }
 
 // Adjoint: the mirror image of solve_t. Forward passes sum their inputs
@@ -563,6 +615,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->off_y = p->off_x2 + align(x2 * cb);
   p->off_z = p->off_y + align(y * cb);
   const size_t ws_bytes = p->off_z + align(z * cb);
+  p->ws_bytes = ws_bytes;
   size_t tw_bytes = 0;
   for (int a = 0; a < dim; ++a) tw_bytes += (size_t)p->P[a] * cb;
   p->bytes = ws_bytes + tw_bytes + (size_t)oct * (rb + 8) + (size_t)vol * 8;
@@ -709,5 +762,249 @@ vgf_status vgf_plan_profile_end(vgf_plan p, double* pass_ms, int* npasses, int* 
 int vgf_plan_hip_error(vgf_plan p) { return p ? (int)p->last_err : (int)hipErrorInvalidValue; }
 
 void vgf_plan_destroy(vgf_plan p) { release(p); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many right-hand sides, possibly of different plans (uneven grid
+// sizes). Entries that share a plan form a group, and each pass of a group
+// runs as one launch over all of its entries (workspaces one entry apart,
+// per-entry rho / phi / E base pointers in device tables). Groups are
+// independent, so with VGF_BATCH_GRAPH they are captured as parallel
+// branches of one hipGraph, which every later solve replays; the tables are
+// refreshed on the solve stream before the replay whenever the caller's
+// pointers change.
+// ---------------------------------------------------------------------------
+struct vgf_batch_s {
+  struct Group {
+    vgf_plan plan = nullptr;
+    std::vector<int> idx;        // entry indices, in order
+    void* ws = nullptr;          // idx.size() x plan->ws_bytes
+    void** tab = nullptr;        // device [3][count]: rho, phi, E
+    hipStream_t st = nullptr;    // capture branch
+    hipEvent_t done = nullptr;
+  };
+  int count = 0;
+  unsigned flags = 0;
+  std::vector<Group> groups;
+  std::vector<void*> cur;        // pointers in the tables, group order [3][count]
+  bool tab_valid = false;
+  hipStream_t cs = nullptr;      // capture origin
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_outputs = -1;        // outputs of the captured graph
+  size_t bytes = 0;
+  hipError_t last_err = hipSuccess;
+};
+
+namespace {
+
+vgf_status batch_hip(vgf_batch b, hipError_t e) {
+  if (e == hipSuccess) return VGF_OK;
+  b->last_err = e;
+  return VGF_ERR_HIP;
+}
+
+void batch_drop_graph(vgf_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_outputs = -1;
+}
+
+void batch_release(vgf_batch b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  for (auto& g : b->groups) {
+    if (g.ws) (void)hipFree(g.ws);
+    if (g.tab) (void)hipFree(g.tab);
+    if (g.st) (void)hipStreamDestroy(g.st);
+    if (g.done) (void)hipEventDestroy(g.done);
+  }
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+}
+
+// the passes of one group, all entries per launch
+template <typename T>
+vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool want_E, hipStream_t s) {
+  const vgf_plan p = g.plan;
+  const int c = (int)g.idx.size();
+  Entries<T> en;
+  en.count = c;
+  en.ws = (char*)g.ws;
+  en.es = (int64_t)(p->ws_bytes / sizeof(cplx<T>));
+  en.rho_tab = (const T* const*)g.tab;
+  en.phi_tab = want_phi ? (T* const*)(g.tab + c) : nullptr;
+  en.E_tab = want_E ? (T* const*)(g.tab + 2 * c) : nullptr;
+  en.want_phi = want_phi;
+  en.want_E = want_E;
+  return enqueue_solve<T>(p, en, s, false);
+}
+
+vgf_status batch_enqueue_groups(vgf_batch b, bool want_phi, bool want_E, bool branches, hipStream_t s) {
+  for (auto& g : b->groups) {
+    hipStream_t gs = branches ? g.st : s;
+    if (branches) {
+      hipError_t e = hipStreamWaitEvent(gs, b->fork, 0);
+      if (e != hipSuccess) return batch_hip(b, e);
+    }
+    vgf_status st = g.plan->prec == VGF_F32 ? batch_group_enqueue<float>(g, want_phi, want_E, gs)
+                                            : batch_group_enqueue<double>(g, want_phi, want_E, gs);
+    if (st != VGF_OK) {
+      if (st == VGF_ERR_HIP) b->last_err = g.plan->last_err;
+      return st;
+    }
+    if (branches) {
+      hipError_t e = hipEventRecord(g.done, gs);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->cs, g.done, 0);
+      if (e != hipSuccess) return batch_hip(b, e);
+    }
+  }
+  return VGF_OK;
+}
+
+vgf_status batch_capture(vgf_batch b, bool want_phi, bool want_E) {
+  batch_drop_graph(b);
+  hipError_t e = hipStreamBeginCapture(b->cs, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return batch_hip(b, e);
+  vgf_status st = VGF_OK;
+  e = hipEventRecord(b->fork, b->cs);
+  if (e != hipSuccess) st = batch_hip(b, e);
+  if (st == VGF_OK) st = batch_enqueue_groups(b, want_phi, want_E, true, b->cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(b->cs, &graph);  // always ends the capture
+  if (st == VGF_OK && e != hipSuccess) st = batch_hip(b, e);
+  if (st != VGF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return st;
+  }
+  b->graph = graph;
+  e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    batch_drop_graph(b);
+    return batch_hip(b, e);
+  }
+  b->graph_outputs = (want_phi ? 1 : 0) | (want_E ? 2 : 0);
+  return VGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, unsigned flags) {
+  if (!out) return VGF_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (count <= 0 || !plans || (flags & ~(unsigned)VGF_BATCH_GRAPH)) return VGF_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i]) return VGF_ERR_INVALID_ARG;
+  vgf_batch b = new (std::nothrow) vgf_batch_s();
+  if (!b) return VGF_ERR_OUT_OF_MEMORY;
+  b->count = count;
+  b->flags = flags;
+  // group by plan, first appearance order; a group's strided launches cover
+  // n0 x entries batches, at most 65535
+  for (int i = 0; i < count; ++i) {
+    const vgf_plan p = plans[i];
+    const int cap = (int)std::max<int64_t>(1, 65535 / p->n[0]);
+    vgf_batch_s::Group* hit = nullptr;
+    for (auto& g : b->groups)
+      if (g.plan == p && (int)g.idx.size() < cap) hit = &g;
+    if (!hit) {
+      b->groups.emplace_back();
+      hit = &b->groups.back();
+      hit->plan = p;
+    }
+    hit->idx.push_back(i);
+  }
+  hipError_t e = hipSuccess;
+  for (auto& g : b->groups) {
+    const size_t c = g.idx.size();
+    const size_t wsb = c * g.plan->ws_bytes;
+    if (b->bytes + wsb > max_workspace_env()) {
+      batch_release(b);
+      return VGF_ERR_OUT_OF_MEMORY;
+    }
+    b->bytes += wsb + 3 * c * sizeof(void*);
+    if ((e = hipMalloc(&g.ws, wsb)) != hipSuccess) break;
+    if ((e = hipMalloc((void**)&g.tab, 3 * c * sizeof(void*))) != hipSuccess) break;
+    if ((e = hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking)) != hipSuccess) break;
+    if ((e = hipEventCreateWithFlags(&g.done, hipEventDisableTiming)) != hipSuccess) break;
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    batch_release(b);
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? VGF_ERR_OUT_OF_MEMORY : VGF_ERR_HIP;
+  }
+  *out = b;
+  return VGF_OK;
+}
+
+vgf_status vgf_batch_solve(vgf_batch b, const void* const* rho, void* const* phi, void* const* E,
+                           hipStream_t stream) {
+  if (!b || !rho || (!phi && !E)) return VGF_ERR_INVALID_ARG;
+  const bool want_phi = phi != nullptr, want_E = E != nullptr;
+  const int n = b->count;
+  std::vector<void*> ptrs((size_t)3 * n, nullptr);
+  size_t k = 0;
+  for (auto& g : b->groups) {
+    const size_t c = g.idx.size();
+    for (size_t j = 0; j < c; ++j) {
+      const int i = g.idx[j];
+      vgf_status st = check_solve_args(g.plan, rho[i], want_phi ? phi[i] : nullptr, want_E ? E[i] : nullptr);
+      if (st != VGF_OK) return st;
+      if (want_phi != (phi && phi[i]) || want_E != (E && E[i])) return VGF_ERR_INVALID_ARG;
+      ptrs[k + j] = const_cast<void*>(rho[i]);
+      ptrs[k + c + j] = want_phi ? phi[i] : nullptr;
+      ptrs[k + 2 * c + j] = want_E ? E[i] : nullptr;
+    }
+    k += 3 * c;
+  }
+  if (!b->tab_valid || ptrs != b->cur) {
+    k = 0;
+    for (auto& g : b->groups) {
+      const size_t c3 = 3 * g.idx.size();
+      for (size_t o = 0; o < c3; o += vgf::PtrChunk::kMax) {
+        vgf::PtrChunk ch{};
+        ch.n = (int)std::min<size_t>(vgf::PtrChunk::kMax, c3 - o);
+        for (int j = 0; j < ch.n; ++j) ch.p[j] = ptrs[k + o + j];
+        hipError_t e = vgf::launch_set_pointers(g.tab + o, ch, stream);
+        if (e != hipSuccess) {
+          b->tab_valid = false;
+          return batch_hip(b, e);
+        }
+      }
+      k += c3;
+    }
+    b->cur = ptrs;
+    b->tab_valid = true;
+  }
+  if (!(b->flags & VGF_BATCH_GRAPH)) return batch_enqueue_groups(b, want_phi, want_E, false, stream);
+  const int outs = (want_phi ? 1 : 0) | (want_E ? 2 : 0);
+  if (!b->exec || b->graph_outputs != outs) {
+    vgf_status st = batch_capture(b, want_phi, want_E);
+    if (st != VGF_OK) return st;
+  }
+  return batch_hip(b, hipGraphLaunch(b->exec, stream));
+}
+
+vgf_status vgf_batch_workspace_bytes(vgf_batch b, size_t* bytes) {
+  if (!b || !bytes) return VGF_ERR_INVALID_ARG;
+  *bytes = b->bytes;
+  return VGF_OK;
+}
+
+int vgf_batch_groups(vgf_batch b) { return b ? (int)b->groups.size() : 0; }
+
+int vgf_batch_hip_error(vgf_batch b) { return b ? (int)b->last_err : (int)hipErrorInvalidValue; }
+
+void vgf_batch_destroy(vgf_batch b) { batch_release(b); }
 
 }  // extern "C"

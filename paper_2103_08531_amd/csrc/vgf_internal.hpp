@@ -24,12 +24,17 @@ inline bool supported_fft_len(int64_t P) {
 }
 
 // Geometry of a batch of lines along a strided axis: element pos of
-// column col (contiguous), batch b is at base + b*bs + pos*ls + col.
+// column col (contiguous), batch b of entry e is at
+// base + e*es + b*bs + pos*ls + col. The launch covers nbatch x nentry
+// batches (entries: independent right-hand sides of one plan whose
+// workspaces sit es elements apart).
 struct StridedGeom {
   int64_t ncols;
   int64_t ls_in, ls_out;
   int64_t bs_in, bs_out;
   int nbatch;
+  int nentry = 1;
+  int64_t es_in = 0, es_out = 0;
 };
 
 // Spectral derivative factors along the transformed axis. A forward pass
@@ -44,12 +49,21 @@ template <typename T> struct Deriv {
   T ks;
 };
 
+// Contiguous-axis passes. nlines = lines of all entries; entry e owns lines
+// [e*lpe, (e+1)*lpe) (lpe even, so a line pair never straddles entries).
+// A user array of entry e is in[t] (one entry) or in_tab[t][e] + in_off[t]
+// (device table of per-entry base pointers, several entries); workspace
+// arrays of entry e sit e*es elements from the first.
 template <typename T> struct R2CArgs {
   const T* in[2];
   cplx<T>* out;    // lines of N+1 values at stride hs
   int64_t nlines;
   int64_t hs;
   Deriv<T> d;
+  int64_t lpe = 0;
+  const T* const* in_tab[2] = {nullptr, nullptr};
+  int64_t in_off[2] = {0, 0};
+  int64_t out_es = 0;
 };
 
 template <typename T> struct C2RArgs {
@@ -58,6 +72,10 @@ template <typename T> struct C2RArgs {
   int64_t nlines;
   int64_t hs;
   Deriv<T> d;
+  int64_t lpe = 0;
+  T* const* out_tab[2] = {nullptr, nullptr};
+  int64_t out_off[2] = {0, 0};
+  int64_t in_es = 0;
 };
 
 template <typename T> struct C2CFwdArgs {
@@ -89,6 +107,8 @@ template <typename T> struct FusedGeom {
   T ks0;             // 2 pi / (P_0 h_0)
   int nf;
   int fields[2];
+  int nentry = 1;    // entries (right-hand sides) of the launch
+  int64_t in_es = 0, out_es = 0;  // element strides between entries
 };
 
 template <typename T>
@@ -102,6 +122,15 @@ hipError_t launch_c2c_inv(int P, const C2CInvArgs<T>& a, const cplx<T>* tw, hipS
 template <typename T>
 hipError_t launch_fused(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,
                         const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
+
+// ---- batched solves ----
+// Up to kMax device pointers, written to dst[0, n) by one small launch.
+struct PtrChunk {
+  static constexpr int kMax = 64;
+  int n;
+  void* p[kMax];
+};
+hipError_t launch_set_pointers(void** dst, const PtrChunk& c, hipStream_t s);
 
 // ---- plan-time precompute (FP64) ----
 // F{G^L}(|k_m|) on m in [0, ext_0) x [0, ext_1) (x [0, ext_2)),

@@ -101,6 +101,21 @@ template <typename T, int P> struct TileW {
   static_assert(n_stages(P) >= 2, "transform needs at least two stages");
 };
 
+// Entry and entry-local line of global line la of a multi-entry launch
+// (lpe lines per entry; lpe <= 0 means a single entry).
+struct EntryLine {
+  int64_t e, line;
+  __device__ __forceinline__ EntryLine(int64_t la, int64_t lpe, int64_t nlines) {
+    if (lpe <= 0 || lpe >= nlines) {
+      e = 0;
+      line = la;
+    } else {
+      e = la / lpe;
+      line = la - e * lpe;
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // k_r2c: out = sum_t m_t(k) R2C(in_t), lines of N = P/2 reals -> N+1 complex
 // ---------------------------------------------------------------------------
@@ -122,14 +137,16 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_r2c(R2CArgs<T> a,
   const int64_t pair = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
   const int64_t la = 2 * pair, lb = la + 1;
   const bool va = la < a.nlines, vb = lb < a.nlines;
+  const EntryLine el(va ? la : 0, a.lpe, a.nlines);
   stage_twiddles<C, P, TW::NT>(twl, tw, tid);
   __syncthreads();
 
   C acc_a[NSLOT], acc_b[NSLOT];
 #pragma unroll
   for (int term = 0; term < NTERM; ++term) {
-    const T* __restrict__ xa = a.in[term] + (va ? la : 0) * N;
-    const T* __restrict__ xb = a.in[term] + (vb ? lb : 0) * N;
+    const T* __restrict__ base = a.in_tab[term] ? a.in_tab[term][el.e] + a.in_off[term] : a.in[term];
+    const T* __restrict__ xa = base + el.line * N;
+    const T* __restrict__ xb = base + (vb ? el.line + 1 : el.line) * N;
     const int code = a.d.code[term];
     typename S0::Regs g0;
     S0::template load_first<true>(g0, q, [&](int j, int r) {
@@ -168,12 +185,13 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_r2c(R2CArgs<T> a,
       }
     }
   }
+  C* __restrict__ out = a.out + el.e * a.out_es + el.line * a.hs;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int k = q + NQ * s;
     if (k >= H) continue;
-    if (va) a.out[la * a.hs + k] = acc_a[s];
-    if (vb) a.out[lb * a.hs + k] = acc_b[s];
+    if (va) out[k] = acc_a[s];
+    if (vb) out[a.hs + k] = acc_b[s];
   }
 }
 
@@ -198,6 +216,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_c2r(C2RArgs<T> a,
   const int64_t pair = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
   const int64_t la = 2 * pair, lb = la + 1;
   const bool va = la < a.nlines, vb = lb < a.nlines;
+  const EntryLine el(va ? la : 0, a.lpe, a.nlines);
+  const C* __restrict__ in = a.in + el.e * a.in_es + el.line * a.hs;
 
   // this lane's k-slots of the two half-spectra
   C xs[NSLOT], ys[NSLOT];
@@ -206,8 +226,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_c2r(C2RArgs<T> a,
     const int k = q + NQ * s;
     xs[s] = ys[s] = C{T(0), T(0)};
     if (k >= H) continue;
-    if (va) xs[s] = a.in[la * a.hs + k];
-    if (vb) ys[s] = a.in[lb * a.hs + k];
+    if (va) xs[s] = in[k];
+    if (vb) ys[s] = in[a.hs + k];
   }
   stage_twiddles<C, P, TW::NT>(twl, tw, tid);
   __syncthreads();
@@ -244,8 +264,9 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_c2r(C2RArgs<T> a,
     wave_sync();
     typename SL::Regs gl;
     middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(gl, tile, twl, l, q);
-    T* __restrict__ oa = a.out[o] + (va ? la : 0) * N;
-    T* __restrict__ ob = a.out[o] + (vb ? lb : 0) * N;
+    T* __restrict__ base = a.out_tab[o] ? a.out_tab[o][el.e] + a.out_off[o] : a.out[o];
+    T* __restrict__ oa = base + el.line * N;
+    T* __restrict__ ob = oa + N;
     SL::template store_last<true>(gl, q, [&](int j, int r, C v) {
       const int pos = SL::out_pos(j, r);
       if (va) oa[pos] = v.x;
@@ -316,9 +337,10 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_fw
   const ColIO co((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_out);
   typename SL::Regs acc;
 
+  const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
 #pragma unroll
   for (int term = 0; term < NTERM; ++term) {
-    const C* __restrict__ src = a.in[term] + blockIdx.y * a.g.bs_in;
+    const C* __restrict__ src = a.in[term] + e * a.g.es_in + bb * a.g.bs_in;
     const int code = a.d.code[term];
     if (term > 0) __syncthreads();
     typename S0::Regs g0;
@@ -342,7 +364,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_fw
     }
   }
   if (!co.valid) return;
-  C* __restrict__ dst = a.out + blockIdx.y * a.g.bs_out;
+  C* __restrict__ dst = a.out + e * a.g.es_out + bb * a.g.bs_out;
   SL::template store_last<false>(acc, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
 }
 
@@ -363,7 +385,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_in
   using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
   const ColIO ci((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_in);
   const ColIO co((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_out);
-  const C* __restrict__ src = a.in + blockIdx.y * a.g.bs_in;
+  const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
+  const C* __restrict__ src = a.in + e * a.g.es_in + bb * a.g.bs_in;
   typename S0::Regs gin;
   S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
   stage_twiddles<C, P, NT>(twl, tw, tid);
@@ -391,7 +414,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_in
     typename SL::Regs gl;
     middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
     if (co.valid) {
-      C* __restrict__ dst = a.out[o] + blockIdx.y * a.g.bs_out;
+      C* __restrict__ dst = a.out[o] + e * a.g.es_out + bb * a.g.bs_out;
       SL::template store_last<true>(gl, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
     }
   }
@@ -495,17 +518,22 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
   // rows k1 and P1-k1 read the same kernel-spectrum octant rows, and
   // neighbouring tiles share 128-byte lines of it, so both reuses land in the
   // same L2 shortly after the first touch.
+  // ntiles tiles per entry; the launch covers ntiles * nentry (entry-major).
+  const int total = ntiles * g.nentry;
   const bool pairs = g.dim == 3 && g.hs % NL == 0;
   const int tiles_per_row = pairs ? g.hs / NL : ntiles;
   const int nrows = ntiles / tiles_per_row;
   const bool xcd = (gridDim.x % 8) == 0 && gridDim.x >= 8;
   const int per_xcd = xcd ? (int)gridDim.x / 8 : (int)gridDim.x;
-  const int chunk = xcd ? (ntiles + 7) / 8 : ntiles;
+  const int chunk = xcd ? (total + 7) / 8 : total;
   const int chunk0 = xcd ? (int)(blockIdx.x % 8) * chunk : 0;
-  const int chunk1 = chunk0 + chunk < ntiles ? chunk0 + chunk : ntiles;
+  const int chunk1 = chunk0 + chunk < total ? chunk0 + chunk : total;
   int u = chunk0 + (xcd ? (int)blockIdx.x / 8 : (int)blockIdx.x);
   if (u >= chunk1) return;
-  auto tile_of = [&](int uu) -> int {
+  // (entry, tile) of position uu in the visiting order
+  auto tile_of = [&](int uu, int& e) -> int {
+    e = uu / ntiles;
+    uu -= e * ntiles;
     if (!pairs) return uu;
     const int row = uu / tiles_per_row, blk = uu - row * tiles_per_row;
     int k1;
@@ -517,14 +545,16 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
     }
     return k1 * tiles_per_row + blk;
   };
-  int tile = tile_of(u);
+  int ent = 0;
+  int tile = tile_of(u, ent);
   stage_twiddles<C, P, NT>(twl, tw, tid);
 
   // loads of one tile: the stage-0 inputs and the kernel spectrum at this
   // thread's forward-output rows (natural order j + r*NB)
-  auto load_tile = [&](const FusedCol<T>& fc, typename S0::Regs& g0, T (&sv)[SL::NTASK][SL::R]) {
+  auto load_tile = [&](const FusedCol<T>& fc, int e, typename S0::Regs& g0, T (&sv)[SL::NTASK][SL::R]) {
     const ColIO& cio = fc.io;
-    S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
+    const C* __restrict__ src = in + e * g.in_es;
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
       if (!SL::active(t, q)) continue;
@@ -538,10 +568,11 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
   FusedCol<T> fcn(g, (int64_t)tile * NL + l);
   typename S0::Regs g0n;
   T svn[SL::NTASK][SL::R];
-  load_tile(fcn, g0n, svn);
+  load_tile(fcn, ent, g0n, svn);
 
   for (;;) {
     const FusedCol<T> fc = fcn;
+    const int e = ent;
     typename S0::Regs g0 = g0n;
     T sv[SL::NTASK][SL::R];
 #pragma unroll
@@ -550,10 +581,11 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
       for (int r = 0; r < SL::R; ++r) sv[t][r] = svn[t][r];
     const int unext = u + per_xcd;
     const bool more = unext < chunk1;
-    const int next = more ? tile_of(unext) : 0;
+    int enext = 0;
+    const int next = more ? tile_of(unext, enext) : 0;
     if (more) {
       fcn = FusedCol<T>(g, (int64_t)next * NL + l);
-      load_tile(fcn, g0n, svn);
+      load_tile(fcn, enext, g0n, svn);
     }
 
     S0::butterflies(g0, q);
@@ -588,13 +620,14 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
       typename ISL::Regs o;
       transform_pp<T, P, NT, NL, LP, 1>(v, o, pp, twl, l, q);
       if (fc.io.valid) {
-        C* __restrict__ dst = out + fi * g.out_fs;
+        C* __restrict__ dst = out + e * g.out_es + fi * g.out_fs;
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[fc.io.template off<ISL::NB>(j, r)] = val; });
       }
     }
     if (!more) break;
     u = unext;
     tile = next;
+    ent = enext;
   }
 }
 
@@ -713,8 +746,10 @@ template <typename T, int P>
 hipError_t launch_c2c_fwd_p(const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
   using TL = Tile<T, P>;
   const int64_t bx = (a.g.ncols + TL::NL - 1) / TL::NL;
-  if (bx == 0 || a.g.nbatch == 0 || a.d.n == 0) return hipSuccess;
-  const dim3 grid((unsigned)bx, (unsigned)a.g.nbatch);
+  const int64_t by = (int64_t)a.g.nbatch * a.g.nentry;
+  if (bx == 0 || by == 0 || a.d.n == 0) return hipSuccess;
+  if (by > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)bx, (unsigned)by);
   if (a.d.n == 2)
     hipLaunchKernelGGL((k_c2c_fwd<T, P, 2>), grid, dim3(TL::NT), 0, s, a, tw);
   else
@@ -726,8 +761,10 @@ template <typename T, int P>
 hipError_t launch_c2c_inv_p(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
   using TL = Tile<T, P>;
   const int64_t bx = (a.g.ncols + TL::NL - 1) / TL::NL;
-  if (bx == 0 || a.g.nbatch == 0 || a.d.n == 0) return hipSuccess;
-  const dim3 grid((unsigned)bx, (unsigned)a.g.nbatch);
+  const int64_t by = (int64_t)a.g.nbatch * a.g.nentry;
+  if (bx == 0 || by == 0 || a.d.n == 0) return hipSuccess;
+  if (by > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)bx, (unsigned)by);
   if (a.d.n == 2)
     hipLaunchKernelGGL((k_c2c_inv<T, P, 2>), grid, dim3(TL::NT), 0, s, a, tw);
   else
@@ -738,8 +775,9 @@ hipError_t launch_c2c_inv_p(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream
 template <typename T, int P>
 hipError_t launch_fused_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
                           const T* spec, const cplx<T>* tw, hipStream_t s) {
-  if (g.nf == 0) return hipSuccess;
+  if (g.nf == 0 || g.nentry == 0) return hipSuccess;
   if (adjoint) {
+    if (g.nentry != 1) return hipErrorInvalidValue;  // the adjoint runs one entry per launch
     using TL = Tile<T, P>;
     const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
     if (bx == 0) return hipSuccess;
@@ -759,7 +797,9 @@ hipError_t launch_fused_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const F
         return hipGetLastError();
       slots = cus * (per_cu > 0 ? per_cu : 1);
     }
-    const int grid = (int)(bx < slots ? bx : slots);
+    const int64_t total = bx * g.nentry;
+    if (total > INT32_MAX) return hipErrorInvalidConfiguration;
+    const int grid = (int)(total < slots ? total : slots);
     hipLaunchKernelGGL((k_fused<T, P>), dim3((unsigned)grid), dim3(TL::NT), 0, s, in, out, g, spec, tw,
                        (int)bx);
   }

@@ -24,7 +24,10 @@ OUT_PHI, OUT_E = 1, 2
 EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batched",
            "vgf_plan_get_L", "vgf_plan_workspace_bytes", "vgf_plan_get_kernel",
            "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
-           "vgf_status_string", "vgf_plan_profile_begin", "vgf_plan_profile_end"]
+           "vgf_status_string", "vgf_plan_profile_begin", "vgf_plan_profile_end",
+           "vgf_batch_create", "vgf_batch_solve", "vgf_batch_workspace_bytes", "vgf_batch_groups",
+           "vgf_batch_hip_error", "vgf_batch_destroy"]
+BATCH_GRAPH = 1
 PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused_axis0", "c2c_inv", "c2r"],
               2: ["r2c", "fused_axis0", "c2r"]}
 
@@ -74,6 +77,18 @@ def lib():
         L.vgf_plan_profile_end.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.vgf_status_string.restype = C.c_char_p
         L.vgf_status_string.argtypes = [C.c_int]
+        L.vgf_batch_create.restype = C.c_int
+        L.vgf_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_uint]
+        L.vgf_batch_solve.restype = C.c_int
+        L.vgf_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
+        L.vgf_batch_workspace_bytes.restype = C.c_int
+        L.vgf_batch_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.vgf_batch_groups.restype = C.c_int
+        L.vgf_batch_groups.argtypes = [vp]
+        L.vgf_batch_hip_error.restype = C.c_int
+        L.vgf_batch_hip_error.argtypes = [vp]
+        L.vgf_batch_destroy.restype = None
+        L.vgf_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -242,6 +257,75 @@ def solve_batched(plans, rhos, phis=None, Es=None, stream=None):
     ee = (VP * count)(*[(x.data_ptr() if x is not None else None) for x in Es]) if Es is not None else None
     st = lib().vgf_solve_batched(pl, count, rh, ph, ee, _stream(stream))
     _check(st, "vgf_solve_batched")
+
+
+class Batch:
+    """Many right-hand sides over fixed plans (vgf_batch_*): entries sharing a
+    plan run as one launch per pass; with graph=True the whole batch is
+    captured once and replayed as one hipGraph per solve."""
+
+    def __init__(self, plans, graph=True):
+        self.plans = list(plans)  # keeps the plans alive
+        count = len(self.plans)
+        VP = C.c_void_p
+        pl = (VP * count)(*[p.handle.value for p in self.plans])
+        handle = C.c_void_p()
+        self._h = None
+        _check(lib().vgf_batch_create(C.byref(handle), pl, count, BATCH_GRAPH if graph else 0),
+               "vgf_batch_create")
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch destroyed")
+        return self._h
+
+    @property
+    def groups(self):
+        return lib().vgf_batch_groups(self.handle)
+
+    @property
+    def workspace_bytes(self):
+        v = C.c_size_t()
+        _check(lib().vgf_batch_workspace_bytes(self.handle, C.byref(v)), "vgf_batch_workspace_bytes")
+        return v.value
+
+    def solve(self, rhos, phis=None, Es=None, stream=None):
+        """rhos, phis, Es: lists of tensors shaped for each entry's plan
+        (phis / Es None: that output is skipped for every entry)."""
+        count = len(self.plans)
+        if len(rhos) != count or (phis is not None and len(phis) != count) or (
+                Es is not None and len(Es) != count):
+            raise ValueError("one rho (and phi / E) per entry")
+        for i, p in enumerate(self.plans):
+            p._check_tensor(rhos[i], p.n, "rho[%d]" % i)
+            if phis is not None:
+                p._check_tensor(phis[i], p.n, "phi[%d]" % i)
+            if Es is not None:
+                p._check_tensor(Es[i], (p.dim,) + p.n, "E[%d]" % i)
+        VP = C.c_void_p
+        rh = (VP * count)(*[r.data_ptr() for r in rhos])
+        ph = (VP * count)(*[x.data_ptr() for x in phis]) if phis is not None else None
+        ee = (VP * count)(*[x.data_ptr() for x in Es]) if Es is not None else None
+        _check(lib().vgf_batch_solve(self.handle, rh, ph, ee, _stream(stream)), "vgf_batch_solve")
+
+    def close(self):
+        if self._h is not None:
+            lib().vgf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def _autograd_function():

@@ -99,3 +99,23 @@ def test_workspace_cap_is_enforced(V, monkeypatch):
     monkeypatch.setenv("VGF_MAX_WORKSPACE", "1024")
     st, handle = _create(V)
     assert st == -4 and handle.value is None
+
+
+def test_null_batch_calls_fail_cleanly(V):
+    L = V.lib()
+    VP = C.c_void_p
+    handle = VP(12345)
+    assert L.vgf_batch_create(None, None, 1, 0) == -1
+    assert L.vgf_batch_create(C.byref(handle), None, 1, 0) == -1
+    assert handle.value is None  # *out is cleared on error
+    plans = (VP * 2)(None, None)
+    assert L.vgf_batch_create(C.byref(handle), plans, 2, 0) == -1  # NULL plan entries
+    assert L.vgf_batch_create(C.byref(handle), plans, 0, 0) == -1
+    assert L.vgf_batch_create(C.byref(handle), plans, -3, 0) == -1
+    assert L.vgf_batch_create(C.byref(handle), plans, 2, 4) == -1  # unknown flag
+    ptrs = (VP * 1)(None)
+    assert L.vgf_batch_solve(None, ptrs, ptrs, None, None) == -1
+    s = C.c_size_t()
+    assert L.vgf_batch_workspace_bytes(None, C.byref(s)) == -1
+    assert L.vgf_batch_groups(None) == 0
+    L.vgf_batch_destroy(None)

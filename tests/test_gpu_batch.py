@@ -1,0 +1,165 @@
+"""Batched solves (vgf_batch_*): entries of several plans, one launch per pass
+and per plan, optionally replayed as one captured hipGraph. Every entry must
+equal vgf_solve on the same plan bit for bit (the same kernels in the same
+arithmetic order), across graph replays with eager work between them, new
+pointers and new output sets; and a mixed batch must match the FP64 oracle."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_common import FP32_TOL, FP64_TOL, check_fields, need_gpu, rounded_input, say
+from paper_2103_08531_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _plans(vgf, specs):
+    plans = {}
+    for n, prec, method in specs:
+        key = (n, prec, method)
+        if key not in plans:
+            h = tuple(2.0 / (x - 1) for x in n)
+            plans[key] = vgf.Plan(n, h, method=method, precision=prec)
+    return plans
+
+
+def _entries(torch, plans, keys, seed):
+    rhos = []
+    for i, k in enumerate(keys):
+        p = plans[k]
+        rhos.append(torch.from_numpy(W.random_field(seed + i, p.n)).to("cuda", p.dtype))
+    return rhos
+
+
+def _outputs(torch, plans, keys):
+    phis = [torch.full(plans[k].n, float("nan"), dtype=plans[k].dtype, device="cuda") for k in keys]
+    Es = [torch.full((plans[k].dim,) + plans[k].n, float("nan"), dtype=plans[k].dtype, device="cuda")
+          for k in keys]
+    return phis, Es
+
+
+# 3D and 2D, both precisions, VGF and HE, repeated plans (groups of 1..3)
+KEYS = [((32, 32, 32), "f32", "vgf"), ((48, 48, 48), "f32", "vgf"), ((32, 32, 32), "f32", "vgf"),
+        ((16, 24, 32), "f64", "vgf"), ((32, 32, 32), "f32", "vgf"), ((64, 48), "f64", "he"),
+        ((96, 96, 96), "f32", "vgf"), ((64, 48), "f64", "he"), ((24, 24, 24), "f64", "vgf")]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_single_solves(graph):
+    torch, vgf = need_gpu()
+    plans = _plans(vgf, KEYS)
+    batch = vgf.Batch([plans[k] for k in KEYS], graph=graph)
+    assert batch.groups == len(set(KEYS))
+    say("batch of %d entries, %d groups, graph=%s, %.1f MB" % (len(KEYS), batch.groups, graph,
+                                                                batch.workspace_bytes / 1e6))
+    for rep in range(3):
+        rhos = _entries(torch, plans, KEYS, seed=100 * rep)
+        phis, Es = _outputs(torch, plans, KEYS)
+        batch.solve(rhos, phis, Es)
+        # eager work between replays on the same stream
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i, k in enumerate(KEYS):
+            p1, E1 = plans[k].solve(rhos[i])
+            torch.cuda.synchronize()
+            assert torch.equal(phis[i], p1), (rep, i, k)
+            assert torch.equal(Es[i], E1), (rep, i, k)
+        say("  replay %d: all %d entries bit-identical to vgf_solve" % (rep, len(KEYS)))
+    # a different output set re-captures; E only, then phi only
+    rhos = _entries(torch, plans, KEYS, seed=7)
+    phis, Es = _outputs(torch, plans, KEYS)
+    batch.solve(rhos, None, Es)
+    torch.cuda.synchronize()
+    for i, k in enumerate(KEYS):
+        _, E1 = plans[k].solve(rhos[i], want_phi=False)
+        torch.cuda.synchronize()
+        assert torch.equal(Es[i], E1), ("E only", i)
+        assert torch.isnan(phis[i]).all()
+    batch.solve(rhos, phis, None)
+    torch.cuda.synchronize()
+    for i, k in enumerate(KEYS):
+        p1, _ = plans[k].solve(rhos[i], want_E=False)
+        torch.cuda.synchronize()
+        assert torch.equal(phis[i], p1), ("phi only", i)
+    batch.close()
+    for p in plans.values():
+        p.close()
+
+
+def test_batch_rejects_partial_outputs():
+    torch, vgf = need_gpu()
+    keys = KEYS[:3]
+    plans = _plans(vgf, keys)
+    batch = vgf.Batch([plans[k] for k in keys], graph=True)
+    rhos = _entries(torch, plans, keys, seed=1)
+    phis, Es = _outputs(torch, plans, keys)
+    VP = C.c_void_p
+    rh = (VP * 3)(*[r.data_ptr() for r in rhos])
+    ph = (VP * 3)(phis[0].data_ptr(), None, phis[2].data_ptr())
+    assert vgf.lib().vgf_batch_solve(batch.handle, rh, ph, None, None) == -1
+    rh_bad = (VP * 3)(rhos[0].data_ptr(), None, rhos[2].data_ptr())
+    ph = (VP * 3)(*[x.data_ptr() for x in phis])
+    assert vgf.lib().vgf_batch_solve(batch.handle, rh_bad, ph, None, None) == -1
+    torch.cuda.synchronize()
+    for x in phis:
+        assert torch.isnan(x).all()  # nothing was enqueued
+    batch.close()
+    for p in plans.values():
+        p.close()
+
+
+def test_batch_3d_mixed_graph_vs_oracle():
+    """The 64-entry mixed-size FP32 workload through one graph launch."""
+    torch, vgf = need_gpu()
+    charges = W.batch_3d_mixed(seed=0, count=64)
+    plans = {}
+    kernels = {}
+    for ch in charges:
+        if ch.n not in plans:
+            plans[ch.n] = vgf.Plan(ch.n, ch.h, method="vgf", precision="f32")
+            kernels[ch.n] = orc.vgf_kernel(ch.n, ch.h, plans[ch.n].L)
+    pl = [plans[ch.n] for ch in charges]
+    batch = vgf.Batch(pl, graph=True)
+    assert batch.groups == len(plans)
+    rhos = [torch.from_numpy(ch.rho()).to("cuda", torch.float32) for ch in charges]
+    phis = [torch.empty(ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    Es = [torch.empty((3,) + ch.n, dtype=torch.float32, device="cuda") for ch in charges]
+    batch.solve(rhos, phis, Es)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for b, ch in enumerate(charges):
+        rho = rounded_input(ch.rho(), "f32")
+        phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, kernels[ch.n], rho)
+        errs = check_fields(phis[b].double().cpu().numpy(), Es[b].double().cpu().numpy(), phi_o, E_o,
+                            FP32_TOL, "graph batch[%d] N=%d" % (b, ch.n[0]))
+        worst = max(worst, max(errs.values()))
+    say("graph batch worst rel-L2 %.3e" % worst)
+    batch.close()
+    for p in plans.values():
+        p.close()
+
+
+def test_batch_fp64_vs_oracle():
+    torch, vgf = need_gpu()
+    keys = [((24, 24, 24), "f64", "vgf"), ((32, 32, 32), "f64", "he"), ((24, 24, 24), "f64", "vgf"),
+            ((48, 32), "f64", "vgf")]
+    plans = _plans(vgf, keys)
+    batch = vgf.Batch([plans[k] for k in keys], graph=True)
+    rho_np = [W.random_field(50 + i, plans[k].n) for i, k in enumerate(keys)]
+    rhos = [torch.from_numpy(r).to("cuda", torch.float64) for r in rho_np]
+    phis, Es = _outputs(torch, plans, keys)
+    batch.solve(rhos, phis, Es)
+    torch.cuda.synchronize()
+    for i, k in enumerate(keys):
+        n, _, method = k
+        h = plans[k].h
+        w = orc.vgf_kernel(n, h, plans[k].L) if method == "vgf" else orc.he_kernel(n, h)
+        phi_o, E_o = orc.solve_fft2n(n, h, w, rho_np[i])
+        check_fields(phis[i].cpu().numpy(), Es[i].cpu().numpy(), phi_o, E_o, FP64_TOL,
+                     "f64 batch[%d] %s %s" % (i, n, method))
+    batch.close()
+    for p in plans.values():
+        p.close()
