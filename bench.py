@@ -26,7 +26,10 @@ Printed JSON line (one, rank 0):
                rel-L2 of the GPU results)
   batch        batch_3d_mixed (64 FP32 grids of uneven N): one solve per
                entry vs one launch per pass and grid size vs the same as one
-               replayed hipGraph, in ms per batch and solves/s
+               replayed hipGraph, before and after autotuning the groups' tile
+               schedules, in ms per batch and solves/s
+The 256^3 plans are autotuned (tile schedule per pass, bit-identical results)
+before the warm-up; the chosen schedules are reported.
 
 roofline.traffic is the dominant kernel's HBM bytes per launch from two
 rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
@@ -281,12 +284,13 @@ def kernel_bytes(n, prec_bytes):
     }
 
 
-def run_precision(vgf, torch, ch, rho64, precision, steps, warmup):
+def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
     dt = torch.float32 if precision == "f32" else torch.float64
     plan = vgf.Plan(ch.n, ch.h, method="vgf", precision=precision)
     rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
     phi = torch.empty(ch.n, dtype=dt, device="cuda")
     E = torch.empty((3,) + ch.n, dtype=dt, device="cuda")
+    schedule = plan.autotune(rho, phi, E, reps=3) if tune else plan.schedule
     for _ in range(warmup):
         plan.solve(rho, phi, E)
     torch.cuda.synchronize()
@@ -311,7 +315,7 @@ def run_precision(vgf, torch, ch, rho64, precision, steps, warmup):
     del rho, phi, E
     torch.cuda.empty_cache()
     return {"wall_ms": wall_ms, "event_ms": ev_ms, "passes": passes, "nsolves": nsolves,
-            "out": out, "L": L}
+            "out": out, "L": L, "schedule": list(schedule)}
 
 
 def run_batch(vgf, torch, workloads, steps, warmup, seed):
@@ -337,9 +341,13 @@ def run_batch(vgf, torch, workloads, steps, warmup, seed):
             p.solve(r, ph, E)
 
     runs = {"single": single, "grouped": lambda: grouped.solve(rhos, phis, Es),
-            "graph": lambda: graphed.solve(rhos, phis, Es)}
+            "graph": lambda: graphed.solve(rhos, phis, Es),
+            "graph_tuned": lambda: graphed.solve(rhos, phis, Es)}
     out = {}
+    schedules = None
     for name, fn in runs.items():
+        if name == "graph_tuned":
+            schedules = graphed.autotune(rhos, phis, Es, reps=3)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -360,10 +368,10 @@ def run_batch(vgf, torch, workloads, steps, warmup, seed):
     for ch in charges:
         sizes[str(ch.n[0])] = sizes.get(str(ch.n[0]), 0) + 1
     res = {"workload": "batch_3d_mixed", "entries": len(charges), "precision": "f32",
-           "outputs": "phi+E", "sizes": sizes, "groups": graphed.groups, "modes": out,
+           "outputs": "phi+E", "sizes": sizes, "groups": graphed.groups, "schedules": schedules, "modes": out,
            "moved_bytes_per_batch": moved,
-           "graph_gbs": moved / (out["graph"]["ms_per_batch"] * 1e-3) / 1e9,
-           "speedup_graph_vs_single": out["single"]["ms_per_batch"] / out["graph"]["ms_per_batch"]}
+           "graph_gbs": moved / (out["graph_tuned"]["ms_per_batch"] * 1e-3) / 1e9,
+           "speedup_graph_vs_single": out["single"]["ms_per_batch"] / out["graph_tuned"]["ms_per_batch"]}
     grouped.close()
     graphed.close()
     for p in plans.values():
@@ -478,6 +486,7 @@ def main():
                    "seed": args.seed, "L": f32["L"], "parallelism": "single GPU"},
         "fp64": {"value": 1e3 / f64["wall_ms"], "unit": "solves/s", "ms_per_step": f64["wall_ms"],
                  "dtype": "f64"},
+        "schedule": {"f32": f32["schedule"], "f64": f64["schedule"]},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": tr32,

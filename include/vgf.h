@@ -150,6 +150,18 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
 vgf_status vgf_batch_solve(vgf_batch batch, const void* const* rho, void* const* phi, void* const* E,
                            hipStream_t stream);
 
+/* Tunes every group's schedule as vgf_plan_autotune does, with the group's
+ * entry count per launch (a schedule that suits one grid alone may not suit
+ * many at once), on the caller's buffers (arguments as vgf_batch_solve;
+ * outputs receive results). Cached per process per (grid, precision,
+ * outputs, entries). Groups start with their plan's schedule; a captured
+ * graph is dropped and recaptured by the next solve. Synchronises `stream`. */
+vgf_status vgf_batch_autotune(vgf_batch batch, const void* const* rho, void* const* phi,
+                              void* const* E, int reps, hipStream_t stream);
+
+/* The schedule (int[5]) of group `group` (0 <= group < vgf_batch_groups). */
+vgf_status vgf_batch_get_schedule(vgf_batch batch, int group, int* schedule);
+
 /* Device bytes held by the batch (group workspaces and pointer tables). */
 vgf_status vgf_batch_workspace_bytes(vgf_batch batch, size_t* bytes);
 
@@ -163,6 +175,34 @@ int vgf_batch_hip_error(vgf_batch batch);
 /* Waits for nothing: destroy only after the batch's work has completed.
  * NULL is a no-op. */
 void vgf_batch_destroy(vgf_batch batch);
+
+/* ---- Tile schedules and their autotuner ----
+ * The strided FFT passes (axis-1 forward and inverse in 3D, the fused axis-0
+ * pass) come in tile-schedule variants: 0 = one 128-byte row segment of
+ * columns per workgroup (the default), 1 = half of it (more and smaller
+ * workgroups). A variant changes only the launch shape: every line is
+ * transformed with the same arithmetic, so results are bit-identical across
+ * schedules. A schedule is an int[5], one variant per pass in the order
+ * VGF_PASS_R2C, VGF_PASS_C2C_FWD, VGF_PASS_FUSED, VGF_PASS_C2C_INV,
+ * VGF_PASS_C2R; the contiguous-axis passes (and the 2D middle passes, which
+ * do not exist) only take 0. */
+enum { VGF_PASS_R2C = 0, VGF_PASS_C2C_FWD = 1, VGF_PASS_FUSED = 2, VGF_PASS_C2C_INV = 3,
+       VGF_PASS_C2R = 4, VGF_NUM_PASSES = 5 };
+
+/* Chooses the plan's schedule by measurement: for each variant, one warm-up
+ * solve and `reps` timed solves of (rho, phi, E) (arguments as vgf_solve)
+ * with HIP events at the pass boundaries on `stream`; each pass keeps its
+ * fastest variant. phi / E receive solve results. Synchronises `stream`.
+ * The choice is cached in the process per (grid, precision, outputs), so an
+ * identical plan tuned again takes the cached schedule without running.
+ * Errors: as vgf_solve, INVALID_ARG for reps <= 0. */
+vgf_status vgf_plan_autotune(vgf_plan plan, const void* rho, void* phi, void* E, int reps,
+                             hipStream_t stream);
+
+/* The plan's schedule (int[5], see above); set checks every variant and
+ * rejects a non-zero variant for a pass that has none (INVALID_ARG). */
+vgf_status vgf_plan_get_schedule(vgf_plan plan, int* schedule);
+vgf_status vgf_plan_set_schedule(vgf_plan plan, const int* schedule);
 
 /* The truncation radius the plan uses (0 for HE). */
 vgf_status vgf_plan_get_L(vgf_plan plan, double* L);

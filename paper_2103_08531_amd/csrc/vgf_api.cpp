@@ -19,9 +19,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -52,6 +55,7 @@ struct vgf_plan_s {
   void* ws = nullptr;            // solve workspace
   size_t off_x1 = 0, off_x2 = 0, off_y = 0, off_z = 0;
   size_t ws_bytes = 0;           // solve workspace (a multiple of 256 bytes)
+  int schedule[5] = {0, 0, 0, 0, 0};  // tile variant per pass (VGF_PASS_* order)
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
 
@@ -236,22 +240,29 @@ vgf_status hip_status(vgf_plan p, hipError_t e) {
 }
 
 constexpr int kMaxMarks = 6;
+constexpr int vgf_tile_variants() { return vgf::kTileVariantsHost; }
 
-// Records the pass boundaries of one solve when the plan is profiling.
+// Records the pass boundaries of one solve: into the plan's profiling
+// events when the plan is profiling, or into caller-given events (tuning).
 struct Marks {
   vgf_plan p;
   hipStream_t s;
   hipEvent_t* ev = nullptr;
+  bool own = false;  // plan profiling slot
   int n = 0;
-  Marks(vgf_plan p_, hipStream_t s_, bool on = true) : p(p_), s(s_) {
-    if (on && p->profiling && p->prof_used < p->prof_cap)
+  Marks(vgf_plan p_, hipStream_t s_, bool on, hipEvent_t* given) : p(p_), s(s_) {
+    if (given) {
+      ev = given;
+    } else if (on && p->profiling && p->prof_used < p->prof_cap) {
       ev = &p->prof_events[(size_t)p->prof_used++ * kMaxMarks];
+      own = true;
+    }
   }
   void mark() {
     if (ev && n < kMaxMarks) (void)hipEventRecord(ev[n++], s);
   }
   ~Marks() {
-    if (ev) p->prof_npass = n - 1;
+    if (own) p->prof_npass = n - 1;
   }
 };
 
@@ -340,8 +351,12 @@ void c2r_out(vgf::C2RArgs<T>& ca, int o, const Entries<T>& en, int field, int64_
 // Forward solve. Each pass applies the derivative factor of its own axis:
 // the axis-0 pass yields the spectra of phi (Yp) and E_0 (Y0); the last
 // two axes derive E_1 and E_2 from phi's spectrum as they invert.
+// pass ids (also the order of plan->schedule)
+enum { kPassR2C = 0, kPassC2CF = 1, kPassFused = 2, kPassC2CI = 3, kPassC2R = 4, kPasses = 5 };
+
 template <typename T>
-vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks) {
+vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks,
+                         const int* sched, hipEvent_t* mark_events = nullptr) {
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -357,7 +372,7 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
   if (want_E) g.fields[g.nf++] = 1;
   g.nentry = en.count;
   g.in_es = g.out_es = en.es;
-  Marks mk(p, s, marks);
+  Marks mk(p, s, marks, mark_events);
   mk.mark();
   const int64_t lpe = d == 3 ? N0 * N1 : N0;  // contiguous lines per entry
   vgf::R2CArgs<T> ra{};
@@ -392,9 +407,9 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     fg.nentry = en.count;
     fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
     mk.mark();
-    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x2, b.y, g, spec, tw(0), s));
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x2, b.y, g, spec, tw(0), s));
     mk.mark();
     // Yp -> Zp (phi, and E_2 later) and Z1 = -i k_1 Zp; Y0 -> Z0
     vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
@@ -404,10 +419,10 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     cplx<T>* z1 = b.z + zfs;
     cplx<T>* z0 = b.z + 2 * zfs;
     vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
     if (want_E) {
       vgf::C2CInvArgs<T> ia0{b.y + yfs, {z0, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia0, tw(1), s));
+      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia0, tw(1), s));
     }
     mk.mark();
     if (want_phi && want_E) VGF_RUN(c2r(zp, -1, 0, 2, -1));
@@ -423,7 +438,7 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     g.out_fs = yfs;
     VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
     mk.mark();
-    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], false, b.x1, b.y, g, spec, tw(0), s));
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x1, b.y, g, spec, tw(0), s));
     mk.mark();
     if (want_phi && want_E) VGF_RUN(c2r(b.y, -1, 0, 1, -1));
     else if (want_phi) VGF_RUN(c2r(b.y, -1, 0, -2, 0));
@@ -431,6 +446,100 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     if (want_E) VGF_RUN(c2r(b.y + yfs, 0, 0, -2, 0));
     mk.mark();
   }
+  return VGF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the tile schedules. Each candidate schedule (every tunable
+// pass at variant v) runs one warm-up enqueue and `reps` timed ones; HIP
+// events at the pass boundaries give each pass's time, and each pass keeps
+// its fastest variant. The choice is cached per process for the grid,
+// precision, outputs and number of entries per launch.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  int prec, dim, outs, count;
+  int64_t n[3];
+  bool operator<(const TuneKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (dim != o.dim) return dim < o.dim;
+    if (outs != o.outs) return outs < o.outs;
+    if (count != o.count) return count < o.count;
+    for (int a = 0; a < 3; ++a)
+      if (n[a] != o.n[a]) return n[a] < o.n[a];
+    return false;
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int, kPasses>> g_tune_cache;
+
+bool pass_tunable(int dim, int pass) {
+  return pass == kPassFused || (dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
+}
+
+// run(sched, events) enqueues one solve (or one group of entries) with the
+// given schedule, recording the pass boundaries into events when non-null.
+template <class Run>
+vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, hipError_t* herr) {
+  const int nint = dim == 3 ? 5 : 3;
+  static const int pass3[5] = {kPassR2C, kPassC2CF, kPassFused, kPassC2CI, kPassC2R};
+  static const int pass2[3] = {kPassR2C, kPassFused, kPassC2R};
+  const int* pass_of = dim == 3 ? pass3 : pass2;
+  std::vector<hipEvent_t> ev((size_t)reps * kMaxMarks, nullptr);
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  double t[vgf_tile_variants()][kPasses] = {};
+  vgf_status st = VGF_OK;
+  for (int v = 0; v < vgf_tile_variants() && st == VGF_OK && e == hipSuccess; ++v) {
+    int sched[kPasses];
+    for (int k = 0; k < kPasses; ++k) sched[k] = pass_tunable(dim, k) ? v : 0;
+    st = run(sched, nullptr);
+    for (int r = 0; r < reps && st == VGF_OK; ++r) st = run(sched, &ev[(size_t)r * kMaxMarks]);
+    if (st != VGF_OK) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      for (int i = 0; i < nint && e == hipSuccess; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[(size_t)r * kMaxMarks + i], ev[(size_t)r * kMaxMarks + i + 1]);
+        t[v][pass_of[i]] += ms;
+      }
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (st != VGF_OK) return st;
+  if (e != hipSuccess) {
+    *herr = e;
+    return VGF_ERR_HIP;
+  }
+  for (int k = 0; k < kPasses; ++k) {
+    best[k] = 0;
+    if (!pass_tunable(dim, k)) continue;
+    for (int v = 1; v < vgf_tile_variants(); ++v)
+      if (t[v][k] < t[best[k]][k]) best[k] = v;
+  }
+  return VGF_OK;
+}
+
+template <class Run>
+vgf_status tune_cached(vgf_plan p, bool want_phi, bool want_E, int count, int reps, hipStream_t s, Run run,
+                       int* sched_out, hipError_t* herr) {
+  TuneKey key{(int)p->prec, p->dim, (want_phi ? 1 : 0) | (want_E ? 2 : 0), count,
+              {p->n[0], p->n[1], p->dim == 3 ? p->n[2] : 0}};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (int k = 0; k < kPasses; ++k) sched_out[k] = it->second[k];
+      return VGF_OK;
+    }
+  }
+  int best[kPasses];
+  vgf_status st = tune_schedule(p->dim, reps, s, run, best, herr);
+  if (st != VGF_OK) return st;
+  std::array<int, kPasses> a{};
+  for (int k = 0; k < kPasses; ++k) a[k] = sched_out[k] = best[k];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = a;
   return VGF_OK;
 }
 
@@ -443,7 +552,7 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   en.E = E;
   en.want_phi = phi != nullptr;
   en.want_E = E != nullptr;
-  return enqueue_solve<T>(p, en, s, true);
+  return enqueue_solve<T>(p, en, s, true, p->schedule);
 }
 
 // Adjoint: the mirror image of solve_t. Forward passes sum their inputs
@@ -487,16 +596,16 @@ vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStre
     }
     const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, fa, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, p->schedule[kPassC2CF], fa, tw(1), s));
     if (g_E) {
       vgf::C2CFwdArgs<T> f0{{zb0, nullptr}, b.y + yfs, fg, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, f0, tw(1), s));
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, p->schedule[kPassC2CF], f0, tw(1), s));
     }
     g.in_fs = yfs;
-    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x2, g, spec, tw(0), s));
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], 0, true, b.y, b.x2, g, spec, tw(0), s));
     const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, ia, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, p->schedule[kPassC2CI], ia, tw(1), s));
     vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
     VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
   } else {
@@ -508,7 +617,7 @@ vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStre
       VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], r0, tw(1), s));
     }
     g.in_fs = yfs;
-    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], true, b.y, b.x1, g, spec, tw(0), s));
+    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], 0, true, b.y, b.x1, g, spec, tw(0), s));
     vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0, Hs, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2r<T>((int)p->P[1], ca, tw(1), s));
   }
@@ -691,6 +800,52 @@ vgf_status vgf_solve_batched(const vgf_plan* plans, int count, const void* const
   return VGF_OK;
 }
 
+vgf_status vgf_plan_autotune(vgf_plan p, const void* rho, void* phi, void* E, int reps, hipStream_t stream) {
+  vgf_status st = check_solve_args(p, rho, phi, E);
+  if (st != VGF_OK) return st;
+  if (reps <= 0) return VGF_ERR_INVALID_ARG;
+  auto run = [&](const int* sched, hipEvent_t* ev) -> vgf_status {
+    if (p->prec == VGF_F32) {
+      Entries<float> en;
+      en.ws = (char*)p->ws;
+      en.rho = (const float*)rho;
+      en.phi = (float*)phi;
+      en.E = (float*)E;
+      en.want_phi = phi != nullptr;
+      en.want_E = E != nullptr;
+      return enqueue_solve<float>(p, en, stream, false, sched, ev);
+    }
+    Entries<double> en;
+    en.ws = (char*)p->ws;
+    en.rho = (const double*)rho;
+    en.phi = (double*)phi;
+    en.E = (double*)E;
+    en.want_phi = phi != nullptr;
+    en.want_E = E != nullptr;
+    return enqueue_solve<double>(p, en, stream, false, sched, ev);
+  };
+  hipError_t herr = hipSuccess;
+  st = tune_cached(p, phi != nullptr, E != nullptr, 1, reps, stream, run, p->schedule, &herr);
+  if (herr != hipSuccess) p->last_err = herr;
+  return st;
+}
+
+vgf_status vgf_plan_get_schedule(vgf_plan p, int* schedule) {
+  if (!p || !schedule) return VGF_ERR_INVALID_ARG;
+  for (int k = 0; k < kPasses; ++k) schedule[k] = p->schedule[k];
+  return VGF_OK;
+}
+
+vgf_status vgf_plan_set_schedule(vgf_plan p, const int* schedule) {
+  if (!p || !schedule) return VGF_ERR_INVALID_ARG;
+  for (int k = 0; k < kPasses; ++k) {
+    if (schedule[k] < 0 || schedule[k] >= vgf_tile_variants()) return VGF_ERR_INVALID_ARG;
+    if (schedule[k] != 0 && !pass_tunable(p->dim, k)) return VGF_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < kPasses; ++k) p->schedule[k] = schedule[k];
+  return VGF_OK;
+}
+
 vgf_status vgf_plan_get_L(vgf_plan p, double* L) {
   if (!p || !L) return VGF_ERR_INVALID_ARG;
   *L = p->L;
@@ -783,6 +938,7 @@ struct vgf_batch_s {
     void** tab = nullptr;        // device [3][count]: rho, phi, E
     hipStream_t st = nullptr;    // capture branch
     hipEvent_t done = nullptr;
+    int schedule[5] = {0, 0, 0, 0, 0};  // tile variants of the group's launches
   };
   int count = 0;
   unsigned flags = 0;
@@ -830,7 +986,8 @@ void batch_release(vgf_batch b) {
 
 // the passes of one group, all entries per launch
 template <typename T>
-vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool want_E, hipStream_t s) {
+vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool want_E, hipStream_t s,
+                               const int* sched = nullptr, hipEvent_t* marks = nullptr) {
   const vgf_plan p = g.plan;
   const int c = (int)g.idx.size();
   Entries<T> en;
@@ -842,7 +999,7 @@ vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool 
   en.E_tab = want_E ? (T* const*)(g.tab + 2 * c) : nullptr;
   en.want_phi = want_phi;
   en.want_E = want_E;
-  return enqueue_solve<T>(p, en, s, false);
+  return enqueue_solve<T>(p, en, s, false, sched ? sched : g.schedule, marks);
 }
 
 vgf_status batch_enqueue_groups(vgf_batch b, bool want_phi, bool want_E, bool branches, hipStream_t s) {
@@ -893,6 +1050,49 @@ vgf_status batch_capture(vgf_batch b, bool want_phi, bool want_E) {
   return VGF_OK;
 }
 
+// Validates one call's pointers and refreshes the device pointer tables on
+// `stream` when they differ from the last ones written.
+vgf_status batch_set_tables(vgf_batch b, const void* const* rho, void* const* phi, void* const* E,
+                            hipStream_t stream) {
+  if (!b || !rho || (!phi && !E)) return VGF_ERR_INVALID_ARG;
+  const bool want_phi = phi != nullptr, want_E = E != nullptr;
+  const int n = b->count;
+  std::vector<void*> ptrs((size_t)3 * n, nullptr);
+  size_t k = 0;
+  for (auto& g : b->groups) {
+    const size_t c = g.idx.size();
+    for (size_t j = 0; j < c; ++j) {
+      const int i = g.idx[j];
+      vgf_status st = check_solve_args(g.plan, rho[i], want_phi ? phi[i] : nullptr, want_E ? E[i] : nullptr);
+      if (st != VGF_OK) return st;
+      if (want_phi != (phi && phi[i]) || want_E != (E && E[i])) return VGF_ERR_INVALID_ARG;
+      ptrs[k + j] = const_cast<void*>(rho[i]);
+      ptrs[k + c + j] = want_phi ? phi[i] : nullptr;
+      ptrs[k + 2 * c + j] = want_E ? E[i] : nullptr;
+    }
+    k += 3 * c;
+  }
+  if (b->tab_valid && ptrs == b->cur) return VGF_OK;
+  k = 0;
+  for (auto& g : b->groups) {
+    const size_t c3 = 3 * g.idx.size();
+    for (size_t o = 0; o < c3; o += vgf::PtrChunk::kMax) {
+      vgf::PtrChunk ch{};
+      ch.n = (int)std::min<size_t>(vgf::PtrChunk::kMax, c3 - o);
+      for (int j = 0; j < ch.n; ++j) ch.p[j] = ptrs[k + o + j];
+      hipError_t e = vgf::launch_set_pointers(g.tab + o, ch, stream);
+      if (e != hipSuccess) {
+        b->tab_valid = false;
+        return batch_hip(b, e);
+      }
+    }
+    k += c3;
+  }
+  b->cur = ptrs;
+  b->tab_valid = true;
+  return VGF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -919,6 +1119,7 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
       b->groups.emplace_back();
       hit = &b->groups.back();
       hit->plan = p;
+      for (int k = 0; k < kPasses; ++k) hit->schedule[k] = p->schedule[k];
     }
     hit->idx.push_back(i);
   }
@@ -949,50 +1150,47 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
 
 vgf_status vgf_batch_solve(vgf_batch b, const void* const* rho, void* const* phi, void* const* E,
                            hipStream_t stream) {
-  if (!b || !rho || (!phi && !E)) return VGF_ERR_INVALID_ARG;
+  vgf_status st = batch_set_tables(b, rho, phi, E, stream);
+  if (st != VGF_OK) return st;
   const bool want_phi = phi != nullptr, want_E = E != nullptr;
-  const int n = b->count;
-  std::vector<void*> ptrs((size_t)3 * n, nullptr);
-  size_t k = 0;
-  for (auto& g : b->groups) {
-    const size_t c = g.idx.size();
-    for (size_t j = 0; j < c; ++j) {
-      const int i = g.idx[j];
-      vgf_status st = check_solve_args(g.plan, rho[i], want_phi ? phi[i] : nullptr, want_E ? E[i] : nullptr);
-      if (st != VGF_OK) return st;
-      if (want_phi != (phi && phi[i]) || want_E != (E && E[i])) return VGF_ERR_INVALID_ARG;
-      ptrs[k + j] = const_cast<void*>(rho[i]);
-      ptrs[k + c + j] = want_phi ? phi[i] : nullptr;
-      ptrs[k + 2 * c + j] = want_E ? E[i] : nullptr;
-    }
-    k += 3 * c;
-  }
-  if (!b->tab_valid || ptrs != b->cur) {
-    k = 0;
-    for (auto& g : b->groups) {
-      const size_t c3 = 3 * g.idx.size();
-      for (size_t o = 0; o < c3; o += vgf::PtrChunk::kMax) {
-        vgf::PtrChunk ch{};
-        ch.n = (int)std::min<size_t>(vgf::PtrChunk::kMax, c3 - o);
-        for (int j = 0; j < ch.n; ++j) ch.p[j] = ptrs[k + o + j];
-        hipError_t e = vgf::launch_set_pointers(g.tab + o, ch, stream);
-        if (e != hipSuccess) {
-          b->tab_valid = false;
-          return batch_hip(b, e);
-        }
-      }
-      k += c3;
-    }
-    b->cur = ptrs;
-    b->tab_valid = true;
-  }
   if (!(b->flags & VGF_BATCH_GRAPH)) return batch_enqueue_groups(b, want_phi, want_E, false, stream);
   const int outs = (want_phi ? 1 : 0) | (want_E ? 2 : 0);
   if (!b->exec || b->graph_outputs != outs) {
-    vgf_status st = batch_capture(b, want_phi, want_E);
+    st = batch_capture(b, want_phi, want_E);
     if (st != VGF_OK) return st;
   }
   return batch_hip(b, hipGraphLaunch(b->exec, stream));
+}
+
+vgf_status vgf_batch_autotune(vgf_batch b, const void* const* rho, void* const* phi, void* const* E,
+                              int reps, hipStream_t stream) {
+  if (!b || reps <= 0) return VGF_ERR_INVALID_ARG;
+  vgf_status st = batch_set_tables(b, rho, phi, E, stream);
+  if (st != VGF_OK) return st;
+  const bool want_phi = phi != nullptr, want_E = E != nullptr;
+  for (auto& g : b->groups) {
+    const int count = (int)g.idx.size();
+    auto run = [&](const int* sched, hipEvent_t* ev) -> vgf_status {
+      vgf_status r = g.plan->prec == VGF_F32 ? batch_group_enqueue<float>(g, want_phi, want_E, stream, sched, ev)
+                                             : batch_group_enqueue<double>(g, want_phi, want_E, stream, sched, ev);
+      if (r == VGF_ERR_HIP) b->last_err = g.plan->last_err;
+      return r;
+    };
+    hipError_t herr = hipSuccess;
+    st = tune_cached(g.plan, want_phi, want_E, count, reps, stream, run, g.schedule, &herr);
+    if (st != VGF_OK) {
+      if (herr != hipSuccess) b->last_err = herr;
+      return st;
+    }
+  }
+  batch_drop_graph(b);  // the next solve captures the tuned launches
+  return VGF_OK;
+}
+
+vgf_status vgf_batch_get_schedule(vgf_batch b, int group, int* schedule) {
+  if (!b || !schedule || group < 0 || group >= (int)b->groups.size()) return VGF_ERR_INVALID_ARG;
+  for (int k = 0; k < kPasses; ++k) schedule[k] = b->groups[(size_t)group].schedule[k];
+  return VGF_OK;
 }
 
 vgf_status vgf_batch_workspace_bytes(vgf_batch b, size_t* bytes) {

@@ -94,8 +94,8 @@ template <typename T> struct C2CInvArgs {
 
 // Geometry of the axis-0 (outermost) fused pass. Forward: one input, outputs
 // fields[f] in {0: times the kernel spectrum, 1: times -i k_0 and the kernel
-// spectrum}, at out + f*out_fs. Adjoint: inputs fields[f] at in + f*in_fs,
-// summed with the conjugate factors, one output.
+// spectrum}, at out + f*out_fs; fields must be {0} or {0, 1}. Adjoint: inputs
+// fields[f] at in + f*in_fs, summed with the conjugate factors, one output.
 template <typename T> struct FusedGeom {
   int64_t ncols;     // columns of the inner plane: P1*hs (3D) or hs (2D)
   int64_t out_fs;
@@ -115,12 +115,16 @@ template <typename T>
 hipError_t launch_r2c(int P, const R2CArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_c2r(int P, const C2RArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+// Number of tile-schedule variants of the strided passes (see TileV).
+constexpr int kTileVariantsHost = 2;
+// The strided passes take a tile-schedule variant (0 or 1, see TileV):
+// every variant computes identical results; only the launch shape differs.
 template <typename T>
-hipError_t launch_c2c_fwd(int P, const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+hipError_t launch_c2c_fwd(int P, int variant, const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_c2c_inv(int P, const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+hipError_t launch_c2c_inv(int P, int variant, const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
-hipError_t launch_fused(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,
+hipError_t launch_fused(int P, int variant, bool adjoint, const cplx<T>* in, cplx<T>* out,
                         const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
 
 // ---- batched solves ----

@@ -61,6 +61,15 @@ template <typename T, int P, int NL_FORCE = 0> struct Tile {
   static constexpr int MINW_PP = lds_waves_per_simd((2 * P * NL + P) * CB, NT);
 };
 
+// Tile schedules of the strided passes: variant 0 uses the default tile
+// width (one 128-byte row segment per position), variant 1 half of it (more,
+// smaller workgroups: less padding waste on narrow planes, more workgroups
+// per CU). Every column is transformed with the same arithmetic in both, so
+// the choice never changes a result bit.
+constexpr int kTileVariants = kTileVariantsHost;
+template <typename T, int P, int V>
+struct TileV : Tile<T, P, (V == 0 ? 0 : (Tile<T, P>::NL > 1 ? Tile<T, P>::NL / 2 : 1))> {};
+
 // signed frequency of index k on a length-2N axis, Nyquist index N -> 0
 __device__ __forceinline__ int signed_freq_zn(int k, int N) {
   return k < N ? k : (k == N ? 0 : k - 2 * N);
@@ -320,11 +329,11 @@ __device__ __forceinline__ T axis_k(T ks, int j, int r) {
 // k_c2c_fwd: out = sum_t m_t(pos) FFT(in_t) along a strided axis, pruned input
 // grid = (ceil(ncols/NL), nbatch)
 // ---------------------------------------------------------------------------
-template <typename T, int P, int NTERM>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_fwd(C2CFwdArgs<T> a,
-                                                             const cplx<T>* __restrict__ tw) {
+template <typename T, int P, int NTERM, int V>
+__global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void k_c2c_fwd(C2CFwdArgs<T> a,
+                                                                     const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  using TL = Tile<T, P>;
+  using TL = TileV<T, P, V>;
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
@@ -371,11 +380,11 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_fw
 // ---------------------------------------------------------------------------
 // k_c2c_inv: out_o = first P/2 of IFFT(m_o(pos) in) along a strided axis
 // ---------------------------------------------------------------------------
-template <typename T, int P, int NOUT>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_inv(C2CInvArgs<T> a,
-                                                             const cplx<T>* __restrict__ tw) {
+template <typename T, int P, int NOUT, int V>
+__global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void k_c2c_inv(C2CInvArgs<T> a,
+                                                                     const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
-  using TL = Tile<T, P>;
+  using TL = TileV<T, P, V>;
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
@@ -420,16 +429,12 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_c2c_in
   }
 }
 
-// Tile of the fused axis-0 pass (columns per workgroup may differ from the
-// other strided passes: it holds two LDS tiles and more registers).
-#ifndef VGF_FUSED_NL32
-#define VGF_FUSED_NL32 0
-#endif
-#ifndef VGF_FUSED_NL64
-#define VGF_FUSED_NL64 0
-#endif
-template <typename T, int P>
-using TileF = Tile<T, P, (sizeof(T) == 4 ? VGF_FUSED_NL32 : VGF_FUSED_NL64)>;
+// Tile of the fused axis-0 pass (two LDS tiles, more registers).
+template <typename T, int P, int V> struct TileF : TileV<T, P, V> {
+  // inverse fields as two straight-line copies (measured faster in FP64;
+  // in FP32 at 1024 threads the copies exceed 128 VGPRs and spill)
+  static constexpr bool SPLIT_FIELDS = sizeof(T) == 8;
+};
 
 // Kernel-spectrum addressing for the axis-0 lines: column c of the inner
 // plane (3D: (k1, k2) of [P1][H2]; 2D: k1 of [H1]) reads the octant at
@@ -490,15 +495,15 @@ template <typename T> struct SpecIdx {
 // barrier-separated transforms of the current tile, so HBM traffic overlaps
 // the FFT arithmetic of the same CU.
 // ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_fused(const cplx<T>* __restrict__ in,
+template <typename T, int P, int V>
+__global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) void k_fused(const cplx<T>* __restrict__ in,
                                                            cplx<T>* __restrict__ out,
                                                            FusedGeom<T> g,
                                                            const T* __restrict__ spec,
                                                            const cplx<T>* __restrict__ tw,
                                                            int ntiles) {
   using C = cplx<T>;
-  using TL = TileF<T, P>;
+  using TL = TileF<T, P, V>;
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
@@ -599,9 +604,20 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
         rh.v[t][r].y *= sv[t][r];
       }
 
-    for (int fi = 0; fi < g.nf; ++fi) {
-      typename IS0::Regs v;
-      if (g.fields[fi] == 0) {
+    // inverse of one output field (fi = 0: phi's spectrum, 1: E_0's), stored
+    auto inverse_store = [&](typename IS0::Regs& v, int fi) {
+      IS0::butterflies(v, q);
+      typename ISL::Regs o;
+      transform_pp<T, P, NT, NL, LP, 1>(v, o, pp, twl, l, q);
+      if (fc.io.valid) {
+        C* __restrict__ dst = out + e * g.out_es + fi * g.out_fs;
+        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[fc.io.template off<ISL::NB>(j, r)] = val; });
+      }
+    };
+    // field 0 always (phi's spectrum, also the source of E_1 and E_2 later);
+    // field 1 (-i k_0 times it) when E is requested.
+    auto field_input = [&](typename IS0::Regs& v, bool d0) {
+      if (!d0) {
 #pragma unroll
         for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
@@ -616,12 +632,25 @@ __global__ __launch_bounds__((TileF<T, P>::NT), (TileF<T, P>::MINW_PP)) void k_f
             v.v[t][r] = deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks0, j, r));
         }
       }
-      IS0::butterflies(v, q);
-      typename ISL::Regs o;
-      transform_pp<T, P, NT, NL, LP, 1>(v, o, pp, twl, l, q);
-      if (fc.io.valid) {
-        C* __restrict__ dst = out + e * g.out_es + fi * g.out_fs;
-        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[fc.io.template off<ISL::NB>(j, r)] = val; });
+    };
+    if constexpr (TL::SPLIT_FIELDS) {
+      // two straight-line copies: no per-element selection between factors
+      {
+        typename IS0::Regs v;
+        field_input(v, false);
+        inverse_store(v, 0);
+      }
+      if (g.nf > 1) {
+        typename IS0::Regs v;
+        field_input(v, true);
+        inverse_store(v, 1);
+      }
+    } else {
+      // one copy in a loop (fits the register budget of the wider tiles)
+      for (int fi = 0; fi < g.nf; ++fi) {
+        typename IS0::Regs v;
+        field_input(v, g.fields[fi] != 0);
+        inverse_store(v, fi);
       }
     }
     if (!more) break;
@@ -742,75 +771,96 @@ hipError_t launch_c2r_p(const C2RArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int P>
-hipError_t launch_c2c_fwd_p(const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
-  using TL = Tile<T, P>;
+template <typename T, int P, int V>
+hipError_t launch_c2c_fwd_v(const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  using TL = TileV<T, P, V>;
   const int64_t bx = (a.g.ncols + TL::NL - 1) / TL::NL;
   const int64_t by = (int64_t)a.g.nbatch * a.g.nentry;
   if (bx == 0 || by == 0 || a.d.n == 0) return hipSuccess;
   if (by > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)bx, (unsigned)by);
   if (a.d.n == 2)
-    hipLaunchKernelGGL((k_c2c_fwd<T, P, 2>), grid, dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_c2c_fwd<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw);
   else
-    hipLaunchKernelGGL((k_c2c_fwd<T, P, 1>), grid, dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_c2c_fwd<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw);
   return hipGetLastError();
 }
 
-template <typename T, int P>
-hipError_t launch_c2c_inv_p(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
-  using TL = Tile<T, P>;
+template <typename T, int P, int V>
+hipError_t launch_c2c_inv_v(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  using TL = TileV<T, P, V>;
   const int64_t bx = (a.g.ncols + TL::NL - 1) / TL::NL;
   const int64_t by = (int64_t)a.g.nbatch * a.g.nentry;
   if (bx == 0 || by == 0 || a.d.n == 0) return hipSuccess;
   if (by > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)bx, (unsigned)by);
   if (a.d.n == 2)
-    hipLaunchKernelGGL((k_c2c_inv<T, P, 2>), grid, dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_c2c_inv<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw);
   else
-    hipLaunchKernelGGL((k_c2c_inv<T, P, 1>), grid, dim3(TL::NT), 0, s, a, tw);
+    hipLaunchKernelGGL((k_c2c_inv<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int P, int V>
+hipError_t launch_fused_v(const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g, const T* spec,
+                          const cplx<T>* tw, hipStream_t s) {
+  using TL = TileF<T, P, V>;
+  const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
+  if (bx == 0) return hipSuccess;
+  // one persistent workgroup per resident slot
+  static int slots = 0;
+  if (slots == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fused<T, P, V>, TL::NT, 0) !=
+            hipSuccess)
+      return hipGetLastError();
+    slots = cus * (per_cu > 0 ? per_cu : 1);
+  }
+  const int64_t total = bx * g.nentry;
+  if (total > INT32_MAX) return hipErrorInvalidConfiguration;
+  const int grid = (int)(total < slots ? total : slots);
+  hipLaunchKernelGGL((k_fused<T, P, V>), dim3((unsigned)grid), dim3(TL::NT), 0, s, in, out, g, spec, tw,
+                     (int)bx);
   return hipGetLastError();
 }
 
 template <typename T, int P>
-hipError_t launch_fused_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
+hipError_t launch_c2c_fwd_p(int variant, const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  return variant == 1 ? launch_c2c_fwd_v<T, P, 1>(a, tw, s) : launch_c2c_fwd_v<T, P, 0>(a, tw, s);
+}
+
+template <typename T, int P>
+hipError_t launch_c2c_inv_p(int variant, const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  return variant == 1 ? launch_c2c_inv_v<T, P, 1>(a, tw, s) : launch_c2c_inv_v<T, P, 0>(a, tw, s);
+}
+
+template <typename T, int P>
+hipError_t launch_fused_p(int variant, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
                           const T* spec, const cplx<T>* tw, hipStream_t s) {
   if (g.nf == 0 || g.nentry == 0) return hipSuccess;
+  // forward outputs are field 0 (times the kernel spectrum), then optionally
+  // field 1 (times -i k_0 and the kernel spectrum), in this order
+  if (!adjoint && (g.fields[0] != 0 || (g.nf > 1 && g.fields[1] != 1) || g.nf > 2))
+    return hipErrorInvalidValue;
   if (adjoint) {
     if (g.nentry != 1) return hipErrorInvalidValue;  // the adjoint runs one entry per launch
     using TL = Tile<T, P>;
     const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
     if (bx == 0) return hipSuccess;
     hipLaunchKernelGGL((k_fused_adj<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, spec, tw);
-  } else {
-    using TL = TileF<T, P>;
-    const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
-    if (bx == 0) return hipSuccess;
-    // one persistent workgroup per resident slot
-    static int slots = 0;
-    if (slots == 0) {
-      int dev = 0, cus = 0, per_cu = 0;
-      if (hipGetDevice(&dev) != hipSuccess ||
-          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fused<T, P>, TL::NT, 0) !=
-              hipSuccess)
-        return hipGetLastError();
-      slots = cus * (per_cu > 0 ? per_cu : 1);
-    }
-    const int64_t total = bx * g.nentry;
-    if (total > INT32_MAX) return hipErrorInvalidConfiguration;
-    const int grid = (int)(total < slots ? total : slots);
-    hipLaunchKernelGGL((k_fused<T, P>), dim3((unsigned)grid), dim3(TL::NT), 0, s, in, out, g, spec, tw,
-                       (int)bx);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  return variant == 1 ? launch_fused_v<T, P, 1>(in, out, g, spec, tw, s)
+                      : launch_fused_v<T, P, 0>(in, out, g, spec, tw, s);
 }
 
 #define VGF_CASE_R2C(PP) case PP: return launch_r2c_p<VGF_T, PP>(a, tw, s);
 #define VGF_CASE_C2R(PP) case PP: return launch_c2r_p<VGF_T, PP>(a, tw, s);
-#define VGF_CASE_C2CF(PP) case PP: return launch_c2c_fwd_p<VGF_T, PP>(a, tw, s);
-#define VGF_CASE_C2CI(PP) case PP: return launch_c2c_inv_p<VGF_T, PP>(a, tw, s);
-#define VGF_CASE_FUSED(PP) case PP: return launch_fused_p<VGF_T, PP>(adjoint, in, out, g, spec, tw, s);
+#define VGF_CASE_C2CF(PP) case PP: return launch_c2c_fwd_p<VGF_T, PP>(variant, a, tw, s);
+#define VGF_CASE_C2CI(PP) case PP: return launch_c2c_inv_p<VGF_T, PP>(variant, a, tw, s);
+#define VGF_CASE_FUSED(PP) case PP: return launch_fused_p<VGF_T, PP>(variant, adjoint, in, out, g, spec, tw, s);
 
 #define VGF_DEFINE_DISPATCH(T)                                                                  \
   template <>                                                                                   \
@@ -822,17 +872,17 @@ hipError_t launch_fused_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const F
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2R) default: return hipErrorInvalidValue; }           \
   }                                                                                             \
   template <>                                                                                   \
-  hipError_t launch_c2c_fwd<T>(int P, const C2CFwdArgs<T>& a, const cplx<T>* tw,               \
+  hipError_t launch_c2c_fwd<T>(int P, int variant, const C2CFwdArgs<T>& a, const cplx<T>* tw,  \
                                hipStream_t s) {                                                 \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2CF) default: return hipErrorInvalidValue; }          \
   }                                                                                             \
   template <>                                                                                   \
-  hipError_t launch_c2c_inv<T>(int P, const C2CInvArgs<T>& a, const cplx<T>* tw,               \
+  hipError_t launch_c2c_inv<T>(int P, int variant, const C2CInvArgs<T>& a, const cplx<T>* tw,  \
                                hipStream_t s) {                                                 \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2CI) default: return hipErrorInvalidValue; }          \
   }                                                                                             \
   template <>                                                                                   \
-  hipError_t launch_fused<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,              \
+  hipError_t launch_fused<T>(int P, int variant, bool adjoint, const cplx<T>* in, cplx<T>* out, \
                              const FusedGeom<T>& g, const T* spec, const cplx<T>* tw,           \
                              hipStream_t s) {                                                   \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_FUSED) default: return hipErrorInvalidValue; }         \

@@ -26,7 +26,8 @@ EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batch
            "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
            "vgf_status_string", "vgf_plan_profile_begin", "vgf_plan_profile_end",
            "vgf_batch_create", "vgf_batch_solve", "vgf_batch_workspace_bytes", "vgf_batch_groups",
-           "vgf_batch_hip_error", "vgf_batch_destroy"]
+           "vgf_batch_hip_error", "vgf_batch_destroy", "vgf_plan_autotune", "vgf_plan_get_schedule",
+           "vgf_plan_set_schedule", "vgf_batch_autotune", "vgf_batch_get_schedule"]
 BATCH_GRAPH = 1
 PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused_axis0", "c2c_inv", "c2r"],
               2: ["r2c", "fused_axis0", "c2r"]}
@@ -89,6 +90,17 @@ def lib():
         L.vgf_batch_hip_error.argtypes = [vp]
         L.vgf_batch_destroy.restype = None
         L.vgf_batch_destroy.argtypes = [vp]
+        ip = C.POINTER(C.c_int)
+        L.vgf_plan_autotune.restype = C.c_int
+        L.vgf_plan_autotune.argtypes = [vp, vp, vp, vp, C.c_int, vp]
+        L.vgf_plan_get_schedule.restype = C.c_int
+        L.vgf_plan_get_schedule.argtypes = [vp, ip]
+        L.vgf_plan_set_schedule.restype = C.c_int
+        L.vgf_plan_set_schedule.argtypes = [vp, ip]
+        L.vgf_batch_autotune.restype = C.c_int
+        L.vgf_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int, vp]
+        L.vgf_batch_get_schedule.restype = C.c_int
+        L.vgf_batch_get_schedule.argtypes = [vp, C.c_int, ip]
         _lib = L
     return _lib
 
@@ -217,6 +229,30 @@ class Plan:
         _check(st, "vgf_solve_adjoint")
         return g_rho
 
+    @property
+    def schedule(self):
+        """Tile variant per pass (r2c, c2c fwd, fused axis 0, c2c inv, c2r)."""
+        v = (C.c_int * 5)()
+        _check(lib().vgf_plan_get_schedule(self.handle, v), "vgf_plan_get_schedule")
+        return tuple(v)
+
+    @schedule.setter
+    def schedule(self, sched):
+        v = (C.c_int * 5)(*[int(x) for x in sched])
+        _check(lib().vgf_plan_set_schedule(self.handle, v), "vgf_plan_set_schedule")
+
+    def autotune(self, rho, phi=None, E=None, reps=3, stream=None):
+        """Measure every tile schedule on this call's buffers and keep the fastest per pass."""
+        torch = _torch()
+        self._check_tensor(rho, self.n, "rho")
+        if phi is None and "phi" in self.outputs:
+            phi = torch.empty(self.n, dtype=self.dtype, device=rho.device)
+        if E is None and "E" in self.outputs:
+            E = torch.empty((self.dim,) + self.n, dtype=self.dtype, device=rho.device)
+        _check(lib().vgf_plan_autotune(self.handle, _ptr(rho), _ptr(phi), _ptr(E), int(reps), _stream(stream)),
+               "vgf_plan_autotune")
+        return self.schedule
+
     def profile_begin(self, max_solves):
         _check(lib().vgf_plan_profile_begin(self.handle, int(max_solves)), "vgf_plan_profile_begin")
 
@@ -294,6 +330,10 @@ class Batch:
     def solve(self, rhos, phis=None, Es=None, stream=None):
         """rhos, phis, Es: lists of tensors shaped for each entry's plan
         (phis / Es None: that output is skipped for every entry)."""
+        rh, ph, ee = self._arrays(rhos, phis, Es)
+        _check(lib().vgf_batch_solve(self.handle, rh, ph, ee, _stream(stream)), "vgf_batch_solve")
+
+    def _arrays(self, rhos, phis, Es):
         count = len(self.plans)
         if len(rhos) != count or (phis is not None and len(phis) != count) or (
                 Es is not None and len(Es) != count):
@@ -308,7 +348,22 @@ class Batch:
         rh = (VP * count)(*[r.data_ptr() for r in rhos])
         ph = (VP * count)(*[x.data_ptr() for x in phis]) if phis is not None else None
         ee = (VP * count)(*[x.data_ptr() for x in Es]) if Es is not None else None
-        _check(lib().vgf_batch_solve(self.handle, rh, ph, ee, _stream(stream)), "vgf_batch_solve")
+        return rh, ph, ee
+
+    def autotune(self, rhos, phis=None, Es=None, reps=3, stream=None):
+        """Tune every group's tile schedule on these buffers; returns the schedules."""
+        rh, ph, ee = self._arrays(rhos, phis, Es)
+        _check(lib().vgf_batch_autotune(self.handle, rh, ph, ee, int(reps), _stream(stream)),
+               "vgf_batch_autotune")
+        return self.schedules()
+
+    def schedules(self):
+        out = []
+        for g in range(self.groups):
+            v = (C.c_int * 5)()
+            _check(lib().vgf_batch_get_schedule(self.handle, g, v), "vgf_batch_get_schedule")
+            out.append(tuple(v))
+        return out
 
     def close(self):
         if self._h is not None:

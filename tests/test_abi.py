@@ -119,3 +119,13 @@ def test_null_batch_calls_fail_cleanly(V):
     assert L.vgf_batch_workspace_bytes(None, C.byref(s)) == -1
     assert L.vgf_batch_groups(None) == 0
     L.vgf_batch_destroy(None)
+
+
+def test_null_schedule_calls_fail_cleanly(V):
+    L = V.lib()
+    sched = (C.c_int * 5)()
+    assert L.vgf_plan_get_schedule(None, sched) == -1
+    assert L.vgf_plan_set_schedule(None, sched) == -1
+    assert L.vgf_plan_autotune(None, None, None, None, 3, None) == -1
+    assert L.vgf_batch_autotune(None, None, None, None, 3, None) == -1
+    assert L.vgf_batch_get_schedule(None, 0, sched) == -1
