@@ -58,9 +58,29 @@ typedef enum {
   VGF_ERR_NOT_REQUESTED = -6     /* an output that the plan was not created for */
 } vgf_status;
 
-typedef enum { VGF_METHOD_VGF = 0, VGF_METHOD_HE = 1 } vgf_method;
+/* VGF: Vico-Greengard-Ferrando (Sec. II). HE: Hockney-Eastwood (Eq. 3) with
+ * the origin weight vol * G0, G0 = 1/(4 pi) in 3D, 1/(2 pi) in 2D (the
+ * singular factor replaced by 1). HE_NEARBY: origin weight vol * G(r0) at
+ * r0 = half the smallest spacing ("nearby value" of the comparison figures,
+ * Sec. III.A). HE_CELLAVG: origin weight = the integral of G over the cell
+ * prod_a [-h_a/2, h_a/2] ("cell average"). All HE variants share w[n] =
+ * vol * G(|n h|) for n != 0, vol = prod_a h_a. */
+typedef enum {
+  VGF_METHOD_VGF = 0,
+  VGF_METHOD_HE = 1,
+  VGF_METHOD_HE_NEARBY = 2,
+  VGF_METHOD_HE_CELLAVG = 3
+} vgf_method;
 typedef enum { VGF_F64 = 0, VGF_F32 = 1 } vgf_precision;
-enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u };
+/* Outputs a plan may return, and how E is obtained:
+ *   VGF_OUT_PHI, VGF_OUT_E : the fields later solves may return;
+ *   VGF_FIELD_CENTERED     : (with VGF_OUT_E) E = -D phi by second-order
+ *     finite differences of the computed phi -- centred at interior points,
+ *     one-sided (-3, 4, -1)/(2h) on the first and (3, -4, 1)/(2h) on the last
+ *     plane of each axis -- instead of Fourier differentiation. This is the
+ *     "Finite Diff" field of the comparison figures (Sec. III.A); Fourier
+ *     differentiation is the default. Not accepted by vgf_batch_create. */
+enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u, VGF_FIELD_CENTERED = 16u };
 
 /* Build a plan for a fixed grid (Sec. II: one precomputation per grid, then
  * a solve per right-hand side).
@@ -77,7 +97,8 @@ enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u };
  *              (diameter, min_a(4 n_a h_a - (n_a - 1) h_a)): below it the
  *              truncated kernel misses source-target pairs (Sec. II), above
  *              it the 4N-periodic images reach the box. Ignored for HE.
- *   outputs  : VGF_OUT_PHI | VGF_OUT_E, the fields later solves may return.
+ *   outputs  : VGF_OUT_PHI | VGF_OUT_E, the fields later solves may return,
+ *              optionally | VGF_FIELD_CENTERED (requires VGF_OUT_E).
  *   stream   : stream on which the FP64 precompute runs; the call
  *              synchronises it before returning.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, L_WINDOW, OUT_OF_MEMORY, HIP. On
@@ -133,8 +154,8 @@ vgf_status vgf_solve_batched(const vgf_plan* plans, int count, const void* const
 typedef struct vgf_batch_s* vgf_batch;
 enum { VGF_BATCH_GRAPH = 1u };
 
-/* plans[0..count): the plan of each entry (non-NULL, count >= 1). flags: 0 or
- * VGF_BATCH_GRAPH. Allocates the group workspaces (VGF_ERR_OUT_OF_MEMORY
+/* plans[0..count): the plan of each entry (non-NULL, count >= 1, not created
+ * with VGF_FIELD_CENTERED). flags: 0 or VGF_BATCH_GRAPH. Allocates the group workspaces (VGF_ERR_OUT_OF_MEMORY
  * beyond VGF_MAX_WORKSPACE). Enqueues nothing. */
 vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, unsigned flags);
 

@@ -26,6 +26,13 @@ def lib():
         L.orc_window.argtypes = [C.c_int, i64p, dp, dp, dp]
         L.orc_vgf_kernel.argtypes = [C.c_int, i64p, dp, d, dp]
         L.orc_he_kernel.argtypes = [C.c_int, i64p, dp, dp]
+        L.orc_he_kernel_mode.argtypes = [C.c_int, i64p, dp, C.c_int, dp]
+        L.orc_he_origin.restype = d
+        L.orc_he_origin.argtypes = [C.c_int, dp, C.c_int]
+        L.orc_cell_average_integral.restype = d
+        L.orc_cell_average_integral.argtypes = [C.c_int, dp]
+        L.orc_fd_field.argtypes = [C.c_int, i64p, dp, dp, dp]
+        L.orc_fd_field_T.argtypes = [C.c_int, i64p, dp, dp, dp]
         L.orc_periodic_kernel.argtypes = [C.c_int, i64p, dp, dp]
         L.orc_field_kernel.argtypes = [C.c_int, i64p, dp, dp, C.c_int, dp]
         L.orc_conv_direct.argtypes = [C.c_int, i64p, dp, dp, dp]
@@ -119,13 +126,51 @@ def vgf_kernel(n, h, L):
     return w
 
 
-def he_kernel(n, h):
+HE_MODES = {"he": 0, "he_nearby": 1, "he_cellavg": 2}
+
+
+def he_kernel(n, h, mode=0):
+    """Hockney-Eastwood kernel; mode 0 (G0 convention), 1 (nearby value),
+    2 (cell average) for the origin weight."""
     dim = len(n)
     n_, pn = _i64(n)
     h_, ph = _f64(h)
     w, pw = _out(tuple(n))
-    assert lib().orc_he_kernel(dim, pn, ph, pw) == 0
+    assert lib().orc_he_kernel_mode(dim, pn, ph, int(mode), pw) == 0
     return w
+
+
+def he_origin(h, mode):
+    h_, ph = _f64(h)
+    return lib().orc_he_origin(len(h), ph, int(mode))
+
+
+def cell_average_integral(h):
+    """Integral of G over the cell prod_a [-h_a/2, h_a/2]."""
+    h_, ph = _f64(h)
+    return lib().orc_cell_average_integral(len(h), ph)
+
+
+def fd_field(n, h, phi):
+    """E = -D phi, second-order differences (centred inside, one-sided ends)."""
+    dim = len(n)
+    n_, pn = _i64(n)
+    h_, ph = _f64(h)
+    p_, pp = _f64(phi)
+    E, pE = _out((dim,) + tuple(n))
+    assert lib().orc_fd_field(dim, pn, ph, pp, pE) == 0
+    return E
+
+
+def fd_field_T(n, h, gE):
+    """-sum_a D_a^T gE[a]: the transpose of fd_field."""
+    dim = len(n)
+    n_, pn = _i64(n)
+    h_, ph = _f64(h)
+    g_, pg = _f64(gE)
+    out, po = _out(tuple(n))
+    assert lib().orc_fd_field_T(dim, pn, ph, pg, po) == 0
+    return out
 
 
 def periodic_kernel(n, w_oct):
@@ -321,8 +366,8 @@ def kernel(method, n, h, L=None):
     """Octant kernel for 'vgf' or 'he'."""
     if method == "vgf":
         return vgf_kernel(n, h, default_L(n, h) if L is None else L)
-    if method == "he":
-        return he_kernel(n, h)
+    if method in HE_MODES:
+        return he_kernel(n, h, HE_MODES[method])
     raise ValueError(method)
 
 

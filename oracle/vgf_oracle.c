@@ -30,9 +30,15 @@
  * Arrays are C-contiguous, last axis fastest. dim is 2 or 3. For dim == 2
  * only n[0], n[1] (and h[0], h[1]) are read.
  *
+ *   - the Hockney-Eastwood variants of the comparison figures (Sec. III.A):
+ *     "nearby value" (G at half a spacing) and "cell average" (the integral
+ *     of G over the origin cell, by pyramids and Gauss-Legendre), and the
+ *     second-order finite-difference field and its transpose.
+ *
  * Parity unpinned: the Hockney-Eastwood origin constant G0 (1/(4 pi) in 3D,
  * 1/(2 pi) in 2D) is a reading of the paper's "G(0)=1" and its figure legend;
- * nothing outside the paper fixes it.
+ * nothing outside the paper fixes it. Likewise the "nearby value" distance
+ * (half the smallest spacing) is a reading of a figure legend.
  */
 #include <complex.h>
 #include <math.h>
@@ -226,8 +232,108 @@ int orc_vgf_kernel(int dim, const int64_t* n, const double* h, double L,
  * G0 = 1/(4 pi) in 3D and 1/(2 pi) in 2D (Sec. I, "G(0)=1", and the figure
  * legend of Sec. III.A). Parity unpinned beyond this convention.
  * Octant n_a in [0, N_a). */
+/* Gauss-Legendre nodes and weights on [0, 1] (m points): Newton iteration
+ * on P_m from the Chebyshev guesses, the three-term recurrence for P_m. */
+static void gauss_legendre01(int m, double* x, double* wt) {
+  for (int i = 0; i < m; ++i) {
+    double z = cos(ORC_PI * (i + 0.75) / (m + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[i] = 0.5 * (1.0 - z);
+    wt[i] = 1.0 / ((1.0 - z * z) * dp * dp);  /* 2/((1-z^2)P'^2), halved for [0,1] */
+  }
+}
+
+/* Integral of G over the cell prod_a [-h_a/2, h_a/2] around the origin,
+ * by symmetry 2^d times the integral over the corner box [0, h_a/2]. The
+ * corner box is split into d pyramids with apex at the origin, one per far
+ * face; on the pyramid over the face x_a = c_a the points are t * (face
+ * point), t in [0, 1]. The t-integral is done in closed form, leaving a
+ * smooth integral over the face, done with tensor Gauss-Legendre:
+ *   3D, G = 1/(4 pi r): int_0^1 t^2 c_a /(t R) dt = c_a / (2 R);
+ *   2D, G = -ln(r)/(2 pi): int_0^1 t c_a (-ln t - ln R) dt = c_a (1/4 - ln(R)/2);
+ * R = |face point|. */
+double orc_cell_average_integral(int dim, const double* h) {
+  enum { M = 48 };
+  double x[M], wt[M];
+  gauss_legendre01(M, x, wt);
+  double c[3];
+  for (int a = 0; a < dim; ++a) c[a] = 0.5 * h[a];
+  double total = 0.0;
+  if (dim == 3) {
+    for (int a = 0; a < 3; ++a) {
+      const double ca = c[a], cb = c[(a + 1) % 3], cc = c[(a + 2) % 3];
+      double acc = 0.0;
+      for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+          const double y = cb * x[i], z = cc * x[j];
+          acc += wt[i] * wt[j] * ca / (2.0 * sqrt(ca * ca + y * y + z * z));
+        }
+      total += acc * cb * cc;
+    }
+    return 8.0 * total / (4.0 * ORC_PI);
+  }
+  for (int a = 0; a < 2; ++a) {
+    const double ca = c[a], cb = c[1 - a];
+    double acc = 0.0;
+    for (int i = 0; i < M; ++i) {
+      const double y = cb * x[i];
+      acc += wt[i] * ca * (0.25 - 0.5 * log(sqrt(ca * ca + y * y)));
+    }
+    total += acc * cb;
+  }
+  return 4.0 * total / (2.0 * ORC_PI);
+}
+
+/* Origin weight w[0] of the Hockney-Eastwood kernel (Sec. I and the legends
+ * of Sec. III.A):
+ *   mode 0: the singular factor (1/r, -ln r) replaced by 1: vol * G0 with
+ *           G0 = 1/(4 pi) in 3D, 1/(2 pi) in 2D;
+ *   mode 1: "nearby value": vol * G(r0), r0 = half the smallest spacing;
+ *   mode 2: "cell average": the integral of G over the cell around the
+ *           origin (vol times the average of G over it). */
+double orc_he_origin(int dim, const double* h, int mode) {
+  double vol = 1.0, hmin = h[0];
+  for (int a = 0; a < dim; ++a) {
+    vol *= h[a];
+    if (h[a] < hmin) hmin = h[a];
+  }
+  if (mode == 1) {
+    const double r0 = 0.5 * hmin;
+    return vol * (dim == 3 ? 1.0 / (4.0 * ORC_PI * r0) : -log(r0) / (2.0 * ORC_PI));
+  }
+  if (mode == 2) return orc_cell_average_integral(dim, h);
+  return vol * ((dim == 3) ? 1.0 / (4.0 * ORC_PI) : 1.0 / (2.0 * ORC_PI));
+}
+
+int orc_he_kernel_mode(int dim, const int64_t* n, const double* h, int mode, double* w);
+
 int orc_he_kernel(int dim, const int64_t* n, const double* h, double* w) {
+  return orc_he_kernel_mode(dim, n, h, 0, w);
+}
+
+int orc_he_kernel_mode(int dim, const int64_t* n, const double* h, int mode, double* w) {
   if (dim != 2 && dim != 3) return -1;
+  if (mode < 0 || mode > 2) return -1;
   double vol = 1.0;
   for (int a = 0; a < dim; ++a) vol *= h[a];
   int64_t total = prod(dim, n);
@@ -239,14 +345,72 @@ int orc_he_kernel(int dim, const int64_t* n, const double* h, double* w) {
       double x = (double)idx[a] * h[a];
       r2 += x * x;
     }
-    double g;
-    if (lin == 0)
-      g = (dim == 3) ? 1.0 / (4.0 * ORC_PI) : 1.0 / (2.0 * ORC_PI);
-    else if (dim == 3)
-      g = 1.0 / (4.0 * ORC_PI * sqrt(r2));
-    else
-      g = -log(sqrt(r2)) / (2.0 * ORC_PI);
+    if (lin == 0) {
+      w[0] = orc_he_origin(dim, h, mode);
+      continue;
+    }
+    const double g = (dim == 3) ? 1.0 / (4.0 * ORC_PI * sqrt(r2)) : -log(sqrt(r2)) / (2.0 * ORC_PI);
     w[lin] = vol * g;
+  }
+  return 0;
+}
+
+/* Finite-difference field E = -D phi (Sec. III.A, the "Finite Diff" curves):
+ * along each axis a second-order centred difference (phi[i+1] - phi[i-1]) /
+ * (2 h_a) at interior points and the second-order one-sided differences
+ * (-3 phi[0] + 4 phi[1] - phi[2]) / (2 h_a) and
+ * (3 phi[N-1] - 4 phi[N-2] + phi[N-3]) / (2 h_a) on the two end planes.
+ * Needs N_a >= 3. E is planar [dim][n]. */
+static double fd_coef(int64_t N, int64_t i, int64_t j) {
+  /* D[i][j] * 2h */
+  if (i == 0) return j == 0 ? -3.0 : (j == 1 ? 4.0 : (j == 2 ? -1.0 : 0.0));
+  if (i == N - 1) return j == N - 1 ? 3.0 : (j == N - 2 ? -4.0 : (j == N - 3 ? 1.0 : 0.0));
+  return j == i + 1 ? 1.0 : (j == i - 1 ? -1.0 : 0.0);
+}
+
+int orc_fd_field(int dim, const int64_t* n, const double* h, const double* phi, double* E) {
+  if (dim != 2 && dim != 3) return -1;
+  for (int a = 0; a < dim; ++a)
+    if (n[a] < 3) return -1;
+  const int64_t total = prod(dim, n);
+  for (int a = 0; a < dim; ++a) {
+    int64_t stride = 1;
+    for (int b = a + 1; b < dim; ++b) stride *= n[b];
+    for (int64_t lin = 0; lin < total; ++lin) {
+      int64_t idx[3];
+      unravel(dim, n, lin, idx);
+      const int64_t i = idx[a], N = n[a];
+      double acc = 0.0;
+      for (int64_t j = 0; j < N; ++j) {
+        const double c = fd_coef(N, i, j);
+        if (c != 0.0) acc += c * phi[lin + (j - i) * stride];
+      }
+      E[a * total + lin] = -acc / (2.0 * h[a]);
+    }
+  }
+  return 0;
+}
+
+/* Transpose: gphi = -sum_a D_a^T gE[a], by scattering each row's
+ * coefficients (no use of the stencil's structure). */
+int orc_fd_field_T(int dim, const int64_t* n, const double* h, const double* gE, double* gphi) {
+  if (dim != 2 && dim != 3) return -1;
+  for (int a = 0; a < dim; ++a)
+    if (n[a] < 3) return -1;
+  const int64_t total = prod(dim, n);
+  memset(gphi, 0, sizeof(double) * (size_t)total);
+  for (int a = 0; a < dim; ++a) {
+    int64_t stride = 1;
+    for (int b = a + 1; b < dim; ++b) stride *= n[b];
+    for (int64_t lin = 0; lin < total; ++lin) {
+      int64_t idx[3];
+      unravel(dim, n, lin, idx);
+      const int64_t i = idx[a], N = n[a];
+      for (int64_t j = 0; j < N; ++j) {
+        const double c = fd_coef(N, i, j);
+        if (c != 0.0) gphi[lin + (j - i) * stride] -= c * gE[a * total + lin] / (2.0 * h[a]);
+      }
+    }
   }
   return 0;
 }

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libvgf.so")
 OBJDIR = os.path.join(ROOT, "_build", "vgf")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["vgf_api.cpp", "vgf_precompute.hip", "vgf_batch.hip", "vgf_solve_f32.hip", "vgf_solve_f64.hip"]
+SOURCES = ["vgf_api.cpp", "vgf_precompute.hip", "vgf_batch.hip", "vgf_fd.hip", "vgf_solve_f32.hip", "vgf_solve_f64.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

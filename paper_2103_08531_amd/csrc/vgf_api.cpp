@@ -56,6 +56,8 @@ struct vgf_plan_s {
   size_t off_x1 = 0, off_x2 = 0, off_y = 0, off_z = 0;
   size_t ws_bytes = 0;           // solve workspace (a multiple of 256 bytes)
   int schedule[5] = {0, 0, 0, 0, 0};  // tile variant per pass (VGF_PASS_* order)
+  bool fd = false;               // E by finite differences of phi (VGF_FIELD_CENTERED)
+  size_t off_phi = 0;            // real phi array in the workspace (fd only)
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
 
@@ -70,6 +72,8 @@ namespace {
 constexpr long double kPiL = 3.14159265358979323846264338327950288L;
 
 bool size_supported(int64_t n) { return n >= 8 && vgf::supported_fft_len(2 * n); }
+
+double he_origin(int dim, const double* h, vgf_method m);
 
 int64_t prod(const int64_t* v, int d) {
   int64_t p = 1;
@@ -188,7 +192,9 @@ vgf_status precompute(vgf_plan p, hipStream_t s) {
       }
       if (err != hipSuccess) break;
     } else {
-      if ((err = vgf::launch_he_kernel(p->w64, d, p->n, p->h, s)) != hipSuccess) break;
+      if ((err = vgf::launch_he_kernel(p->w64, d, p->n, p->h, he_origin(d, p->h, p->method), s)) !=
+          hipSuccess)
+        break;
     }
 
     // (iii) spectrum of the 2N-periodic even kernel (zero where |n_a| = N_a):
@@ -265,6 +271,46 @@ struct Marks {
     if (own) p->prof_npass = n - 1;
   }
 };
+
+// Origin weight w[0] of the Hockney-Eastwood kernels (w[n] = vol G(|n h|)
+// elsewhere; Sec. I and the legends of the comparison figures, Sec. III.A):
+//   HE         the singular factor (1/r, -ln r) replaced by 1: vol * G0;
+//   HE_NEARBY  vol * G(r0), r0 = half the smallest spacing;
+//   HE_CELLAVG the integral of G over the cell prod_a [-h_a/2, h_a/2], in
+//              closed form: with (a, b, c) the half-widths and d the corner
+//              distance, 8 x the corner-box integral of 1/r,
+//                ab ln((c+d)/|(a,b)|) + bc ln((a+d)/|(b,c)|) + ca ln((b+d)/|(c,a)|)
+//                - a^2/2 atan(bc/(ad)) - b^2/2 atan(ca/(bd)) - c^2/2 atan(ab/(cd)),
+//              over 4 pi (3D); in 2D -4/(2 pi) x the corner integral of ln r,
+//                (ab ln(a^2+b^2) - 3ab + a^2 atan(b/a) + b^2 atan(a/b)) / 2.
+double he_origin(int dim, const double* h, vgf_method m) {
+  long double vol = 1.0L, hmin = h[0];
+  for (int a = 0; a < dim; ++a) {
+    vol *= (long double)h[a];
+    hmin = std::min(hmin, (long double)h[a]);
+  }
+  if (m == VGF_METHOD_HE_NEARBY) {
+    const long double r0 = 0.5L * hmin;
+    return (double)(vol * (dim == 3 ? 1.0L / (4.0L * kPiL * r0) : -logl(r0) / (2.0L * kPiL)));
+  }
+  if (m == VGF_METHOD_HE_CELLAVG) {
+    if (dim == 3) {
+      const long double a = 0.5L * h[0], b = 0.5L * h[1], c = 0.5L * h[2];
+      const long double dd = sqrtl(a * a + b * b + c * c);
+      const long double I = a * b * logl((c + dd) / sqrtl(a * a + b * b)) +
+                            b * c * logl((a + dd) / sqrtl(b * b + c * c)) +
+                            c * a * logl((b + dd) / sqrtl(c * c + a * a)) -
+                            0.5L * a * a * atanl(b * c / (a * dd)) - 0.5L * b * b * atanl(c * a / (b * dd)) -
+                            0.5L * c * c * atanl(a * b / (c * dd));
+      return (double)(8.0L * I / (4.0L * kPiL));
+    }
+    const long double a = 0.5L * h[0], b = 0.5L * h[1];
+    const long double J = 0.5L * (a * b * logl(a * a + b * b) - 3.0L * a * b + a * a * atanl(b / a) +
+                                  b * b * atanl(a / b));
+    return (double)(-4.0L * J / (2.0L * kPiL));
+  }
+  return (double)(vol * (dim == 3 ? 1.0L / (4.0L * kPiL) : 1.0L / (2.0L * kPiL)));
+}
 
 // 2 pi / (P_a h_a): wavenumber of one frequency step along axis a
 double wavenumber_step(vgf_plan p, int a) {
@@ -543,6 +589,20 @@ vgf_status tune_cached(vgf_plan p, bool want_phi, bool want_E, int count, int re
   return VGF_OK;
 }
 
+vgf::FdGeom fd_geom(vgf_plan p) {
+  vgf::FdGeom g{};
+  g.dim = p->dim;
+  g.total = prod(p->n, p->dim);
+  int64_t st = 1;
+  for (int a = p->dim - 1; a >= 0; --a) {
+    g.n[a] = (int)p->n[a];
+    g.stride[a] = st;
+    st *= p->n[a];
+    g.inv2h[a] = 0.5 / p->h[a];
+  }
+  return g;
+}
+
 template <typename T>
 vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   Entries<T> en;
@@ -552,7 +612,16 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   en.E = E;
   en.want_phi = phi != nullptr;
   en.want_E = E != nullptr;
-  return enqueue_solve<T>(p, en, s, true, p->schedule);
+  if (!(p->fd && E)) return enqueue_solve<T>(p, en, s, true, p->schedule);
+  // E = -D phi: phi (the caller's, or the workspace's), then the differences
+  T* ph = phi ? phi : (T*)((char*)p->ws + p->off_phi);
+  en.phi = ph;
+  en.E = nullptr;
+  en.want_phi = true;
+  en.want_E = false;
+  vgf_status st = enqueue_solve<T>(p, en, s, true, p->schedule);
+  if (st != VGF_OK) return st;
+  return hip_status(p, vgf::launch_fd_field<T>(ph, E, fd_geom(p), s));
 }
 
 // Adjoint: the mirror image of solve_t. Forward passes sum their inputs
@@ -655,9 +724,14 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   if (!out) return VGF_ERR_INVALID_ARG;
   *out = nullptr;
   if ((dim != 2 && dim != 3) || !n || !h) return VGF_ERR_INVALID_ARG;
-  if (method != VGF_METHOD_VGF && method != VGF_METHOD_HE) return VGF_ERR_INVALID_ARG;
+  if (method != VGF_METHOD_VGF && method != VGF_METHOD_HE && method != VGF_METHOD_HE_NEARBY &&
+      method != VGF_METHOD_HE_CELLAVG)
+    return VGF_ERR_INVALID_ARG;
   if (prec != VGF_F64 && prec != VGF_F32) return VGF_ERR_INVALID_ARG;
-  if (outputs == 0 || (outputs & ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E))) return VGF_ERR_INVALID_ARG;
+  if ((outputs & ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E | VGF_FIELD_CENTERED)) ||
+      !(outputs & (VGF_OUT_PHI | VGF_OUT_E)))
+    return VGF_ERR_INVALID_ARG;
+  if ((outputs & VGF_FIELD_CENTERED) && !(outputs & VGF_OUT_E)) return VGF_ERR_INVALID_ARG;
   for (int a = 0; a < dim; ++a) {
     if (!(h[a] > 0.0) || !std::isfinite(h[a])) return VGF_ERR_INVALID_ARG;
     if (n[a] <= 0) return VGF_ERR_INVALID_ARG;
@@ -696,6 +770,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->L = Lp;
   p->outputs = outputs;
   p->nf_max = ((outputs & VGF_OUT_PHI) ? 1 : 0) + ((outputs & VGF_OUT_E) ? dim : 0);
+  p->fd = (outputs & VGF_FIELD_CENTERED) != 0;
 
   const size_t rb = prec == VGF_F32 ? 4 : 8, cb = 2 * rb;
   const int64_t N0 = n[0], N1 = n[1], H = p->Hs;
@@ -707,7 +782,10 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   // Y holds the axis-0 outputs (phi's spectrum, and E_0's when E is
   // requested); Z the axis-1 outputs (phi, E_1, E_0). The adjoint reuses
   // the same regions in the mirrored order.
-  const size_t ny = (outputs & VGF_OUT_E) ? 2 : 1, nz = (outputs & VGF_OUT_E) ? 3 : 1;
+  // (A finite-difference field needs phi's spectrum only, and phi itself in
+  // a real array when the caller does not ask for it.)
+  const bool fourier_E = (outputs & VGF_OUT_E) && !p->fd;
+  const size_t ny = fourier_E ? 2 : 1, nz = fourier_E ? 3 : 1;
   size_t x1 = 0, x2 = 0, y = 0, z = 0;
   if (dim == 3) {
     x1 = (size_t)(N0 * N1 * H);
@@ -723,7 +801,8 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->off_x2 = align(x1 * cb);
   p->off_y = p->off_x2 + align(x2 * cb);
   p->off_z = p->off_y + align(y * cb);
-  const size_t ws_bytes = p->off_z + align(z * cb);
+  p->off_phi = p->off_z + align(z * cb);
+  const size_t ws_bytes = p->off_phi + (p->fd ? align((size_t)vol * rb) : 0);
   p->ws_bytes = ws_bytes;
   size_t tw_bytes = 0;
   for (int a = 0; a < dim; ++a) tw_bytes += (size_t)p->P[a] * cb;
@@ -781,6 +860,18 @@ vgf_status vgf_solve_adjoint(vgf_plan p, const void* g_phi, const void* g_E, voi
   if (!p || !g_rho || (!g_phi && !g_E)) return VGF_ERR_INVALID_ARG;
   if (g_phi && !(p->outputs & VGF_OUT_PHI)) return VGF_ERR_NOT_REQUESTED;
   if (g_E && !(p->outputs & VGF_OUT_E)) return VGF_ERR_NOT_REQUESTED;
+  if (p->fd && g_E) {
+    // E = -D phi, so the field's cotangent reaches phi as -D^T g_E
+    void* tmp = (char*)p->ws + p->off_phi;
+    hipError_t e = p->prec == VGF_F32
+                       ? vgf::launch_fd_adjoint<float>((const float*)g_phi, (const float*)g_E, (float*)tmp,
+                                                       fd_geom(p), stream)
+                       : vgf::launch_fd_adjoint<double>((const double*)g_phi, (const double*)g_E,
+                                                        (double*)tmp, fd_geom(p), stream);
+    if (e != hipSuccess) return hip_status(p, e);
+    g_phi = tmp;
+    g_E = nullptr;
+  }
   if (p->prec == VGF_F32)
     return adjoint_t<float>(p, (const float*)g_phi, (const float*)g_E, (float*)g_rho, stream);
   return adjoint_t<double>(p, (const double*)g_phi, (const double*)g_E, (double*)g_rho, stream);
@@ -804,6 +895,10 @@ vgf_status vgf_plan_autotune(vgf_plan p, const void* rho, void* phi, void* E, in
   vgf_status st = check_solve_args(p, rho, phi, E);
   if (st != VGF_OK) return st;
   if (reps <= 0) return VGF_ERR_INVALID_ARG;
+  if (p->fd && E) {  // the tuned passes compute phi; the field is a separate kernel
+    if (!phi) phi = (char*)p->ws + p->off_phi;
+    E = nullptr;
+  }
   auto run = [&](const int* sched, hipEvent_t* ev) -> vgf_status {
     if (p->prec == VGF_F32) {
       Entries<float> en;
@@ -1102,7 +1197,7 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
   *out = nullptr;
   if (count <= 0 || !plans || (flags & ~(unsigned)VGF_BATCH_GRAPH)) return VGF_ERR_INVALID_ARG;
   for (int i = 0; i < count; ++i)
-    if (!plans[i]) return VGF_ERR_INVALID_ARG;
+    if (!plans[i] || plans[i]->fd) return VGF_ERR_INVALID_ARG;
   vgf_batch b = new (std::nothrow) vgf_batch_s();
   if (!b) return VGF_ERR_OUT_OF_MEMORY;
   b->count = count;

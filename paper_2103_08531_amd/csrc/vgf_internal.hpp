@@ -127,6 +127,22 @@ template <typename T>
 hipError_t launch_fused(int P, int variant, bool adjoint, const cplx<T>* in, cplx<T>* out,
                         const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
 
+// ---- finite-difference field (second order; centred inside, one-sided at
+// the two end planes of each axis) ----
+struct FdGeom {
+  int dim;
+  int n[3];
+  int64_t stride[3];  // element stride of each axis
+  int64_t total;
+  double inv2h[3];    // 1 / (2 h_a)
+};
+// E[a] = -(D_a phi), E planar [dim][total]
+template <typename T>
+hipError_t launch_fd_field(const T* phi, T* E, const FdGeom& g, hipStream_t s);
+// out = g_phi - sum_a D_a^T g_E[a]  (g_phi may be null: zero)
+template <typename T>
+hipError_t launch_fd_adjoint(const T* g_phi, const T* g_E, T* out, const FdGeom& g, hipStream_t s);
+
 // ---- batched solves ----
 // Up to kMax device pointers, written to dst[0, n) by one small launch.
 struct PtrChunk {
@@ -141,8 +157,8 @@ hipError_t launch_set_pointers(void** dst, const PtrChunk& c, hipStream_t s);
 // k_{m,a} = m_a * dk_a.
 hipError_t launch_ghat(double* out, int dim, const int64_t* ext, const double* dk, double L,
                        hipStream_t s);
-// HE kernel octant: vol * G(|n h|), origin vol * G0.
-hipError_t launch_he_kernel(double* out, int dim, const int64_t* n, const double* h,
+// HE kernel octant: vol * G(|n h|), origin value `origin`.
+hipError_t launch_he_kernel(double* out, int dim, const int64_t* n, const double* h, double origin,
                             hipStream_t s);
 // out[o][j][i] = sum_{m < M} mat[m*J + j] * in[(o*M + m)*inner + i]
 hipError_t launch_axis_apply(const double* in, double* out, const double* mat, int64_t outer,

@@ -52,7 +52,7 @@ __global__ void k_ghat(double* __restrict__ out, int dim, int64_t e0, int64_t e1
 }
 
 __global__ void k_he(double* __restrict__ out, int dim, int64_t n0, int64_t n1, int64_t n2,
-                     double h0, double h1, double h2, int64_t total) {
+                     double h0, double h1, double h2, int64_t total, double origin) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   double r2, vol;
@@ -67,10 +67,11 @@ __global__ void k_he(double* __restrict__ out, int dim, int64_t n0, int64_t n1, 
     r2 = x * x + y * y;
     vol = h0 * h1;
   }
-  double g;
-  if (i == 0) g = (dim == 3) ? 1.0 / (4.0 * kPi) : 1.0 / (2.0 * kPi);
-  else if (dim == 3) g = 1.0 / (4.0 * kPi * sqrt(r2));
-  else g = -0.5 * log(r2) / (2.0 * kPi);
+  if (i == 0) {
+    out[0] = origin;
+    return;
+  }
+  const double g = (dim == 3) ? 1.0 / (4.0 * kPi * sqrt(r2)) : -0.5 * log(r2) / (2.0 * kPi);
   out[i] = vol * g;
 }
 
@@ -125,12 +126,12 @@ hipError_t launch_ghat(double* out, int dim, const int64_t* ext, const double* d
   return hipGetLastError();
 }
 
-hipError_t launch_he_kernel(double* out, int dim, const int64_t* n, const double* h,
+hipError_t launch_he_kernel(double* out, int dim, const int64_t* n, const double* h, double origin,
                             hipStream_t s) {
   const int64_t n2 = dim == 3 ? n[2] : 1;
   const int64_t total = n[0] * n[1] * n2;
   hipLaunchKernelGGL(k_he, dim3(blocks_for(total, 256)), dim3(256), 0, s, out, dim, n[0], n[1], n2,
-                     h[0], h[1], dim == 3 ? h[2] : 0.0, total);
+                     h[0], h[1], dim == 3 ? h[2] : 0.0, total, origin);
   return hipGetLastError();
 }
 

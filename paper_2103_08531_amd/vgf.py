@@ -18,9 +18,9 @@ OK = 0
 STATUS = {0: "VGF_OK", -1: "VGF_ERR_INVALID_ARG", -2: "VGF_ERR_UNSUPPORTED_SIZE",
           -3: "VGF_ERR_L_WINDOW", -4: "VGF_ERR_OUT_OF_MEMORY", -5: "VGF_ERR_HIP",
           -6: "VGF_ERR_NOT_REQUESTED"}
-METHODS = {"vgf": 0, "he": 1}
+METHODS = {"vgf": 0, "he": 1, "he_nearby": 2, "he_cellavg": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
-OUT_PHI, OUT_E = 1, 2
+OUT_PHI, OUT_E, FIELD_CENTERED = 1, 2, 16
 EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batched",
            "vgf_plan_get_L", "vgf_plan_workspace_bytes", "vgf_plan_get_kernel",
            "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
@@ -129,13 +129,15 @@ def _ptr(t):
 class Plan:
     """A solver plan for one grid (Sec. II: precompute once, then solve per rho).
 
-    n: points per axis (2 or 3 values); h: spacings; method 'vgf' or 'he';
+    n: points per axis (2 or 3 values); h: spacings; method 'vgf', 'he', 'he_nearby' or
+    'he_cellavg';
     precision 'f64' or 'f32'; L: VGF truncation radius (None: 1.1 x diameter);
-    outputs: subset of {'phi', 'E'}.
+    outputs: subset of {'phi', 'E'}; field: 'fourier' (default) or 'centered'
+    (E by second-order finite differences of phi).
     """
 
     def __init__(self, n, h, method="vgf", precision="f64", L=None, outputs=("phi", "E"),
-                 stream=None):
+                 stream=None, field="fourier"):
         torch = _torch()
         self.n = tuple(int(x) for x in n)
         self.h = tuple(float(x) for x in h)
@@ -144,7 +146,12 @@ class Plan:
         self.precision = precision
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.outputs = tuple(outputs)
+        if field not in ("fourier", "centered"):
+            raise ValueError("field must be 'fourier' or 'centered'")
+        self.field = field
         flags = (OUT_PHI if "phi" in outputs else 0) | (OUT_E if "E" in outputs else 0)
+        if field == "centered":
+            flags |= FIELD_CENTERED
         n_arr = (C.c_int64 * self.dim)(*self.n)
         h_arr = (C.c_double * self.dim)(*self.h)
         handle = C.c_void_p()

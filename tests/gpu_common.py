@@ -42,7 +42,7 @@ def gpu_solve(plan, rho_np, want_phi=True, want_E=True):
 
 
 def oracle_kernel(method, n, h, L):
-    return orc.vgf_kernel(n, h, L) if method == "vgf" else orc.he_kernel(n, h)
+    return orc.kernel(method, n, h, L)
 
 
 def oracle_solve(method, n, h, L, rho_np, want_E=True):
