@@ -32,6 +32,10 @@ def lib():
         L.orc_cell_average_integral.restype = d
         L.orc_cell_average_integral.argtypes = [C.c_int, dp]
         L.orc_fd_field.argtypes = [C.c_int, i64p, dp, dp, dp]
+        L.orc_vgf_grad_kernel.argtypes = [C.c_int, i64p, dp, d, C.c_int, dp]
+        L.orc_periodic_kernel_odd.argtypes = [C.c_int, i64p, dp, C.c_int, dp]
+        L.orc_conv_fft2n.argtypes = [C.c_int, i64p, dp, dp, dp]
+        L.orc_solve_fft4n_grad.argtypes = [C.c_int, i64p, dp, d, C.c_int, dp, dp]
         L.orc_fd_field_T.argtypes = [C.c_int, i64p, dp, dp, dp]
         L.orc_periodic_kernel.argtypes = [C.c_int, i64p, dp, dp]
         L.orc_field_kernel.argtypes = [C.c_int, i64p, dp, dp, C.c_int, dp]
@@ -149,6 +153,57 @@ def cell_average_integral(h):
     """Integral of G over the cell prod_a [-h_a/2, h_a/2]."""
     h_, ph = _f64(h)
     return lib().orc_cell_average_integral(len(h), ph)
+
+
+def vgf_grad_kernel(n, h, L, axis):
+    """Restricted inverse 4N DFT of -i k_axis Ghat: octant [0, N)^d, odd in axis."""
+    dim = len(n)
+    n_, pn = _i64(n)
+    h_, ph = _f64(h)
+    w, pw = _out(tuple(n))
+    assert lib().orc_vgf_grad_kernel(dim, pn, ph, float(L), int(axis), pw) == 0
+    return w
+
+
+def periodic_kernel_odd(n, w_oct, axis):
+    dim = len(n)
+    n_, pn = _i64(n)
+    w_, pw = _f64(w_oct)
+    W, pW = _out(tuple(2 * x for x in n))
+    lib().orc_periodic_kernel_odd(dim, pn, pw, int(axis), pW)
+    return W
+
+
+def conv_fft2n(n, V, rho):
+    """Restriction of the 2N-periodic convolution of V with zero-padded rho (FFT route)."""
+    dim = len(n)
+    n_, pn = _i64(n)
+    v_, pv = _f64(V)
+    r_, pr = _f64(rho)
+    out, po = _out(tuple(n))
+    assert lib().orc_conv_fft2n(dim, pn, pv, pr, po) == 0
+    return out
+
+
+def solve_fft4n_grad(n, h, L, axis, rho):
+    dim = len(n)
+    n_, pn = _i64(n)
+    h_, ph = _f64(h)
+    r_, pr = _f64(rho)
+    out, po = _out(tuple(n))
+    assert lib().orc_solve_fft4n_grad(dim, pn, ph, float(L), int(axis), pr, po) == 0
+    return out
+
+
+def solve_grad_kernel(n, h, L, rho, w=None, want_phi=True):
+    """phi (2N path, kernel w) and E_a = w_a * rho with the gradient kernels."""
+    dim = len(n)
+    if w is None and want_phi:
+        w = vgf_kernel(n, h, L)
+    phi = conv_fft2n(n, periodic_kernel(n, w), rho) if want_phi else None
+    E = np.stack([conv_fft2n(n, periodic_kernel_odd(n, vgf_grad_kernel(n, h, L, a), a), rho)
+                  for a in range(dim)])
+    return phi, E
 
 
 def fd_field(n, h, phi):

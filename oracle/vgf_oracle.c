@@ -153,8 +153,30 @@ void orc_window(int dim, const int64_t* n, const double* h, double* Lmin,
  * The d-fold sum factorises over axes in the cosine weights and is taken one
  * axis at a time, with compensated sums. w carries the h^d quadrature weight
  * implicitly. Output shape n[0..dim). */
+static int vgf_kernel_impl(int dim, const int64_t* n, const double* h, double L, int odd_axis,
+                           double* w);
+
 int orc_vgf_kernel(int dim, const int64_t* n, const double* h, double L,
                    double* w) {
+  return vgf_kernel_impl(dim, n, h, L, -1, w);
+}
+
+/* Gradient kernel of the field reading that transforms -i k_a times the
+ * windowed spectrum instead of differentiating the potential on the 2N grid
+ * (the alternative reading of "multiplying by the wavevector", Sec. III.A):
+ *   w_a[n] = (prod_b 4N_b)^{-1} sum_m (-i k_{m,a}) Ghat(|k_m|) e^{i k_m . x_n},
+ * restricted to n in [0, N)^d. The sum is real: pairing m_a with -m_a gives
+ * 2 k_{m,a} sin(2 pi m_a n_a / 4N_a) along axis a (the m_a = 0 and -2N_a
+ * terms vanish), the cosine weights of orc_vgf_kernel along the others.
+ * w_a is odd in n_a and even in the other offsets; E_a = w_a * rho. */
+int orc_vgf_grad_kernel(int dim, const int64_t* n, const double* h, double L, int axis,
+                        double* w) {
+  if (axis < 0 || axis >= dim) return -1;
+  return vgf_kernel_impl(dim, n, h, L, axis, w);
+}
+
+static int vgf_kernel_impl(int dim, const int64_t* n, const double* h, double L, int odd_axis,
+                           double* w) {
   if (dim != 2 && dim != 3) return -1;
   int64_t ms[3], cur[3];
   for (int a = 0; a < dim; ++a) ms[a] = 2 * n[a] + 1;
@@ -195,8 +217,13 @@ int orc_vgf_kernel(int dim, const int64_t* n, const double* h, double L,
       for (int64_t j = 0; j < N; ++j) {
         double c, s;
         cis_frac(m * j, M, &c, &s);
-        double wgt = (m == 0 || m == 2 * N) ? 1.0 : 2.0;
-        cosm[m * N + j] = wgt * c / (double)M;
+        if (a == odd_axis) {
+          const double km = 2.0 * ORC_PI * (double)m / ((double)M * h[a]);
+          cosm[m * N + j] = (m == 0 || m == 2 * N) ? 0.0 : 2.0 * km * s / (double)M;
+        } else {
+          double wgt = (m == 0 || m == 2 * N) ? 1.0 : 2.0;
+          cosm[m * N + j] = wgt * c / (double)M;
+        }
       }
     /* every output is one compensated sum over m in increasing order; the
      * loops run m outside i only so that rows are read contiguously */
@@ -496,6 +523,28 @@ void orc_conv_direct(int dim, const int64_t* n, const double* w_oct,
 
 /* out_i = sum_{j in [0,N)^d} V[(i - j) mod P] x_j, V a full 2N-periodic
  * kernel (shape 2 n). */
+/* 2N-periodic embedding of a kernel odd in axis `axis` and even in the
+ * others: W[p] = sign * w[|s|] with sign = -1 when s_axis < 0, and 0
+ * wherever some |s_a| = N_a. */
+void orc_periodic_kernel_odd(int dim, const int64_t* n, const double* w_oct, int axis,
+                             double* W) {
+  int64_t P[3];
+  for (int a = 0; a < dim; ++a) P[a] = 2 * n[a];
+  int64_t total = prod(dim, P);
+  for (int64_t lin = 0; lin < total; ++lin) {
+    int64_t p[3], q[3];
+    unravel(dim, P, lin, p);
+    int zero = 0;
+    double sign = 1.0;
+    for (int a = 0; a < dim; ++a) {
+      if (p[a] == n[a]) zero = 1;
+      q[a] = (p[a] < n[a]) ? p[a] : P[a] - p[a];
+      if (a == axis && p[a] > n[a]) sign = -1.0;
+    }
+    W[lin] = zero ? 0.0 : sign * w_oct[ravel(dim, n, q)];
+  }
+}
+
 void orc_conv_periodic(int dim, const int64_t* n, const double* V,
                        const double* x, double* out) {
   int64_t P[3];
@@ -756,6 +805,60 @@ int orc_solve_fft2n(int dim, const int64_t* n, const double* h,
   free(W);
   free(What);
   free(F);
+  free(R);
+  return 0;
+}
+
+/* out = restriction to [0, N) of the 2N-periodic convolution of V (full
+ * 2N-periodic real kernel) with rho zero-padded to 2N, through the naive
+ * FFT: pad, DFT, multiply by DFT(V), inverse DFT, restrict. */
+int orc_conv_fft2n(int dim, const int64_t* n, const double* V, const double* rho, double* out) {
+  int64_t P[3] = {1, 1, 1};
+  for (int a = 0; a < dim; ++a) P[a] = 2 * n[a];
+  const int64_t tp = prod(dim, P);
+  cplx* R = pad_complex(dim, n, P, rho);
+  cplx* K = (cplx*)malloc(sizeof(cplx) * (size_t)tp);
+  if (!R || !K) {
+    free(R);
+    free(K);
+    return -2;
+  }
+  for (int64_t i = 0; i < tp; ++i) K[i] = V[i];
+  fftnd(dim, P, R, -1);
+  fftnd(dim, P, K, -1);
+  for (int64_t i = 0; i < tp; ++i) R[i] *= K[i];
+  fftnd(dim, P, R, +1);
+  restrict_real(dim, n, P, R, 1.0 / (double)tp, out);
+  free(R);
+  free(K);
+  return 0;
+}
+
+/* The "in principle" 4N path for the gradient-kernel field: pad rho to 4N,
+ * multiply its DFT by -i k_a Ghat(|k|) (k_m from the signed index m), invert,
+ * restrict to [0, N) and keep the real part. */
+int orc_solve_fft4n_grad(int dim, const int64_t* n, const double* h, double L, int axis,
+                         const double* rho, double* Ea) {
+  int64_t M[3];
+  for (int a = 0; a < dim; ++a) M[a] = 4 * n[a];
+  int64_t tm = prod(dim, M);
+  cplx* R = pad_complex(dim, n, M, rho);
+  if (!R) return -2;
+  fftnd(dim, M, R, -1);
+#pragma omp parallel for schedule(static)
+  for (int64_t lin = 0; lin < tm; ++lin) {
+    int64_t m[3];
+    unravel(dim, M, lin, m);
+    double k2 = 0.0, kax = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      double ka = 2.0 * ORC_PI * signed_freq(m[a], M[a], 0) / ((double)M[a] * h[a]);
+      k2 += ka * ka;
+      if (a == axis) kax = ka;
+    }
+    R[lin] *= -I * kax * orc_ghat(dim, L, sqrt(k2));
+  }
+  fftnd(dim, M, R, +1);
+  restrict_real(dim, n, M, R, 1.0 / (double)tm, Ea);
   free(R);
   return 0;
 }

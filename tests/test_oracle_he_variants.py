@@ -140,3 +140,55 @@ def test_fd_field_second_order_and_transpose(orc):
     lhs = float(np.vdot(orc.fd_field(n, h, xv), yv))
     rhs = float(np.vdot(xv, orc.fd_field_T(n, h, yv)))
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+
+
+# ---------------------------------------------------------------------------
+# Gradient-kernel field (the alternative reading of "multiplying by the
+# wavevector": transform -i k_a Ghat on the 4N grid and restrict, Sec. II /
+# Sec. III.A).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_grad_kernel_4n_path_equals_restricted_kernel(orc, dim):
+    """The restricted odd kernel convolved on the 2N grid equals the 4N
+    "in principle" computation with -i k_a Ghat (both from the oracle, by
+    different routes: cosine/sine sums + FFT convolution vs. a 4N FFT)."""
+    n = (12, 16, 8)[:dim]
+    h = (0.1, 0.09, 0.12)[:dim]
+    L = orc.default_L(n, h)
+    rho = W.random_field(3, n)
+    _, E = orc.solve_grad_kernel(n, h, L, rho, want_phi=False)
+    for a in range(dim):
+        e4 = orc.solve_fft4n_grad(n, h, L, a, rho)
+        assert orc.rel_l2(E[a], e4) < 1e-13, a
+
+
+def test_grad_kernel_symmetry_and_direct_sum(orc):
+    n, h = (8, 10, 12), (0.11, 0.1, 0.09)
+    L = orc.default_L(n, h)
+    rho = W.random_field(4, n)
+    for a in range(3):
+        w = orc.vgf_grad_kernel(n, h, L, a)
+        idx = [slice(None)] * 3
+        idx[a] = 0
+        assert np.all(w[tuple(idx)] == 0.0)  # odd in n_a
+        V = orc.periodic_kernel_odd(n, w, a)
+        direct = orc.conv_periodic(n, V, rho)
+        assert orc.rel_l2(orc.conv_fft2n(n, V, rho), direct) < 1e-13
+
+
+def test_grad_kernel_converges_to_analytic_field(orc):
+    errs, errs_ik = [], []
+    for N in (16, 24, 32, 48):
+        n, h, x0 = W.cube_grid(3, N, -1.0, 1.0)
+        c, s = np.zeros((1, 3)), np.full((1, 3), 0.1)
+        rho = W.gaussian_density(n, x0, h, c, s, np.ones(1))
+        _, Ea = orc.gauss_mixture_grid(n, x0, h, c, s, np.ones(1))
+        L = orc.default_L(n, h)
+        _, E = orc.solve_grad_kernel(n, h, L, rho, want_phi=False)
+        _, E2 = orc.solve_fft2n(n, h, orc.vgf_kernel(n, h, L), rho, want_phi=False)
+        errs.append(orc.rel_l2(E, Ea))
+        errs_ik.append(orc.rel_l2(E2, Ea))
+    assert errs[0] / errs[1] > 30 and errs[1] / errs[2] > 100, errs  # spectral
+    assert errs[3] < 1e-11, errs
+    # the two readings differ at moderate N (both are converged at N = 48)
+    assert abs(errs[2] - errs_ik[2]) > 1e-7, (errs, errs_ik)
