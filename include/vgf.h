@@ -80,7 +80,14 @@ typedef enum { VGF_F64 = 0, VGF_F32 = 1 } vgf_precision;
  *     plane of each axis -- instead of Fourier differentiation. This is the
  *     "Finite Diff" field of the comparison figures (Sec. III.A); Fourier
  *     differentiation is the default. Not accepted by vgf_batch_create. */
-enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u, VGF_FIELD_CENTERED = 16u };
+/*   VGF_FIELD_GRADIENT_KERNEL : (VGF method, with VGF_OUT_E) E_a = w_a * rho
+ *     with w_a the gradient kernel: the inverse DFT on the 4N-oversampled grid
+ *     of -i k_a times the windowed spectrum, restricted like the potential's
+ *     kernel (Sec. II, applied to the field; the other reading of Sec. III.A's
+ *     "multiplying by the wavevector"). The plan stores dim more kernel
+ *     spectra; the axis-0 pass multiplies every field by its own spectrum and
+ *     inverts each field separately. Not accepted by vgf_batch_create. */
+enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u, VGF_FIELD_CENTERED = 16u, VGF_FIELD_GRADIENT_KERNEL = 32u };
 
 /* Build a plan for a fixed grid (Sec. II: one precomputation per grid, then
  * a solve per right-hand side).
@@ -98,7 +105,8 @@ enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u, VGF_FIELD_CENTERED = 16u };
  *              truncated kernel misses source-target pairs (Sec. II), above
  *              it the 4N-periodic images reach the box. Ignored for HE.
  *   outputs  : VGF_OUT_PHI | VGF_OUT_E, the fields later solves may return,
- *              optionally | VGF_FIELD_CENTERED (requires VGF_OUT_E).
+ *              optionally | VGF_FIELD_CENTERED or | VGF_FIELD_GRADIENT_KERNEL
+ *              (either requires VGF_OUT_E; the latter the VGF method).
  *   stream   : stream on which the FP64 precompute runs; the call
  *              synchronises it before returning.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, L_WINDOW, OUT_OF_MEMORY, HIP. On
@@ -155,7 +163,7 @@ typedef struct vgf_batch_s* vgf_batch;
 enum { VGF_BATCH_GRAPH = 1u };
 
 /* plans[0..count): the plan of each entry (non-NULL, count >= 1, not created
- * with VGF_FIELD_CENTERED). flags: 0 or VGF_BATCH_GRAPH. Allocates the group workspaces (VGF_ERR_OUT_OF_MEMORY
+ * with VGF_FIELD_CENTERED or VGF_FIELD_GRADIENT_KERNEL). flags: 0 or VGF_BATCH_GRAPH. Allocates the group workspaces (VGF_ERR_OUT_OF_MEMORY
  * beyond VGF_MAX_WORKSPACE). Enqueues nothing. */
 vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, unsigned flags);
 
@@ -224,6 +232,13 @@ vgf_status vgf_plan_autotune(vgf_plan plan, const void* rho, void* phi, void* E,
  * rejects a non-zero variant for a pass that has none (INVALID_ARG). */
 vgf_status vgf_plan_get_schedule(vgf_plan plan, int* schedule);
 vgf_status vgf_plan_set_schedule(vgf_plan plan, const int* schedule);
+
+/* Gradient-kernel plans only (VGF_ERR_NOT_REQUESTED otherwise): the FP64
+ * gradient kernel w_axis on [0, N)^d (odd in the axis, even in the others;
+ * prod(n) doubles) and T_axis on [0, N]^d (the 2N spectrum of the odd
+ * periodic kernel is -i T_axis; prod(n_a + 1) doubles). Synchronous. */
+vgf_status vgf_plan_get_gradient_kernel(vgf_plan plan, int axis, double* host_out);
+vgf_status vgf_plan_get_gradient_spectrum(vgf_plan plan, int axis, double* host_out);
 
 /* The truncation radius the plan uses (0 for HE). */
 vgf_status vgf_plan_get_L(vgf_plan plan, double* L);

@@ -57,6 +57,10 @@ struct vgf_plan_s {
   size_t ws_bytes = 0;           // solve workspace (a multiple of 256 bytes)
   int schedule[5] = {0, 0, 0, 0, 0};  // tile variant per pass (VGF_PASS_* order)
   bool fd = false;               // E by finite differences of phi (VGF_FIELD_CENTERED)
+  bool gradk = false;            // E by gradient kernels (VGF_FIELD_GRADIENT_KERNEL)
+  double* wgrad64 = nullptr;     // [dim][prod(n)] gradient-kernel octants, FP64
+  double* specg64 = nullptr;     // [dim][prod(n+1)] their spectra T_a, FP64, unscaled
+  void* specg = nullptr;         // [dim][prod(n+1)] plan type, scaled by 1/prod(P)
   size_t off_phi = 0;            // real phi array in the workspace (fd only)
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
@@ -122,6 +126,9 @@ void release(vgf_plan p) {
   f(p->spec);
   f(p->w64);
   f(p->spec64);
+  f(p->wgrad64);
+  f(p->specg64);
+  f(p->specg);
   for (int a = 0; a < 3; ++a) f(p->tw[a]);
   f(p->ws);
   for (hipEvent_t ev : p->prof_events) (void)hipEventDestroy(ev);
@@ -163,63 +170,96 @@ vgf_status precompute(vgf_plan p, hipStream_t s) {
     if ((err = hipMalloc(&bufB, sizeof(double) * (size_t)gsz)) != hipSuccess) break;
     if ((err = hipMalloc(&mat, sizeof(double) * (size_t)maxmat)) != hipSuccess) break;
 
-    if (p->method == VGF_METHOD_VGF) {
-      // (i) spectrum samples on m in [0, 2N]^d of the 4N grid, k = 2 pi m / (4 N h)
-      for (int a = 0; a < d; ++a)
-        dk[a] = (double)(2.0L * kPiL / (4.0L * (long double)p->n[a] * (long double)p->h[a]));
-      if ((err = vgf::launch_ghat(bufA, d, ext, dk, p->L, s)) != hipSuccess) break;
-      // (ii) inverse DFT over the 4N grid restricted to n_a in [0, N_a):
-      //  out[j] = (4N)^{-1} (f(0) + 2 sum_{0<m<2N} f(m) cos(2 pi m j / 4N) + f(2N) cos(pi j))
+    // (i) spectrum samples on m in [0, 2N]^d of the 4N grid, k = 2 pi m / (4 N h)
+    for (int a = 0; a < d; ++a)
+      dk[a] = (double)(2.0L * kPiL / (4.0L * (long double)p->n[a] * (long double)p->h[a]));
+    // (ii) inverse DFT over the 4N grid restricted to n_a in [0, N_a), one
+    // axis at a time. Even axes:
+    //  out[j] = (4N)^{-1} (f(0) + 2 sum_{0<m<2N} f(m) cos(2 pi m j / 4N) + f(2N) cos(pi j));
+    // the odd axis of a gradient kernel (-i k_a times the spectrum; pairing
+    // m with -m leaves a sine, the m = 0 and m = -2N terms vanish):
+    //  out[j] = (4N)^{-1} 2 sum_{0<m<2N} k_m f(m) sin(2 pi m j / 4N).
+    auto restricted = [&](double* target, int odd_axis) -> hipError_t {
+      hipError_t e = vgf::launch_ghat(bufA, d, ext, dk, p->L, s);
       for (int a = 0; a < d; ++a) cur[a] = ext[a];
       double *src = bufA, *dst = bufB;
-      for (int a = 0; a < d && err == hipSuccess; ++a) {
+      for (int a = 0; a < d && e == hipSuccess; ++a) {
         const int64_t N = p->n[a], M4 = 4 * p->n[a], Mi = ext[a];
         host_mat.assign((size_t)(Mi * N), 0.0);
         for (int64_t m = 0; m < Mi; ++m)
           for (int64_t j = 0; j < N; ++j) {
             long double c, sn;
             cis(m * j, M4, &c, &sn);
-            const long double wgt = (m == 0 || m == 2 * N) ? 1.0L : 2.0L;
-            host_mat[(size_t)(m * N + j)] = (double)(wgt * c / (long double)M4);
+            if (a == odd_axis) {
+              const long double km = 2.0L * kPiL * (long double)m / ((long double)M4 * (long double)p->h[a]);
+              host_mat[(size_t)(m * N + j)] =
+                  (m == 0 || m == 2 * N) ? 0.0 : (double)(2.0L * km * sn / (long double)M4);
+            } else {
+              const long double wgt = (m == 0 || m == 2 * N) ? 1.0L : 2.0L;
+              host_mat[(size_t)(m * N + j)] = (double)(wgt * c / (long double)M4);
+            }
           }
         int64_t outer = 1, inner = 1;
         for (int b = 0; b < a; ++b) outer *= cur[b];
         for (int b = a + 1; b < d; ++b) inner *= cur[b];
-        double* target = (a == d - 1) ? p->w64 : dst;
-        err = apply_axis(host_mat, mat, src, target, outer, (int)Mi, (int)N, inner, s);
+        double* tgt = (a == d - 1) ? target : dst;
+        e = apply_axis(host_mat, mat, src, tgt, outer, (int)Mi, (int)N, inner, s);
         cur[a] = N;
         std::swap(src, dst);
       }
-      if (err != hipSuccess) break;
+      return e;
+    };
+    // (iii) spectrum of the 2N-periodic kernel (zero where |n_a| = N_a), on
+    // k in [0, N]: even axes S[k] = w[0] + 2 sum_{0<n<N} w[n] cos(2 pi n k / 2N);
+    // the odd axis of a gradient kernel gives -i T with
+    // T[k] = 2 sum_{0<n<N} w[n] sin(2 pi n k / 2N).
+    auto spectrum = [&](const double* from, double* target, int odd_axis) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int a = 0; a < d; ++a) cur[a] = p->n[a];
+      double* tmp[2] = {bufA, bufB};
+      for (int a = 0; a < d && e == hipSuccess; ++a) {
+        const int64_t N = p->n[a], P2 = 2 * p->n[a];
+        host_mat.assign((size_t)(N * (N + 1)), 0.0);
+        for (int64_t m = 0; m < N; ++m)
+          for (int64_t k = 0; k <= N; ++k) {
+            long double c, sn;
+            cis(m * k, P2, &c, &sn);
+            host_mat[(size_t)(m * (N + 1) + k)] =
+                a == odd_axis ? (m == 0 ? 0.0 : (double)(2.0L * sn)) : (double)((m == 0 ? 1.0L : 2.0L) * c);
+          }
+        int64_t outer = 1, inner = 1;
+        for (int b = 0; b < a; ++b) outer *= cur[b];
+        for (int b = a + 1; b < d; ++b) inner *= cur[b];
+        double* tgt = (a == d - 1) ? target : tmp[a % 2];
+        e = apply_axis(host_mat, mat, from, tgt, outer, (int)N, (int)(N + 1), inner, s);
+        cur[a] = N + 1;
+        from = tgt;
+      }
+      return e;
+    };
+
+    if (p->method == VGF_METHOD_VGF) {
+      if ((err = restricted(p->w64, -1)) != hipSuccess) break;
     } else {
       if ((err = vgf::launch_he_kernel(p->w64, d, p->n, p->h, he_origin(d, p->h, p->method), s)) !=
           hipSuccess)
         break;
     }
-
-    // (iii) spectrum of the 2N-periodic even kernel (zero where |n_a| = N_a):
-    //  S[k] = w[0] + 2 sum_{0<n<N} w[n] cos(2 pi n k / 2N),  k in [0, N]
-    for (int a = 0; a < d; ++a) cur[a] = p->n[a];
-    const double* from = p->w64;
-    double* tmp[2] = {bufA, bufB};
-    for (int a = 0; a < d && err == hipSuccess; ++a) {
-      const int64_t N = p->n[a], P2 = 2 * p->n[a];
-      host_mat.assign((size_t)(N * (N + 1)), 0.0);
-      for (int64_t m = 0; m < N; ++m)
-        for (int64_t k = 0; k <= N; ++k) {
-          long double c, sn;
-          cis(m * k, P2, &c, &sn);
-          host_mat[(size_t)(m * (N + 1) + k)] = (double)((m == 0 ? 1.0L : 2.0L) * c);
-        }
-      int64_t outer = 1, inner = 1;
-      for (int b = 0; b < a; ++b) outer *= cur[b];
-      for (int b = a + 1; b < d; ++b) inner *= cur[b];
-      double* target = (a == d - 1) ? p->spec64 : tmp[a % 2];
-      err = apply_axis(host_mat, mat, from, target, outer, (int)N, (int)(N + 1), inner, s);
-      cur[a] = N + 1;
-      from = target;
+    if ((err = spectrum(p->w64, p->spec64, -1)) != hipSuccess) break;
+    if (p->gradk) {
+      const int64_t vol = prod(p->n, d);
+      for (int ax = 0; ax < d && err == hipSuccess; ++ax) {
+        if ((err = restricted(p->wgrad64 + ax * vol, ax)) != hipSuccess) break;
+        if ((err = spectrum(p->wgrad64 + ax * vol, p->specg64 + ax * oct, ax)) != hipSuccess) break;
+        if (p->prec == VGF_F32)
+          err = vgf::launch_scale_convert<float>(p->specg64 + ax * oct, (float*)p->specg + ax * oct, oct,
+                                                 1.0 / pp, s);
+        else
+          err = vgf::launch_scale_convert<double>(p->specg64 + ax * oct, (double*)p->specg + ax * oct, oct,
+                                                  1.0 / pp, s);
+      }
+      if (err != hipSuccess) break;
     }
-    if (err != hipSuccess) break;
 
     // plan-precision copy, divided by the inverse FFT normalisation
     if (p->prec == VGF_F32)
@@ -401,8 +441,82 @@ void c2r_out(vgf::C2RArgs<T>& ca, int o, const Entries<T>& en, int field, int64_
 enum { kPassR2C = 0, kPassC2CF = 1, kPassFused = 2, kPassC2CI = 3, kPassC2R = 4, kPasses = 5 };
 
 template <typename T>
+vgf::GradSpec<T> grad_spec(vgf_plan p) {
+  vgf::GradSpec<T> sp{};
+  int64_t oct = 1;
+  for (int a = 0; a < p->dim; ++a) oct *= p->n[a] + 1;
+  sp.s[0] = (const T*)p->spec;
+  for (int a = 0; a < p->dim; ++a) sp.s[1 + a] = (const T*)p->specg + a * oct;
+  return sp;
+}
+
+// Forward solve with gradient kernels (one entry): no derivative factors
+// after the axis-0 pass, which multiplies each requested field by its own
+// spectrum; every field is then inverted on its own.
+template <typename T>
+vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks, const int* sched,
+                              hipEvent_t* mark_events) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
+  const int64_t vol = prod(p->n, d);
+  char* base = en.ws;
+  Bufs<T> b{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2), (cplx<T>*)(base + p->off_y),
+            (cplx<T>*)(base + p->off_z)};
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  vgf::FusedGeom<T> g = fused_geom<T>(p);
+  g.nf = 0;
+  if (en.want_phi) g.fields[g.nf++] = 0;
+  if (en.want_E)
+    for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
+  T* outs[4];
+  for (int f = 0; f < g.nf; ++f) outs[f] = g.fields[f] == 0 ? en.phi : en.E + (g.fields[f] - 1) * vol;
+  Marks mk(p, s, marks, mark_events);
+  mk.mark();
+  const int64_t lpe = d == 3 ? N0 * N1 : N0;
+  vgf::R2CArgs<T> ra{{en.rho, nullptr}, b.x1, lpe, Hs, deriv1<T>(p, d - 1, 0)};
+  ra.lpe = lpe;
+  VGF_RUN(vgf::launch_r2c<T>((int)p->P[d - 1], ra, tw(d - 1), s));
+  mk.mark();
+  const cplx<T>* fused_in = b.x1;
+  if (d == 3) {
+    const int64_t P1 = p->P[1];
+    const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
+    vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    mk.mark();
+    fused_in = b.x2;
+    g.out_fs = N0 * P1 * Hs;
+  } else {
+    g.out_fs = N0 * Hs;
+  }
+  VGF_RUN(vgf::launch_fused_grad<T>((int)p->P[0], false, fused_in, b.y, g, grad_spec<T>(p), tw(0), s));
+  mk.mark();
+  const cplx<T>* lastin = b.y;
+  int64_t last_fs = g.out_fs;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], zfs = N0 * N1 * Hs;
+    const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
+    for (int f = 0; f < g.nf; ++f) {
+      vgf::C2CInvArgs<T> ia{b.y + f * g.out_fs, {b.z + f * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    }
+    mk.mark();
+    lastin = b.z;
+    last_fs = zfs;
+  }
+  for (int f = 0; f < g.nf; ++f) {
+    vgf::C2RArgs<T> ca{lastin + f * last_fs, {outs[f], nullptr}, lpe, Hs, deriv1<T>(p, d - 1, 0)};
+    ca.lpe = lpe;
+    VGF_RUN(vgf::launch_c2r<T>((int)p->P[d - 1], ca, tw(d - 1), s));
+  }
+  mk.mark();
+  return VGF_OK;
+}
+
+template <typename T>
 vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks,
                          const int* sched, hipEvent_t* mark_events = nullptr) {
+  if (p->gradk) return enqueue_solve_grad<T>(p, en, s, marks, sched, mark_events);
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -628,8 +742,63 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
 // after multiplying by +i k of their own axis (the conjugate of -i k), the
 // axis-0 pass multiplies by the (real) kernel spectrum and +i k_0, and the
 // inverse passes are plain.
+// Adjoint with gradient kernels: every cotangent is transformed on its own,
+// the axis-0 pass sums them with the conjugate multipliers (+i T_a for the
+// fields), and the sum is inverted once.
+template <typename T>
+vgf_status adjoint_grad_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
+  const int64_t vol = prod(p->n, d);
+  Bufs<T> b = bufs<T>(p);
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  vgf::FusedGeom<T> g = fused_geom<T>(p);
+  const T* srcs[4];
+  g.nf = 0;
+  if (g_phi) {
+    srcs[g.nf] = g_phi;
+    g.fields[g.nf++] = 0;
+  }
+  if (g_E)
+    for (int a = 0; a < d; ++a) {
+      srcs[g.nf] = g_E + a * vol;
+      g.fields[g.nf++] = 1 + a;
+    }
+  const int64_t lpe = d == 3 ? N0 * N1 : N0;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], yfs = N0 * P1 * Hs, zfs = N0 * N1 * Hs;
+    const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
+    for (int f = 0; f < g.nf; ++f) {
+      vgf::R2CArgs<T> ra{{srcs[f], nullptr}, b.z + f * zfs, lpe, Hs, deriv1<T>(p, 2, 0)};
+      ra.lpe = lpe;
+      VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
+      vgf::C2CFwdArgs<T> fa{{b.z + f * zfs, nullptr}, b.y + f * yfs, fg, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, p->schedule[kPassC2CF], fa, tw(1), s));
+    }
+    g.in_fs = yfs;
+    VGF_RUN(vgf::launch_fused_grad<T>((int)p->P[0], true, b.y, b.x2, g, grad_spec<T>(p), tw(0), s));
+    const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
+    vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, p->schedule[kPassC2CI], ia, tw(1), s));
+  } else {
+    const int64_t yfs = N0 * Hs;
+    for (int f = 0; f < g.nf; ++f) {
+      vgf::R2CArgs<T> ra{{srcs[f], nullptr}, b.y + f * yfs, lpe, Hs, deriv1<T>(p, 1, 0)};
+      ra.lpe = lpe;
+      VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
+    }
+    g.in_fs = yfs;
+    VGF_RUN(vgf::launch_fused_grad<T>((int)p->P[0], true, b.y, b.x1, g, grad_spec<T>(p), tw(0), s));
+  }
+  vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, lpe, Hs, deriv1<T>(p, d - 1, 0)};
+  ca.lpe = lpe;
+  VGF_RUN(vgf::launch_c2r<T>((int)p->P[d - 1], ca, tw(d - 1), s));
+  return VGF_OK;
+}
+
 template <typename T>
 vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  if (p->gradk) return adjoint_grad_t<T>(p, g_phi, g_E, g_rho, s);
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -728,10 +897,13 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
       method != VGF_METHOD_HE_CELLAVG)
     return VGF_ERR_INVALID_ARG;
   if (prec != VGF_F64 && prec != VGF_F32) return VGF_ERR_INVALID_ARG;
-  if ((outputs & ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E | VGF_FIELD_CENTERED)) ||
+  if ((outputs & ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E | VGF_FIELD_CENTERED | VGF_FIELD_GRADIENT_KERNEL)) ||
       !(outputs & (VGF_OUT_PHI | VGF_OUT_E)))
     return VGF_ERR_INVALID_ARG;
-  if ((outputs & VGF_FIELD_CENTERED) && !(outputs & VGF_OUT_E)) return VGF_ERR_INVALID_ARG;
+  if ((outputs & (VGF_FIELD_CENTERED | VGF_FIELD_GRADIENT_KERNEL)) && !(outputs & VGF_OUT_E))
+    return VGF_ERR_INVALID_ARG;
+  if ((outputs & VGF_FIELD_CENTERED) && (outputs & VGF_FIELD_GRADIENT_KERNEL)) return VGF_ERR_INVALID_ARG;
+  if ((outputs & VGF_FIELD_GRADIENT_KERNEL) && method != VGF_METHOD_VGF) return VGF_ERR_INVALID_ARG;
   for (int a = 0; a < dim; ++a) {
     if (!(h[a] > 0.0) || !std::isfinite(h[a])) return VGF_ERR_INVALID_ARG;
     if (n[a] <= 0) return VGF_ERR_INVALID_ARG;
@@ -771,6 +943,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->outputs = outputs;
   p->nf_max = ((outputs & VGF_OUT_PHI) ? 1 : 0) + ((outputs & VGF_OUT_E) ? dim : 0);
   p->fd = (outputs & VGF_FIELD_CENTERED) != 0;
+  p->gradk = (outputs & VGF_FIELD_GRADIENT_KERNEL) != 0;
 
   const size_t rb = prec == VGF_F32 ? 4 : 8, cb = 2 * rb;
   const int64_t N0 = n[0], N1 = n[1], H = p->Hs;
@@ -784,8 +957,10 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   // the same regions in the mirrored order.
   // (A finite-difference field needs phi's spectrum only, and phi itself in
   // a real array when the caller does not ask for it.)
+  // With gradient kernels every field is its own spectrum after axis 0.
   const bool fourier_E = (outputs & VGF_OUT_E) && !p->fd;
-  const size_t ny = fourier_E ? 2 : 1, nz = fourier_E ? 3 : 1;
+  size_t ny = fourier_E ? 2 : 1, nz = fourier_E ? 3 : 1;
+  if (p->gradk) ny = nz = (size_t)(1 + dim);
   size_t x1 = 0, x2 = 0, y = 0, z = 0;
   if (dim == 3) {
     x1 = (size_t)(N0 * N1 * H);
@@ -807,6 +982,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   size_t tw_bytes = 0;
   for (int a = 0; a < dim; ++a) tw_bytes += (size_t)p->P[a] * cb;
   p->bytes = ws_bytes + tw_bytes + (size_t)oct * (rb + 8) + (size_t)vol * 8;
+  if (p->gradk) p->bytes += (size_t)dim * ((size_t)oct * (rb + 8) + (size_t)vol * 8);
   if (p->bytes > max_workspace_env()) {
     release(p);
     return VGF_ERR_OUT_OF_MEMORY;
@@ -819,6 +995,11 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
     if ((err = hipMalloc(&p->spec, (size_t)oct * rb)) != hipSuccess) break;
     if ((err = hipMalloc((void**)&p->spec64, (size_t)oct * 8)) != hipSuccess) break;
     if ((err = hipMalloc((void**)&p->w64, (size_t)vol * 8)) != hipSuccess) break;
+    if (p->gradk) {
+      if ((err = hipMalloc((void**)&p->wgrad64, (size_t)dim * vol * 8)) != hipSuccess) break;
+      if ((err = hipMalloc((void**)&p->specg64, (size_t)dim * oct * 8)) != hipSuccess) break;
+      if ((err = hipMalloc(&p->specg, (size_t)dim * oct * rb)) != hipSuccess) break;
+    }
     for (int a = 0; a < dim && err == hipSuccess; ++a) {
       err = hipMalloc(&p->tw[a], (size_t)p->P[a] * cb);
       if (err != hipSuccess) break;
@@ -964,6 +1145,23 @@ vgf_status vgf_plan_get_spectrum(vgf_plan p, double* host_out) {
   size_t cnt = 1;
   for (int a = 0; a < p->dim; ++a) cnt *= (size_t)(p->n[a] + 1);
   return hip_status(p, hipMemcpy(host_out, p->spec64, cnt * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+vgf_status vgf_plan_get_gradient_kernel(vgf_plan p, int axis, double* host_out) {
+  if (!p || !host_out || axis < 0 || axis >= p->dim) return VGF_ERR_INVALID_ARG;
+  if (!p->gradk) return VGF_ERR_NOT_REQUESTED;
+  const size_t cnt = (size_t)prod(p->n, p->dim);
+  return hip_status(p, hipMemcpy(host_out, p->wgrad64 + axis * cnt, cnt * sizeof(double),
+                                 hipMemcpyDeviceToHost));
+}
+
+vgf_status vgf_plan_get_gradient_spectrum(vgf_plan p, int axis, double* host_out) {
+  if (!p || !host_out || axis < 0 || axis >= p->dim) return VGF_ERR_INVALID_ARG;
+  if (!p->gradk) return VGF_ERR_NOT_REQUESTED;
+  size_t cnt = 1;
+  for (int a = 0; a < p->dim; ++a) cnt *= (size_t)(p->n[a] + 1);
+  return hip_status(p, hipMemcpy(host_out, p->specg64 + axis * cnt, cnt * sizeof(double),
+                                 hipMemcpyDeviceToHost));
 }
 
 vgf_status vgf_plan_profile_begin(vgf_plan p, int max_solves) {
@@ -1197,7 +1395,7 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
   *out = nullptr;
   if (count <= 0 || !plans || (flags & ~(unsigned)VGF_BATCH_GRAPH)) return VGF_ERR_INVALID_ARG;
   for (int i = 0; i < count; ++i)
-    if (!plans[i] || plans[i]->fd) return VGF_ERR_INVALID_ARG;
+    if (!plans[i] || plans[i]->fd || plans[i]->gradk) return VGF_ERR_INVALID_ARG;
   vgf_batch b = new (std::nothrow) vgf_batch_s();
   if (!b) return VGF_ERR_OUT_OF_MEMORY;
   b->count = count;

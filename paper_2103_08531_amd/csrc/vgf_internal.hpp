@@ -106,7 +106,7 @@ template <typename T> struct FusedGeom {
   int hs;            // padded stride of the last axis (>= h_last)
   T ks0;             // 2 pi / (P_0 h_0)
   int nf;
-  int fields[2];
+  int fields[4];
   int nentry = 1;    // entries (right-hand sides) of the launch
   int64_t in_es = 0, out_es = 0;  // element strides between entries
 };
@@ -126,6 +126,18 @@ hipError_t launch_c2c_inv(int P, int variant, const C2CInvArgs<T>& a, const cplx
 template <typename T>
 hipError_t launch_fused(int P, int variant, bool adjoint, const cplx<T>* in, cplx<T>* out,
                         const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
+
+// Spectra of the gradient-kernel fields: s[0] the kernel spectrum octant,
+// s[1 + a] the octant of T_a (the 2N spectrum of the odd gradient kernel of
+// axis a is -i T_a), all in plan precision, divided by prod_a P_a. A fused
+// launch in this mode takes fields f in {0, 1, .., dim}: 0 multiplies by
+// s[0], 1 + a by -i T_a (the adjoint by the conjugates).
+template <typename T> struct GradSpec {
+  const T* s[4];
+};
+template <typename T>
+hipError_t launch_fused_grad(int P, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
+                             const GradSpec<T>& sp, const cplx<T>* tw, hipStream_t s);
 
 // ---- finite-difference field (second order; centred inside, one-sided at
 // the two end planes of each axis) ----

@@ -740,6 +740,152 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
 }
 
 // ---------------------------------------------------------------------------
+// Gradient-kernel fields (E_a = w_a * rho with w_a the restricted inverse 4N
+// transform of -i k_a Ghat). The 2N spectrum of the odd kernel w_a is
+// -i T_a with T_a real, odd in the axis-a frequency and even in the others;
+// the octants hold T_a for frequency indices in [0, N]. Field 0 multiplies
+// by the kernel spectrum, field 1 + a by -i s_a T_a, s_a = -1 where the
+// axis-a index exceeds N_a (axis 0: the row of the line; axis 1 in 3D: the
+// column's k1; the last axis is a half spectrum). One tile per workgroup.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int NB>
+__device__ __forceinline__ bool row_above_nyquist(int j, int r) {
+  if constexpr (R % 2 == 0) {
+    return r >= R / 2;  // row N itself has T_0 = 0, either sign is right
+  } else {
+    constexpr int N = R * NB / 2;
+    return j + r * NB > N;
+  }
+}
+
+template <typename T, typename SL, typename RegsOut, typename RegsIn>
+__device__ __forceinline__ void grad_multiply(RegsOut& v, const RegsIn& x, const FusedGeom<T>& g, const GradSpec<T>& sp,
+                                              uint32_t colpart, bool neg1, int field, int sgn, int q) {
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t) {
+    if (!SL::active(t, q)) continue;
+    const int j = q + t * SL::NQ;
+    const SpecIdx<T> si(g, colpart, j);
+    const T* __restrict__ sa = sp.s[field];
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) {
+      T val = sa[si.template at<SL::R, SL::NB>(j, r)];
+      if (field == 0) {
+        v.v[t][r] = {x.v[t][r].x * val, x.v[t][r].y * val};
+      } else {
+        const bool neg = field == 1 ? row_above_nyquist<T, SL::R, SL::NB>(j, r) : (field == 2 && g.dim == 3 && neg1);
+        if (neg) val = -val;
+        v.v[t][r] = deriv(x.v[t][r], sgn, val);
+      }
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_grad(const cplx<T>* __restrict__ in,
+                                                                cplx<T>* __restrict__ out,
+                                                                FusedGeom<T> g, GradSpec<T> sp,
+                                                                const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TL = Tile<T, P>;
+  constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
+  constexpr int NSTG = n_stages(P);
+  __shared__ C lds[P * LP];
+  __shared__ C twl[P];
+  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
+  const ColIO& cio = fc.io;
+  const bool neg1 = g.dim == 3 && (int)(cio.col / (uint32_t)g.hs) > g.n1;
+  stage_twiddles<C, P, NT>(twl, tw, tid);
+  using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
+  using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
+  using IS0 = Stage<T, P, NT, NL, LP, 1, 0>;
+  using ISL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+
+  typename S0::Regs g0;
+  S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
+  S0::butterflies(g0, q);
+  S0::lds_out(g0, lds, l, q);
+  __syncthreads();
+  typename SL::Regs rh;
+  middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
+  for (int fi = 0; fi < g.nf; ++fi) {
+    typename IS0::Regs v;
+    grad_multiply<T, SL>(v, rh, g, sp, fc.colpart, neg1, g.fields[fi], -1, q);
+    IS0::butterflies(v, q);
+    __syncthreads();
+    IS0::lds_out(v, lds, l, q);
+    __syncthreads();
+    typename ISL::Regs o;
+    middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
+    if (cio.valid) {
+      C* __restrict__ dst = out + fi * g.out_fs;
+      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
+    }
+  }
+}
+
+// adjoint: acc = sum_f conj(m_f) FFT(in_f), out = pruned inverse of acc
+template <typename T, int P>
+__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_grad_adj(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedGeom<T> g, GradSpec<T> sp,
+    const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TL = Tile<T, P>;
+  constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
+  constexpr int NSTG = n_stages(P);
+  __shared__ C lds[P * LP];
+  __shared__ C twl[P];
+  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
+  const ColIO& cio = fc.io;
+  const bool neg1 = g.dim == 3 && (int)(cio.col / (uint32_t)g.hs) > g.n1;
+  stage_twiddles<C, P, NT>(twl, tw, tid);
+  using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
+  using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
+  using IS0 = Stage<T, P, NT, NL, LP, 1, 0>;
+  using ISL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+
+  typename IS0::Regs acc;
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t)
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
+  for (int fi = 0; fi < g.nf; ++fi) {
+    const C* __restrict__ src = in + fi * g.in_fs;
+    typename S0::Regs g0;
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
+    S0::butterflies(g0, q);
+    __syncthreads();
+    S0::lds_out(g0, lds, l, q);
+    __syncthreads();
+    typename SL::Regs rh;
+    middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
+    typename IS0::Regs m;
+    grad_multiply<T, SL>(m, rh, g, sp, fc.colpart, neg1, g.fields[fi], 1, q);
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        acc.v[t][r].x += m.v[t][r].x;
+        acc.v[t][r].y += m.v[t][r].y;
+      }
+    }
+  }
+  IS0::butterflies(acc, q);
+  __syncthreads();
+  IS0::lds_out(acc, lds, l, q);
+  __syncthreads();
+  typename ISL::Regs o;
+  middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
+  if (cio.valid)
+    ISL::template store_last<true>(o, q, [&](int j, int r, C val) { out[cio.off<ISL::NB>(j, r)] = val; });
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 #define VGF_FOR_EACH_P(X) \
@@ -856,7 +1002,23 @@ hipError_t launch_fused_p(int variant, bool adjoint, const cplx<T>* in, cplx<T>*
                       : launch_fused_v<T, P, 0>(in, out, g, spec, tw, s);
 }
 
+template <typename T, int P>
+hipError_t launch_fused_grad_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
+                               const GradSpec<T>& sp, const cplx<T>* tw, hipStream_t s) {
+  using TL = Tile<T, P>;
+  if (g.nf == 0) return hipSuccess;
+  if (g.nentry != 1 || g.nf > 4) return hipErrorInvalidValue;
+  const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
+  if (bx == 0) return hipSuccess;
+  if (adjoint)
+    hipLaunchKernelGGL((k_fused_grad_adj<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, sp, tw);
+  else
+    hipLaunchKernelGGL((k_fused_grad<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, sp, tw);
+  return hipGetLastError();
+}
+
 #define VGF_CASE_R2C(PP) case PP: return launch_r2c_p<VGF_T, PP>(a, tw, s);
+#define VGF_CASE_FGRAD(PP) case PP: return launch_fused_grad_p<VGF_T, PP>(adjoint, in, out, g, sp, tw, s);
 #define VGF_CASE_C2R(PP) case PP: return launch_c2r_p<VGF_T, PP>(a, tw, s);
 #define VGF_CASE_C2CF(PP) case PP: return launch_c2c_fwd_p<VGF_T, PP>(variant, a, tw, s);
 #define VGF_CASE_C2CI(PP) case PP: return launch_c2c_inv_p<VGF_T, PP>(variant, a, tw, s);
@@ -886,6 +1048,12 @@ hipError_t launch_fused_p(int variant, bool adjoint, const cplx<T>* in, cplx<T>*
                              const FusedGeom<T>& g, const T* spec, const cplx<T>* tw,           \
                              hipStream_t s) {                                                   \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_FUSED) default: return hipErrorInvalidValue; }         \
+  }                                                                                             \
+  template <>                                                                                   \
+  hipError_t launch_fused_grad<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,         \
+                                  const FusedGeom<T>& g, const GradSpec<T>& sp,                 \
+                                  const cplx<T>* tw, hipStream_t s) {                           \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FGRAD) default: return hipErrorInvalidValue; }         \
   }
 
 }  // namespace vgf

@@ -20,14 +20,15 @@ STATUS = {0: "VGF_OK", -1: "VGF_ERR_INVALID_ARG", -2: "VGF_ERR_UNSUPPORTED_SIZE"
           -6: "VGF_ERR_NOT_REQUESTED"}
 METHODS = {"vgf": 0, "he": 1, "he_nearby": 2, "he_cellavg": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
-OUT_PHI, OUT_E, FIELD_CENTERED = 1, 2, 16
+OUT_PHI, OUT_E, FIELD_CENTERED, FIELD_GRADIENT_KERNEL = 1, 2, 16, 32
 EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batched",
            "vgf_plan_get_L", "vgf_plan_workspace_bytes", "vgf_plan_get_kernel",
            "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
            "vgf_status_string", "vgf_plan_profile_begin", "vgf_plan_profile_end",
            "vgf_batch_create", "vgf_batch_solve", "vgf_batch_workspace_bytes", "vgf_batch_groups",
            "vgf_batch_hip_error", "vgf_batch_destroy", "vgf_plan_autotune", "vgf_plan_get_schedule",
-           "vgf_plan_set_schedule", "vgf_batch_autotune", "vgf_batch_get_schedule"]
+           "vgf_plan_set_schedule", "vgf_batch_autotune", "vgf_batch_get_schedule",
+           "vgf_plan_get_gradient_kernel", "vgf_plan_get_gradient_spectrum"]
 BATCH_GRAPH = 1
 PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused_axis0", "c2c_inv", "c2r"],
               2: ["r2c", "fused_axis0", "c2r"]}
@@ -101,6 +102,10 @@ def lib():
         L.vgf_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int, vp]
         L.vgf_batch_get_schedule.restype = C.c_int
         L.vgf_batch_get_schedule.argtypes = [vp, C.c_int, ip]
+        L.vgf_plan_get_gradient_kernel.restype = C.c_int
+        L.vgf_plan_get_gradient_kernel.argtypes = [vp, C.c_int, dp]
+        L.vgf_plan_get_gradient_spectrum.restype = C.c_int
+        L.vgf_plan_get_gradient_spectrum.argtypes = [vp, C.c_int, dp]
         _lib = L
     return _lib
 
@@ -132,8 +137,9 @@ class Plan:
     n: points per axis (2 or 3 values); h: spacings; method 'vgf', 'he', 'he_nearby' or
     'he_cellavg';
     precision 'f64' or 'f32'; L: VGF truncation radius (None: 1.1 x diameter);
-    outputs: subset of {'phi', 'E'}; field: 'fourier' (default) or 'centered'
-    (E by second-order finite differences of phi).
+    outputs: subset of {'phi', 'E'}; field: 'fourier' (default), 'centered'
+    (E by second-order finite differences of phi) or 'gradient_kernel' (E_a =
+    w_a * rho with the restricted 4N transform of -i k_a Ghat; VGF only).
     """
 
     def __init__(self, n, h, method="vgf", precision="f64", L=None, outputs=("phi", "E"),
@@ -146,12 +152,14 @@ class Plan:
         self.precision = precision
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.outputs = tuple(outputs)
-        if field not in ("fourier", "centered"):
-            raise ValueError("field must be 'fourier' or 'centered'")
+        if field not in ("fourier", "centered", "gradient_kernel"):
+            raise ValueError("field must be 'fourier', 'centered' or 'gradient_kernel'")
         self.field = field
         flags = (OUT_PHI if "phi" in outputs else 0) | (OUT_E if "E" in outputs else 0)
         if field == "centered":
             flags |= FIELD_CENTERED
+        elif field == "gradient_kernel":
+            flags |= FIELD_GRADIENT_KERNEL
         n_arr = (C.c_int64 * self.dim)(*self.n)
         h_arr = (C.c_double * self.dim)(*self.h)
         handle = C.c_void_p()
@@ -190,6 +198,20 @@ class Plan:
         out = np.zeros(tuple(x + 1 for x in self.n), dtype=np.float64)
         _check(lib().vgf_plan_get_spectrum(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))),
                "vgf_plan_get_spectrum")
+        return out
+
+    def gradient_kernel(self, axis):
+        out = np.zeros(self.n, dtype=np.float64)
+        _check(lib().vgf_plan_get_gradient_kernel(self.handle, int(axis),
+                                                  out.ctypes.data_as(C.POINTER(C.c_double))),
+               "vgf_plan_get_gradient_kernel")
+        return out
+
+    def gradient_spectrum(self, axis):
+        out = np.zeros(tuple(x + 1 for x in self.n), dtype=np.float64)
+        _check(lib().vgf_plan_get_gradient_spectrum(self.handle, int(axis),
+                                                    out.ctypes.data_as(C.POINTER(C.c_double))),
+               "vgf_plan_get_gradient_spectrum")
         return out
 
     def _check_tensor(self, t, shape, name):

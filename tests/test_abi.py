@@ -129,3 +129,17 @@ def test_null_schedule_calls_fail_cleanly(V):
     assert L.vgf_plan_autotune(None, None, None, None, 3, None) == -1
     assert L.vgf_batch_autotune(None, None, None, None, 3, None) == -1
     assert L.vgf_batch_get_schedule(None, 0, sched) == -1
+
+
+def test_field_mode_flags_are_checked(V):
+    # centred and gradient-kernel fields need E; they exclude each other; the
+    # gradient kernel needs the VGF method
+    assert _create(V, outputs=1 | 16)[0] == -1
+    assert _create(V, outputs=1 | 32)[0] == -1
+    assert _create(V, outputs=3 | 16 | 32)[0] == -1
+    assert _create(V, method=1, outputs=3 | 32)[0] == -1
+    assert _create(V, outputs=3 | 64)[0] == -1
+    L = V.lib()
+    out = (C.c_double * 8)()
+    assert L.vgf_plan_get_gradient_kernel(None, 0, out) == -1
+    assert L.vgf_plan_get_gradient_spectrum(None, 0, out) == -1
