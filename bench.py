@@ -28,6 +28,8 @@ Printed JSON line (one, rank 0):
                entry vs one launch per pass and grid size vs the same as one
                replayed hipGraph, before and after autotuning the groups' tile
                schedules, in ms per batch and solves/s
+  other_workloads  gaussian_3d_32 and mixture_2d_512 (FP64, VGF and HE)
+               solves/s, diff_3d_128 (8 FP32 forward solves + 8 adjoints) ms
 The 256^3 plans are autotuned (tile schedule per pass, bit-identical results)
 before the warm-up; the chosen schedules are reported.
 
@@ -381,6 +383,61 @@ def run_batch(vgf, torch, workloads, steps, warmup, seed):
     return res
 
 
+def time_fn(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
+    """The other workloads, timed on their own plans (rho resident in HBM):
+    gaussian_3d_32 (3D 32^3, FP64, phi + E) and mixture_2d_512 (2D 512^2,
+    FP64, phi + E), each with VGF and HE; diff_3d_128 (8 right-hand sides at
+    128^3, FP32, E only): one step is the 8 forward solves plus the 8
+    adjoints of the loss gradient."""
+    out = {}
+    for name, ch in (("gaussian_3d_32", workloads.gaussian_3d_32()),
+                     ("mixture_2d_512", workloads.mixture_2d_512(seed=seed))):
+        rho = torch.from_numpy(ch.rho()).to("cuda", torch.float64)
+        res = {"grid": list(ch.n), "precision": "f64", "outputs": "phi+E"}
+        for method in ("vgf", "he"):
+            plan = vgf.Plan(ch.n, ch.h, method=method, precision="f64")
+            phi = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+            E = torch.empty((len(ch.n),) + ch.n, dtype=torch.float64, device="cuda")
+            plan.autotune(rho, phi, E, reps=3)
+            ms = time_fn(torch, lambda: plan.solve(rho, phi, E), max(steps, 50), warmup)
+            res[method] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms}
+            plan.close()
+        out[name] = res
+    rhs, _ = workloads.diff_3d_128(seed=seed)
+    n, h = rhs[0].n, rhs[0].h
+    plan = vgf.Plan(n, h, method="vgf", precision="f32", outputs=("E",))
+    rhos = [torch.from_numpy(c.rho()).to("cuda", torch.float32) for c in rhs]
+    Es = [torch.empty((3,) + n, dtype=torch.float32, device="cuda") for _ in rhs]
+    gEs = [torch.randn((3,) + n, dtype=torch.float32, device="cuda") for _ in rhs]
+    grs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in rhs]
+    plan.autotune(rhos[0], None, Es[0], reps=3)
+
+    def step():
+        for r, E in zip(rhos, Es):
+            plan.solve(r, None, E, want_phi=False)
+        for gE, gr in zip(gEs, grs):
+            plan.adjoint(None, gE, gr)
+
+    ms = time_fn(torch, step, steps, warmup)
+    out["diff_3d_128"] = {"grid": list(n), "batch": len(rhs), "precision": "f32", "outputs": "E",
+                          "ms_per_step": ms, "rhs_per_s": len(rhs) * 1e3 / ms,
+                          "step": "8 forward solves (E only) + 8 adjoints"}
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def rel_l2(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
 
@@ -409,7 +466,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batch_3d_mixed comparison")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch_3d_mixed comparison and the other workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the solves, copy 256 MiB device-to-device once (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -445,6 +503,10 @@ def main():
             prec, results[prec]["wall_ms"], results[prec]["event_ms"],
             {k: round(v, 4) for k, v in results[prec]["passes"].items()}), file=sys.stderr, flush=True)
 
+    others = None
+    if not args.no_batch:
+        others = run_small_configs(vgf, torch, workloads, args.steps, args.warmup, args.seed)
+        print("[bench] other workloads: %s" % json.dumps(others), file=sys.stderr, flush=True)
     batch = None
     if not args.no_batch:
         batch = run_batch(vgf, torch, workloads, args.steps, args.warmup, args.seed)
@@ -508,6 +570,7 @@ def main():
                                         "E": rel_l2(f32["out"]["E"], f64["out"]["E"])}},
     }
     line["batch"] = batch
+    line["other_workloads"] = others
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
