@@ -292,7 +292,7 @@ def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
     rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
     phi = torch.empty(ch.n, dtype=dt, device="cuda")
     E = torch.empty((3,) + ch.n, dtype=dt, device="cuda")
-    schedule = plan.autotune(rho, phi, E, reps=3) if tune else plan.schedule
+    schedule = plan.autotune(rho, phi, E, reps=5) if tune else plan.schedule
     for _ in range(warmup):
         plan.solve(rho, phi, E)
     torch.cuda.synchronize()

@@ -218,10 +218,12 @@ void vgf_batch_destroy(vgf_batch batch);
 enum { VGF_PASS_R2C = 0, VGF_PASS_C2C_FWD = 1, VGF_PASS_FUSED = 2, VGF_PASS_C2C_INV = 3,
        VGF_PASS_C2R = 4, VGF_NUM_PASSES = 5 };
 
-/* Chooses the plan's schedule by measurement: for each variant, one warm-up
- * solve and `reps` timed solves of (rho, phi, E) (arguments as vgf_solve)
- * with HIP events at the pass boundaries on `stream`; each pass keeps its
- * fastest variant. phi / E receive solve results. Synchronises `stream`.
+/* Chooses the plan's schedule by measurement: two warm-up solves per
+ * variant, then `reps` rounds that each run one solve of (rho, phi, E)
+ * (arguments as vgf_solve) per variant, interleaved, with HIP events at the
+ * pass boundaries on `stream`. Each pass takes its fastest repetition per
+ * variant and keeps the default variant unless another is more than 2%
+ * faster. phi / E receive solve results. Synchronises `stream`.
  * The choice is cached in the process per (grid, precision, outputs), so an
  * identical plan tuned again takes the cached schedule without running.
  * Errors: as vgf_solve, INVALID_ARG for reps <= 0. */

@@ -641,29 +641,39 @@ bool pass_tunable(int dim, int pass) {
 // given schedule, recording the pass boundaries into events when non-null.
 template <class Run>
 vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, hipError_t* herr) {
+  constexpr int NV = vgf_tile_variants();
   const int nint = dim == 3 ? 5 : 3;
   static const int pass3[5] = {kPassR2C, kPassC2CF, kPassFused, kPassC2CI, kPassC2R};
   static const int pass2[3] = {kPassR2C, kPassFused, kPassC2R};
   const int* pass_of = dim == 3 ? pass3 : pass2;
-  std::vector<hipEvent_t> ev((size_t)reps * kMaxMarks, nullptr);
+  // events [rep][variant][mark]
+  std::vector<hipEvent_t> ev((size_t)reps * NV * kMaxMarks, nullptr);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-  double t[vgf_tile_variants()][kPasses] = {};
+  int sched[NV][kPasses];
+  for (int v = 0; v < NV; ++v)
+    for (int k = 0; k < kPasses; ++k) sched[v][k] = pass_tunable(dim, k) ? v : 0;
   vgf_status st = VGF_OK;
-  for (int v = 0; v < vgf_tile_variants() && st == VGF_OK && e == hipSuccess; ++v) {
-    int sched[kPasses];
-    for (int k = 0; k < kPasses; ++k) sched[k] = pass_tunable(dim, k) ? v : 0;
-    st = run(sched, nullptr);
-    for (int r = 0; r < reps && st == VGF_OK; ++r) st = run(sched, &ev[(size_t)r * kMaxMarks]);
-    if (st != VGF_OK) break;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
-    for (int r = 0; r < reps && e == hipSuccess; ++r)
+  // warm-up of every variant, then the variants interleaved rep by rep so
+  // that clock ramps and cache state bias none of them
+  for (int w = 0; w < 2 && st == VGF_OK && e == hipSuccess; ++w)
+    for (int v = 0; v < NV && st == VGF_OK; ++v) st = run(sched[v], nullptr);
+  for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
+    for (int v = 0; v < NV && st == VGF_OK; ++v) st = run(sched[v], &ev[((size_t)r * NV + v) * kMaxMarks]);
+  // fastest repetition of each pass under each variant
+  double t[NV][kPasses];
+  for (int v = 0; v < NV; ++v)
+    for (int k = 0; k < kPasses; ++k) t[v][k] = 1e30;
+  if (st == VGF_OK && e == hipSuccess) e = hipStreamSynchronize(s);
+  for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
+    for (int v = 0; v < NV && e == hipSuccess; ++v) {
+      hipEvent_t* m = &ev[((size_t)r * NV + v) * kMaxMarks];
       for (int i = 0; i < nint && e == hipSuccess; ++i) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, ev[(size_t)r * kMaxMarks + i], ev[(size_t)r * kMaxMarks + i + 1]);
-        t[v][pass_of[i]] += ms;
+        e = hipEventElapsedTime(&ms, m[i], m[i + 1]);
+        t[v][pass_of[i]] = std::min(t[v][pass_of[i]], (double)ms);
       }
-  }
+    }
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
   if (st != VGF_OK) return st;
@@ -671,11 +681,12 @@ vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, h
     *herr = e;
     return VGF_ERR_HIP;
   }
+  // keep the default unless another variant is faster by more than 2%
   for (int k = 0; k < kPasses; ++k) {
     best[k] = 0;
     if (!pass_tunable(dim, k)) continue;
-    for (int v = 1; v < vgf_tile_variants(); ++v)
-      if (t[v][k] < t[best[k]][k]) best[k] = v;
+    for (int v = 1; v < NV; ++v)
+      if (t[v][k] < 0.98 * t[best[k]][k]) best[k] = v;
   }
   return VGF_OK;
 }

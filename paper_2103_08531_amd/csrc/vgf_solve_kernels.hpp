@@ -296,6 +296,7 @@ struct ColIO {
   uint32_t col;   // clamped column
   uint32_t ls;    // row stride (elements)
   bool valid;
+  ColIO() = default;
   __device__ __forceinline__ ColIO(int64_t c, int64_t ncols, int64_t ls_) {
     valid = c < ncols;
     col = (uint32_t)(valid ? c : ncols - 1);
@@ -447,6 +448,7 @@ template <typename T, int P, int V> struct TileF : TileV<T, P, V> {
 template <typename T> struct FusedCol {
   ColIO io;
   uint32_t colpart;  // octant offset of (f1, k2) (3D) or f1 (2D)
+  FusedCol() = default;
   __device__ __forceinline__ FusedCol(const FusedGeom<T>& g, int64_t c) : io(c, g.ncols, g.ncols) {
     const int64_t cc = io.col;
     if (g.dim == 3) {
@@ -535,12 +537,23 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
   const int chunk1 = chunk0 + chunk < total ? chunk0 + chunk : total;
   int u = chunk0 + (xcd ? (int)blockIdx.x / 8 : (int)blockIdx.x);
   if (u >= chunk1) return;
-  // (entry, tile) of position uu in the visiting order
-  auto tile_of = [&](int uu, int& e) -> int {
-    e = uu / ntiles;
-    uu -= e * ntiles;
-    if (!pairs) return uu;
-    const int row = uu / tiles_per_row, blk = uu - row * tiles_per_row;
+  // position u in the visiting order as (entry ue, tile-in-entry ut); both
+  // advance by per_xcd per step without a division
+  int ue = u / ntiles, ut = u - ue * ntiles;
+  const int step_e = per_xcd / ntiles, step_t = per_xcd - step_e * ntiles;
+  auto advance = [&]() {
+    u += per_xcd;
+    ue += step_e;
+    ut += step_t;
+    if (ut >= ntiles) {
+      ut -= ntiles;
+      ++ue;
+    }
+  };
+  // tile index of the tile-in-entry position tt (mirrored k1 rows adjacent)
+  auto tile_of = [&](int tt) -> int {
+    if (!pairs) return tt;
+    const int row = tt / tiles_per_row, blk = tt - row * tiles_per_row;
     int k1;
     if (row == 0) k1 = 0;
     else if (row == 1) k1 = nrows / 2;
@@ -550,8 +563,6 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
     }
     return k1 * tiles_per_row + blk;
   };
-  int ent = 0;
-  int tile = tile_of(u, ent);
   stage_twiddles<C, P, NT>(twl, tw, tid);
 
   // loads of one tile: the stage-0 inputs and the kernel spectrum at this
@@ -570,7 +581,8 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
     }
   };
 
-  FusedCol<T> fcn(g, (int64_t)tile * NL + l);
+  FusedCol<T> fcn(g, (int64_t)tile_of(ut) * NL + l);
+  int ent = ue;
   typename S0::Regs g0n;
   T svn[SL::NTASK][SL::R];
   load_tile(fcn, ent, g0n, svn);
@@ -584,13 +596,12 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
     for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) sv[t][r] = svn[t][r];
-    const int unext = u + per_xcd;
-    const bool more = unext < chunk1;
-    int enext = 0;
-    const int next = more ? tile_of(unext, enext) : 0;
+    advance();
+    const bool more = u < chunk1;
     if (more) {
-      fcn = FusedCol<T>(g, (int64_t)next * NL + l);
-      load_tile(fcn, enext, g0n, svn);
+      fcn = FusedCol<T>(g, (int64_t)tile_of(ut) * NL + l);
+      ent = ue;
+      load_tile(fcn, ent, g0n, svn);
     }
 
     S0::butterflies(g0, q);
@@ -654,9 +665,6 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
       }
     }
     if (!more) break;
-    u = unext;
-    tile = next;
-    ent = enext;
   }
 }
 
