@@ -111,7 +111,8 @@ def digest_counters(fetch_csv, fetch_out, write_csv, write_out):
     for path in (fetch_out, write_out):
         if _bench_line(path).get("source_hash") != src:
             raise SystemExit("%s was measured on other sources than these" % path)
-    out = {"source_hash": src, "calibration_bytes": CALIB_BYTES, "kernels": {}}
+    out = {"source_hash": src, "calibration_bytes": CALIB_BYTES, "kernels": {},
+           "schedule": _bench_line(fetch_out).get("schedule")}
     per = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _read_counter(path, counter)
@@ -149,16 +150,33 @@ def load_traffic():
     return d if d.get("source_hash") == kernel_source_hash() else None
 
 
-def traffic_of(traffic, pass_name, prec):
-    """Scaled HBM bytes per launch of a pass's kernel (256^3, P = 512)."""
-    if traffic is None:
+PASS_INDEX = {"r2c": 0, "c2c_fwd": 1, "fused_axis0": 2, "c2c_inv": 3, "c2r": 4}
+TUNABLE = ("c2c_fwd", "fused_axis0", "c2c_inv")
+
+
+def _pass_kernels(kernels, pass_name, t, variant):
+    """Kernels (name -> data) of one pass at precision t ('float'/'double'),
+    P = 512, restricted to the tile-schedule variant for tunable passes."""
+    out = {}
+    for k, v in kernels.items():
+        if not k.startswith(PASS_KERNELS[pass_name]) or ("<%s, 512" % t) not in k:
+            continue
+        if pass_name in TUNABLE and not k.endswith(", %d>" % variant):
+            continue
+        out[k] = v
+    return out
+
+
+def traffic_of(traffic, pass_name, prec, schedule):
+    """Scaled HBM bytes per launch of a pass's kernel (256^3, P = 512) under
+    the tile schedule the timed solves used."""
+    if traffic is None or pass_name != "fused_axis0":
         return None
     t = "float" if prec == "f32" else "double"
-    hits = [v for k, v in traffic["kernels"].items()
-            if k.startswith(PASS_KERNELS[pass_name]) and ("<%s, 512" % t) in k]
+    hits = _pass_kernels(traffic["kernels"], pass_name, t, schedule[PASS_INDEX[pass_name]])
     if len(hits) != 1:
         return None
-    return hits[0]["traffic_bytes"]
+    return next(iter(hits.values()))["traffic_bytes"]
 
 
 def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
@@ -188,21 +206,27 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
         for pname, prefix in PASS_KERNELS.items():
             for t in ("float", "double"):
                 if name.startswith(prefix) and ("<%s, 512" % t) in name:
-                    alg = kb[t][pname]
+                    alg = kb[t][pname]  # per launch for the single-launch passes
         # c2c_inv and c2r run as several launches (fields split between them): see the per-pass table
         ratio = "%.3f" % (v["traffic_bytes"] / alg) if alg and not name.startswith(("k_c2c_inv", "k_c2r")) else "-"
         md.append("| %s | %d | %.1f | %.1f | %.1f | %s | %s |" % (
             name, v["dispatches"], v["read_bytes"] / 1e6, v["write_bytes"] / 1e6, v["traffic_bytes"] / 1e6,
             "%.1f" % (alg / 1e6) if alg and ratio != "-" else "-", ratio))
-    md += ["", "Per solve and pass (launches of a pass summed; solves = launches of k_fused):", "",
+    md += ["", "The run autotunes each plan's tile schedule first, so both variants of the strided kernels "
+           "(last template argument) appear above. Per solve and pass, with the schedule the timed solves "
+           "used (%s): one launch of each kernel per solve, except k_c2r<., ., 1>, launched twice "
+           "(E_1 and E_0):" % json.dumps(d["schedule"]), "",
            "| pass | precision | traffic MB | algorithmic MB | traffic / algorithmic |", "|---|---|---|---|---|"]
     for t, prec in (("float", "FP32"), ("double", "FP64")):
-        ks = {k: v for k, v in d["kernels"].items() if ("<%s, 512" % t) in k}
-        nsolve = max([v["dispatches"] for k, v in ks.items() if k.startswith("k_fused<")] or [0])
-        if not nsolve:
+        sched = (d["schedule"] or {}).get("f32" if t == "float" else "f64")
+        if not sched:
             continue
-        for pname, prefix in PASS_KERNELS.items():
-            tot = sum(v["traffic_bytes"] * v["dispatches"] for k, v in ks.items() if k.startswith(prefix)) / nsolve
+        for pname in PASS_KERNELS:
+            ks = _pass_kernels(d["kernels"], pname, t, sched[PASS_INDEX[pname]])
+            if not ks:
+                continue
+            tot = sum(v["traffic_bytes"] * (2 if (k.startswith("k_c2r") and k.endswith(", 1>")) else 1)
+                      for k, v in ks.items())
             md.append("| %s | %s | %.1f | %.1f | %.3f |" % (pname, prec, tot / 1e6, kb[t][pname] / 1e6,
                                                            tot / kb[t][pname]))
     md += ["", "Source hash (sha256 of the library sources and build flags the counters describe): `%s`"
@@ -526,8 +550,8 @@ def main():
     dom64 = max(f64["passes"], key=lambda k: f64["passes"][k])
     ach64 = kb64[dom64] / (f64["passes"][dom64] * 1e-3) / 1e9
     traffic = load_traffic()
-    tr32 = traffic_of(traffic, dom, "f32")
-    tr64 = traffic_of(traffic, dom64, "f64")
+    tr32 = traffic_of(traffic, dom, "f32", f32["schedule"])
+    tr64 = traffic_of(traffic, dom64, "f64", f64["schedule"])
 
     line = {
         "metric": METRIC,

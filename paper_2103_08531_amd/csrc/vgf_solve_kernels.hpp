@@ -961,16 +961,20 @@ hipError_t launch_fused_v(const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g
   using TL = TileF<T, P, V>;
   const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
   if (bx == 0) return hipSuccess;
-  // one persistent workgroup per resident slot
-  static int slots = 0;
+  // one persistent workgroup per resident slot of the current device
+  constexpr int kMaxDevices = 64;
+  static int slots_of[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  int slots = __atomic_load_n(&slots_of[dev], __ATOMIC_RELAXED);
   if (slots == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fused<T, P, V>, TL::NT, 0) !=
             hipSuccess)
       return hipGetLastError();
     slots = cus * (per_cu > 0 ? per_cu : 1);
+    __atomic_store_n(&slots_of[dev], slots, __ATOMIC_RELAXED);
   }
   const int64_t total = bx * g.nentry;
   if (total > INT32_MAX) return hipErrorInvalidConfiguration;

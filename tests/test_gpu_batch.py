@@ -163,3 +163,26 @@ def test_batch_fp64_vs_oracle():
     batch.close()
     for p in plans.values():
         p.close()
+
+
+def test_batch_splits_groups_beyond_launch_limit():
+    """A plan whose strided launches would exceed 65535 batches is split into
+    several groups; every entry still equals vgf_solve (2D, n0 = 512: at most
+    127 entries per group)."""
+    torch, vgf = need_gpu()
+    n = (512, 8)
+    plan = vgf.Plan(n, (2.0 / 511, 2.0 / 7), precision="f32")
+    count = 130
+    batch = vgf.Batch([plan] * count, graph=True)
+    assert batch.groups == 2
+    rhos = [torch.from_numpy(W.random_field(300 + i, n)).to("cuda", torch.float32) for i in range(count)]
+    phis = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(count)]
+    Es = [torch.empty((2,) + n, dtype=torch.float32, device="cuda") for _ in range(count)]
+    batch.solve(rhos, phis, Es)
+    torch.cuda.synchronize()
+    for i in (0, 1, 126, 127, 128, 129):
+        p1, E1 = plan.solve(rhos[i])
+        torch.cuda.synchronize()
+        assert torch.equal(phis[i], p1) and torch.equal(Es[i], E1), i
+    batch.close()
+    plan.close()
