@@ -124,6 +124,25 @@ def test_fft_lengths(dim, N):
         plan.close()
 
 
+LONG_AXIS_CASES = [(384, 8, 12), (8, 384, 8), (8, 12, 384), (512, 8, 8), (8, 512, 12), (12, 8, 512)]
+
+
+@pytest.mark.parametrize("n", LONG_AXIS_CASES)
+def test_fft_lengths_3d_long_axes(n):
+    """Transform lengths 768 and 1024 on each 3D axis (the axis-1 passes meet
+    them only in 3D), thin grids so the oracle stays fast."""
+    h = tuple(2.0 / (x - 1) for x in n)
+    rho = W.random_field(sum(n), n)
+    say("long axis", n)
+    for precision, tol in (("f64", FP64_TOL), ("f32", FP32_TOL)):
+        plan = make_plan(n, h, "vgf", precision)
+        r = rounded_input(rho, precision)
+        phi_g, E_g = gpu_solve(plan, r)
+        phi_o, E_o = oracle_solve("vgf", n, h, plan.L, r)
+        check_fields(phi_g, E_g, phi_o, E_o, tol, "long %s %s" % (n, precision))
+        plan.close()
+
+
 def test_rectangular_grid():
     n = (16, 24, 32)
     lo = (-0.9, -1.0, -1.1)
