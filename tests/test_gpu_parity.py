@@ -252,3 +252,52 @@ def test_batched_matches_single():
                      "batched %s" % (ch.n,))
     for p in plans.values():
         p.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_degenerate_inputs(precision):
+    """rho = 0 gives exactly zero fields; a unit charge at the origin corner
+    gives phi = the kernel itself (phi[i] = w[i]) and E = the field kernel,
+    against the oracle's kernel and its cot-stencil field kernel."""
+    torch, vgf = need_gpu()
+    n = (12, 16, 8)
+    h = (0.15, 0.12, 0.2)
+    plan = make_plan(n, h, "vgf", precision)
+    phi, E = gpu_solve(plan, np.zeros(n))
+    assert np.all(phi == 0.0) and np.all(E == 0.0)
+    delta = np.zeros(n)
+    delta[0, 0, 0] = 1.0
+    phi, E = gpu_solve(plan, delta)
+    w = orc.vgf_kernel(n, h, plan.L)
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    assert rel_l2(phi, w) <= tol
+    Wp = orc.periodic_kernel(n, w)
+    for a in range(3):
+        V = orc.field_kernel(n, h, Wp, a)
+        Ea = V[:n[0], :n[1], :n[2]]  # E_a[i] = V_a[i - 0]
+        assert rel_l2(E[a], Ea) <= tol, a
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_largest_grid_512(precision):
+    """The largest supported grid, 512^3: a contained Gaussian (sigma = 0.1)
+    against its closed-form potential and field on a stride-16 subsample.
+    VGF is converged far below FP32 rounding here, so the bound is the
+    arithmetic's."""
+    torch, vgf = need_gpu()
+    ch = W.gaussian_3d_32(N=512)
+    say("512^3", precision, "plan ...")
+    plan = make_plan(ch.n, ch.h, "vgf", precision)
+    rho = ch.rho()
+    phi_g, E_g = gpu_solve(plan, rounded_input(rho, precision))
+    plan.close()
+    sub = tuple(slice(0, 512, 16) for _ in range(3))
+    n_s = (32, 32, 32)
+    h_s = tuple(16 * x for x in ch.h)
+    pa, Ea = orc.gauss_mixture_grid(n_s, ch.x0, h_s, ch.centers, ch.sigmas, ch.weights)
+    ep = rel_l2(phi_g[sub], pa)
+    eE = rel_l2(E_g[(slice(None),) + sub], Ea)
+    say("  512^3 %s vs analytic: phi %.3e E %.3e" % (precision, ep, eE))
+    bound = 1e-12 if precision == "f64" else 1e-5
+    assert ep <= bound and eE <= bound
