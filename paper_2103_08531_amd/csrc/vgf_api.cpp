@@ -611,10 +611,12 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
 
 // ---------------------------------------------------------------------------
 // Autotuning of the tile schedules. Each candidate schedule (every tunable
-// pass at variant v) runs one warm-up enqueue and `reps` timed ones; HIP
-// events at the pass boundaries give each pass's time, and each pass keeps
-// its fastest variant. The choice is cached per process for the grid,
-// precision, outputs and number of entries per launch.
+// pass at variant v) runs two warm-up enqueues, then the candidates run
+// interleaved `reps` times; HIP events at the pass boundaries give each
+// pass's time, each pass takes its fastest repetition per variant and keeps
+// the default unless another variant is more than 2% faster. The choice is
+// cached per process for the grid, precision, outputs, field mode and number
+// of entries per launch.
 // ---------------------------------------------------------------------------
 struct TuneKey {
   int prec, dim, outs, count;
@@ -694,8 +696,9 @@ vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, h
 template <class Run>
 vgf_status tune_cached(vgf_plan p, bool want_phi, bool want_E, int count, int reps, hipStream_t s, Run run,
                        int* sched_out, hipError_t* herr) {
-  TuneKey key{(int)p->prec, p->dim, (want_phi ? 1 : 0) | (want_E ? 2 : 0), count,
-              {p->n[0], p->n[1], p->dim == 3 ? p->n[2] : 0}};
+  // the pass structure depends on the outputs and on the field mode
+  const int outs = (want_phi ? 1 : 0) | (want_E ? 2 : 0) | (p->fd ? 4 : 0) | (p->gradk ? 8 : 0);
+  TuneKey key{(int)p->prec, p->dim, outs, count, {p->n[0], p->n[1], p->dim == 3 ? p->n[2] : 0}};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
