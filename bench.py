@@ -65,8 +65,8 @@ TRAFFIC_JSON = os.path.join(PROFILES, "k_fused_beam_3d_256_traffic.json")
 TRACE_MD = os.path.join(PROFILES, "vgf_solve_beam_3d_256_kernel_trace.md")
 CALIB_BYTES = 256 * 1024 * 1024
 # pass name -> kernel name prefix in rocprofv3 output (256^3: P = 512)
-PASS_KERNELS = {"r2c": "k_r2c", "c2c_fwd": "k_c2c_fwd", "fused_axis0": "k_fused<",
-                "c2c_inv": "k_c2c_inv", "c2r": "k_c2r"}
+PASS_KERNELS = {"r2c": "k_r2c_s<", "c2c_fwd": "k_c2c_fwd<", "fused": "k_fused_c<",
+                "c2c_inv": "k_c2c_inv<", "c2r": "k_c2r_s<"}
 
 
 def kernel_source_hash():
@@ -150,8 +150,8 @@ def load_traffic():
     return d if d.get("source_hash") == kernel_source_hash() else None
 
 
-PASS_INDEX = {"r2c": 0, "c2c_fwd": 1, "fused_axis0": 2, "c2c_inv": 3, "c2r": 4}
-TUNABLE = ("c2c_fwd", "fused_axis0", "c2c_inv")
+PASS_INDEX = {"r2c": 0, "c2c_fwd": 1, "fused": 2, "c2c_inv": 3, "c2r": 4}
+TUNABLE = ("r2c", "c2c_fwd", "c2c_inv", "c2r")
 
 
 def _pass_kernels(kernels, pass_name, t, variant):
@@ -304,7 +304,7 @@ def kernel_bytes(n, prec_bytes):
     return {
         "r2c": real + x1,
         "c2c_fwd": x1 + x2,
-        "fused_axis0": x2 + spec + 2 * x2,
+        "fused": x2 + spec + 2 * x2,
         "c2c_inv": 2 * x2 + 3 * x1,
         "c2r": 3 * x1 + 4 * real,
     }

@@ -87,7 +87,18 @@ typedef enum { VGF_F64 = 0, VGF_F32 = 1 } vgf_precision;
  *     "multiplying by the wavevector"). The plan stores dim more kernel
  *     spectra; the axis-0 pass multiplies every field by its own spectrum and
  *     inverts each field separately. Not accepted by vgf_batch_create. */
-enum { VGF_OUT_PHI = 1u, VGF_OUT_E = 2u, VGF_FIELD_CENTERED = 16u, VGF_FIELD_GRADIENT_KERNEL = 32u };
+/*   VGF_LAYOUT_AXIS0 : run the spectral multiply inside the axis-0 pass
+ *     (real-to-complex along the last axis, strided axis-0 multiply pass)
+ *     instead of the default (real-to-complex along axis 0, multiply pass
+ *     along the contiguous last axis). Both compute the same discrete
+ *     result; gradient-kernel plans always use this layout. */
+enum {
+  VGF_OUT_PHI = 1u,
+  VGF_OUT_E = 2u,
+  VGF_FIELD_CENTERED = 16u,
+  VGF_FIELD_GRADIENT_KERNEL = 32u,
+  VGF_LAYOUT_AXIS0 = 64u
+};
 
 /* Build a plan for a fixed grid (Sec. II: one precomputation per grid, then
  * a solve per right-hand side).
@@ -195,7 +206,7 @@ vgf_status vgf_batch_get_schedule(vgf_batch batch, int group, int* schedule);
 vgf_status vgf_batch_workspace_bytes(vgf_batch batch, size_t* bytes);
 
 /* Number of groups (distinct plans, split further when a group would exceed
- * 65535 / n0 entries); 0 for NULL. */
+ * 65535 / (n0 + 1) entries); 0 for NULL. */
 int vgf_batch_groups(vgf_batch batch);
 
 /* The hipError_t behind the batch's last VGF_ERR_HIP. */

@@ -58,6 +58,7 @@ struct vgf_plan_s {
   int schedule[5] = {0, 0, 0, 0, 0};  // tile variant per pass (VGF_PASS_* order)
   bool fd = false;               // E by finite differences of phi (VGF_FIELD_CENTERED)
   bool gradk = false;            // E by gradient kernels (VGF_FIELD_GRADIENT_KERNEL)
+  bool contig = false;           // multiply pass along the contiguous axis (else along axis 0)
   double* wgrad64 = nullptr;     // [dim][prod(n)] gradient-kernel octants, FP64
   double* specg64 = nullptr;     // [dim][prod(n+1)] their spectra T_a, FP64, unscaled
   void* specg = nullptr;         // [dim][prod(n+1)] plan type, scaled by 1/prod(P)
@@ -513,10 +514,123 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
   return VGF_OK;
 }
 
+// output o of an axis-0 complex-to-real launch: phi (field < 0) or E_field
+template <typename T>
+void c2r_s_out(vgf::C2RSArgs<T>& ca, int o, const Entries<T>& en, int field, int64_t vol) {
+  if (!en.phi_tab && !en.E_tab) {
+    ca.out[o] = field < 0 ? en.phi : en.E + field * vol;
+  } else {
+    ca.out[o] = nullptr;
+    ca.out_tab[o] = field < 0 ? en.phi_tab : en.E_tab;
+    ca.out_off[o] = field < 0 ? 0 : field * vol;
+  }
+}
+
+// Forward solve with the multiply pass along the contiguous last axis:
+//   rho [N0][..]  --r2c axis 0-->  X1 [N0+1][N1]([N2])
+//   (3D) X1       --c2c axis 1-->  X2 [N0+1][P1][N2]
+//   X2 (X1 in 2D) --axis-last pass: forward, x kernel, phi and -i k_last phi, inverse-->  Y
+//   (3D) Y        --c2c^-1 axis 1-->  Z: phi, E_1 (from phi), E_2
+//   Z (Y in 2D)   --c2r axis 0-->  phi, E_0 (from phi), and the other fields
+// Each pass again applies the derivative of its own axis.
+template <typename T>
+vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks, const int* sched,
+                           hipEvent_t* mark_events) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H0 = N0 + 1, NL = p->n[d - 1];
+  const int64_t vol = prod(p->n, d);
+  const bool want_phi = en.want_phi, want_E = en.want_E;
+  char* base = en.ws;
+  Bufs<T> b{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2), (cplx<T>*)(base + p->off_y),
+            (cplx<T>*)(base + p->off_z)};
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  Marks mk(p, s, marks, mark_events);
+  mk.mark();
+  vgf::R2CSArgs<T> ra{};
+  if (en.rho_tab) ra.in_tab[0] = en.rho_tab;
+  else ra.in[0] = en.rho;
+  ra.out = b.x1;
+  ra.out_es = en.es;
+  ra.ncols = vol / N0;
+  ra.nentry = en.count;
+  ra.d = deriv1<T>(p, 0, 0);
+  VGF_RUN(vgf::launch_r2c_s<T>((int)p->P[0], sched[kPassR2C], ra, tw(0), s));
+  mk.mark();
+  const cplx<T>* fin = b.x1;
+  vgf::FusedCGeom<T> g{};
+  g.dim = d;
+  g.n0 = (int)N0;
+  g.n1 = (int)N1;
+  g.n_last = (int)NL;
+  g.lpe = d == 3 ? H0 * p->P[1] : H0;
+  g.nlines = g.lpe * en.count;
+  g.in_es = g.out_es = en.es;
+  g.fs = g.lpe * NL;
+  g.ks = (T)wavenumber_step(p, d - 1);
+  g.nf = want_E ? 2 : 1;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], N2 = NL;
+    vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
+    fg.nentry = en.count;
+    fg.es_in = fg.es_out = en.es;
+    vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    mk.mark();
+    fin = b.x2;
+  }
+  VGF_RUN(vgf::launch_fused_c<T>((int)p->P[d - 1], false, fin, b.y, g, (const T*)p->spec, tw(d - 1), s));
+  mk.mark();
+  // axis-0 inputs: phi's spectrum, and the spectra of E_1 (3D) and E_last
+  const cplx<T>* zphi = b.y;
+  const cplx<T>* zf[2] = {nullptr, nullptr};  // E_1, E_2 (3D) or E_1 (2D)
+  int64_t zes = g.fs;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], N2 = NL, zfs = H0 * N1 * N2;
+    vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
+    ig.nentry = en.count;
+    ig.es_in = ig.es_out = en.es;
+    vgf::C2CInvArgs<T> ia{b.y, {b.z, b.z + zfs}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    if (want_E) {
+      vgf::C2CInvArgs<T> ia2{b.y + g.fs, {b.z + 2 * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia2, tw(1), s));
+    }
+    mk.mark();
+    zphi = b.z;
+    zf[0] = b.z + zfs;
+    zf[1] = b.z + 2 * zfs;
+    zes = zfs;
+  } else {
+    zf[0] = b.y + g.fs;
+  }
+  (void)zes;
+  auto c2r = [&](const cplx<T>* in, int f0, int code0, int f1, int code1) -> hipError_t {
+    vgf::C2RSArgs<T> ca{};
+    ca.in = in;
+    ca.in_es = en.es;
+    ca.ncols = vol / N0;
+    ca.nentry = en.count;
+    ca.d = f1 == -2 ? deriv1<T>(p, 0, code0) : deriv2<T>(p, 0, code0, code1);
+    c2r_s_out(ca, 0, en, f0, vol);
+    if (f1 != -2) c2r_s_out(ca, 1, en, f1, vol);
+    return vgf::launch_c2r_s<T>((int)p->P[0], sched[kPassC2R], ca, tw(0), s);
+  };
+  if (want_phi && want_E) VGF_RUN(c2r(zphi, -1, 0, 0, -1));
+  else if (want_phi) VGF_RUN(c2r(zphi, -1, 0, -2, 0));
+  else VGF_RUN(c2r(zphi, 0, -1, -2, 0));
+  if (want_E) {
+    VGF_RUN(c2r(zf[0], 1, 0, -2, 0));
+    if (d == 3) VGF_RUN(c2r(zf[1], 2, 0, -2, 0));
+  }
+  mk.mark();
+  return VGF_OK;
+}
+
 template <typename T>
 vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks,
                          const int* sched, hipEvent_t* mark_events = nullptr) {
   if (p->gradk) return enqueue_solve_grad<T>(p, en, s, marks, sched, mark_events);
+  if (p->contig) return enqueue_solve_c<T>(p, en, s, marks, sched, mark_events);
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -635,14 +749,19 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, std::array<int, kPasses>> g_tune_cache;
 
-bool pass_tunable(int dim, int pass) {
-  return pass == kPassFused || (dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
+// passes with tile-schedule variants: the strided ones of the plan's layout
+bool pass_tunable(vgf_plan p, int pass) {
+  if (p->gradk) return p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI);
+  if (p->contig)
+    return pass == kPassR2C || pass == kPassC2R || (p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
+  return pass == kPassFused || (p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
 }
 
 // run(sched, events) enqueues one solve (or one group of entries) with the
 // given schedule, recording the pass boundaries into events when non-null.
 template <class Run>
-vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, hipError_t* herr) {
+vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best, hipError_t* herr) {
+  const int dim = p->dim;
   constexpr int NV = vgf_tile_variants();
   const int nint = dim == 3 ? 5 : 3;
   static const int pass3[5] = {kPassR2C, kPassC2CF, kPassFused, kPassC2CI, kPassC2R};
@@ -654,7 +773,7 @@ vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, h
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
   int sched[NV][kPasses];
   for (int v = 0; v < NV; ++v)
-    for (int k = 0; k < kPasses; ++k) sched[v][k] = pass_tunable(dim, k) ? v : 0;
+    for (int k = 0; k < kPasses; ++k) sched[v][k] = pass_tunable(p, k) ? v : 0;
   vgf_status st = VGF_OK;
   // warm-up of every variant, then the variants interleaved rep by rep so
   // that clock ramps and cache state bias none of them
@@ -686,7 +805,7 @@ vgf_status tune_schedule(int dim, int reps, hipStream_t s, Run run, int* best, h
   // keep the default unless another variant is faster by more than 2%
   for (int k = 0; k < kPasses; ++k) {
     best[k] = 0;
-    if (!pass_tunable(dim, k)) continue;
+    if (!pass_tunable(p, k)) continue;
     for (int v = 1; v < NV; ++v)
       if (t[v][k] < 0.98 * t[best[k]][k]) best[k] = v;
   }
@@ -697,7 +816,8 @@ template <class Run>
 vgf_status tune_cached(vgf_plan p, bool want_phi, bool want_E, int count, int reps, hipStream_t s, Run run,
                        int* sched_out, hipError_t* herr) {
   // the pass structure depends on the outputs and on the field mode
-  const int outs = (want_phi ? 1 : 0) | (want_E ? 2 : 0) | (p->fd ? 4 : 0) | (p->gradk ? 8 : 0);
+  const int outs = (want_phi ? 1 : 0) | (want_E ? 2 : 0) | (p->fd ? 4 : 0) | (p->gradk ? 8 : 0) |
+                   (p->contig ? 16 : 0);
   TuneKey key{(int)p->prec, p->dim, outs, count, {p->n[0], p->n[1], p->dim == 3 ? p->n[2] : 0}};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -708,7 +828,7 @@ vgf_status tune_cached(vgf_plan p, bool want_phi, bool want_E, int count, int re
     }
   }
   int best[kPasses];
-  vgf_status st = tune_schedule(p->dim, reps, s, run, best, herr);
+  vgf_status st = tune_schedule(p, reps, s, run, best, herr);
   if (st != VGF_OK) return st;
   std::array<int, kPasses> a{};
   for (int k = 0; k < kPasses; ++k) a[k] = sched_out[k] = best[k];
@@ -810,9 +930,87 @@ vgf_status adjoint_grad_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hi
   return VGF_OK;
 }
 
+// Adjoint in the contiguous-multiply layout: the mirror image of
+// enqueue_solve_c (forward passes sum their inputs with +i k of their axis).
+template <typename T>
+vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H0 = N0 + 1, NL = p->n[d - 1];
+  const int64_t vol = prod(p->n, d);
+  Bufs<T> b = bufs<T>(p);
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  const int* sched = p->schedule;
+  const int64_t lpe = d == 3 ? H0 * p->P[1] : H0;
+  const int64_t fs = lpe * NL;             // field stride of Y
+  const int64_t zfs = H0 * N1 * (d == 3 ? NL : 1);  // field stride of Z (3D)
+  // axis 0: A = R2C(g_phi) + i k_0 R2C(g_E0); the other fields plain
+  auto r2c = [&](cplx<T>* out, const T* in0, int code0, const T* in1, int code1) -> hipError_t {
+    vgf::R2CSArgs<T> ra{};
+    ra.out = out;
+    ra.ncols = vol / N0;
+    ra.nentry = 1;
+    ra.d.ks = (T)wavenumber_step(p, 0);
+    ra.d.n = 0;
+    if (in0) { ra.in[ra.d.n] = in0; ra.d.code[ra.d.n++] = code0; }
+    if (in1) { ra.in[ra.d.n] = in1; ra.d.code[ra.d.n++] = code1; }
+    return vgf::launch_r2c_s<T>((int)p->P[0], sched[kPassR2C], ra, tw(0), s);
+  };
+  vgf::FusedCGeom<T> g{};
+  g.dim = d;
+  g.n0 = (int)N0;
+  g.n1 = (int)N1;
+  g.n_last = (int)NL;
+  g.lpe = lpe;
+  g.nlines = lpe;
+  g.fs = fs;
+  g.ks = (T)wavenumber_step(p, d - 1);
+  g.nf = 0;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], N2 = NL;
+    cplx<T>* za = b.z;
+    cplx<T>* zb1 = b.z + zfs;
+    cplx<T>* zb2 = b.z + 2 * zfs;
+    VGF_RUN(r2c(za, g_phi, 0, g_E, 1));
+    if (g_E) {
+      VGF_RUN(r2c(zb1, g_E + vol, 0, nullptr, 0));
+      VGF_RUN(r2c(zb2, g_E + 2 * vol, 0, nullptr, 0));
+    }
+    const vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
+    vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    g.fields[g.nf++] = 0;
+    if (g_E) {
+      vgf::C2CFwdArgs<T> f2{{zb2, nullptr}, b.y + fs, fg, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], f2, tw(1), s));
+      g.fields[g.nf++] = 1;
+    }
+    VGF_RUN(vgf::launch_fused_c<T>((int)p->P[2], true, b.y, b.x2, g, (const T*)p->spec, tw(2), s));
+    const vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
+    vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+  } else {
+    VGF_RUN(r2c(b.y, g_phi, 0, g_E, 1));
+    g.fields[g.nf++] = 0;
+    if (g_E) {
+      VGF_RUN(r2c(b.y + fs, g_E + vol, 0, nullptr, 0));
+      g.fields[g.nf++] = 1;
+    }
+    VGF_RUN(vgf::launch_fused_c<T>((int)p->P[1], true, b.y, b.x1, g, (const T*)p->spec, tw(1), s));
+  }
+  vgf::C2RSArgs<T> ca{};
+  ca.in = b.x1;
+  ca.out[0] = g_rho;
+  ca.ncols = vol / N0;
+  ca.nentry = 1;
+  ca.d = deriv1<T>(p, 0, 0);
+  VGF_RUN(vgf::launch_c2r_s<T>((int)p->P[0], sched[kPassC2R], ca, tw(0), s));
+  return VGF_OK;
+}
+
 template <typename T>
 vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
   if (p->gradk) return adjoint_grad_t<T>(p, g_phi, g_E, g_rho, s);
+  if (p->contig) return adjoint_c_t<T>(p, g_phi, g_E, g_rho, s);
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -911,7 +1109,8 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
       method != VGF_METHOD_HE_CELLAVG)
     return VGF_ERR_INVALID_ARG;
   if (prec != VGF_F64 && prec != VGF_F32) return VGF_ERR_INVALID_ARG;
-  if ((outputs & ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E | VGF_FIELD_CENTERED | VGF_FIELD_GRADIENT_KERNEL)) ||
+  if ((outputs &
+       ~(unsigned)(VGF_OUT_PHI | VGF_OUT_E | VGF_FIELD_CENTERED | VGF_FIELD_GRADIENT_KERNEL | VGF_LAYOUT_AXIS0)) ||
       !(outputs & (VGF_OUT_PHI | VGF_OUT_E)))
     return VGF_ERR_INVALID_ARG;
   if ((outputs & (VGF_FIELD_CENTERED | VGF_FIELD_GRADIENT_KERNEL)) && !(outputs & VGF_OUT_E))
@@ -958,6 +1157,9 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->nf_max = ((outputs & VGF_OUT_PHI) ? 1 : 0) + ((outputs & VGF_OUT_E) ? dim : 0);
   p->fd = (outputs & VGF_FIELD_CENTERED) != 0;
   p->gradk = (outputs & VGF_FIELD_GRADIENT_KERNEL) != 0;
+  // the multiply pass runs along the contiguous axis unless asked otherwise;
+  // gradient-kernel plans use the axis-0 layout
+  p->contig = !p->gradk && !(outputs & VGF_LAYOUT_AXIS0);
 
   const size_t rb = prec == VGF_F32 ? 4 : 8, cb = 2 * rb;
   const int64_t N0 = n[0], N1 = n[1], H = p->Hs;
@@ -976,7 +1178,19 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   size_t ny = fourier_E ? 2 : 1, nz = fourier_E ? 3 : 1;
   if (p->gradk) ny = nz = (size_t)(1 + dim);
   size_t x1 = 0, x2 = 0, y = 0, z = 0;
-  if (dim == 3) {
+  if (p->contig) {
+    // half spectrum along axis 0: [N0 + 1][N1]([N2]), no padding needed
+    const int64_t H0 = N0 + 1;
+    if (dim == 3) {
+      x1 = (size_t)(H0 * N1 * n[2]);
+      x2 = (size_t)(H0 * p->P[1] * n[2]);
+      y = ny * x2;
+      z = nz * x1;
+    } else {
+      x1 = (size_t)(H0 * N1);
+      y = ny * x1;
+    }
+  } else if (dim == 3) {
     x1 = (size_t)(N0 * N1 * H);
     x2 = (size_t)(N0 * p->P[1] * H);
     y = ny * x2;
@@ -1130,7 +1344,7 @@ vgf_status vgf_plan_set_schedule(vgf_plan p, const int* schedule) {
   if (!p || !schedule) return VGF_ERR_INVALID_ARG;
   for (int k = 0; k < kPasses; ++k) {
     if (schedule[k] < 0 || schedule[k] >= vgf_tile_variants()) return VGF_ERR_INVALID_ARG;
-    if (schedule[k] != 0 && !pass_tunable(p->dim, k)) return VGF_ERR_INVALID_ARG;
+    if (schedule[k] != 0 && !pass_tunable(p, k)) return VGF_ERR_INVALID_ARG;
   }
   for (int k = 0; k < kPasses; ++k) p->schedule[k] = schedule[k];
   return VGF_OK;
@@ -1415,10 +1629,10 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
   b->count = count;
   b->flags = flags;
   // group by plan, first appearance order; a group's strided launches cover
-  // n0 x entries batches, at most 65535
+  // (n0 + 1) x entries batches, at most 65535
   for (int i = 0; i < count; ++i) {
     const vgf_plan p = plans[i];
-    const int cap = (int)std::max<int64_t>(1, 65535 / p->n[0]);
+    const int cap = (int)std::max<int64_t>(1, 65535 / (p->n[0] + 1));
     vgf_batch_s::Group* hit = nullptr;
     for (auto& g : b->groups)
       if (g.plan == p && (int)g.idx.size() < cap) hit = &g;

@@ -127,6 +127,54 @@ template <typename T>
 hipError_t launch_fused(int P, int variant, bool adjoint, const cplx<T>* in, cplx<T>* out,
                         const FusedGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
 
+// ---- solve layout with the multiply pass along the contiguous axis ----
+// Axis-0 transforms of real data: two adjacent real columns travel as one
+// complex column. Real input / output arrays are [N0][ncols] (ncols even);
+// the half spectrum is [N0 + 1][ncols] complex. Entry e (blockIdx.y) uses the
+// pointer tables when given, else the direct pointers; workspace arrays of
+// entry e sit e * es elements from the first.
+template <typename T> struct R2CSArgs {
+  const T* in[2];
+  const T* const* in_tab[2];
+  int64_t in_off[2];
+  cplx<T>* out;
+  int64_t out_es;
+  int64_t ncols;  // real columns per row
+  int nentry;
+  Deriv<T> d;     // per input term: factor applied after its transform
+};
+template <typename T> struct C2RSArgs {
+  const cplx<T>* in;
+  int64_t in_es;
+  T* out[2];
+  T* const* out_tab[2];
+  int64_t out_off[2];
+  int64_t ncols;
+  int nentry;
+  Deriv<T> d;     // per output: factor applied before its transform
+};
+// Lines along the contiguous last axis (length n_last in, 2 n_last transformed)
+// of the arrays [H0][P1][n_last] (3D) or [H0][n_last] (2D), H0 = n0 + 1; line
+// (k0, k1) multiplies by the kernel-spectrum octant row (k0, fold(k1)).
+template <typename T> struct FusedCGeom {
+  int dim;
+  int n0, n1, n_last;
+  int64_t lpe;        // lines per entry: H0 * P1 (3D) or H0 (2D)
+  int64_t nlines;     // lines of all entries
+  int64_t in_es, out_es;
+  int64_t fs;         // field stride (elements): output fields (forward), input fields (adjoint)
+  T ks;               // 2 pi / (P_last h_last)
+  int nf;             // forward: 1 (phi) or 2 (phi, E_last); adjoint: inputs
+  int fields[2];      // adjoint: per input 0 or 1 (+i k_last)
+};
+template <typename T>
+hipError_t launch_r2c_s(int P, int variant, const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_c2r_s(int P, int variant, const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_c(int P, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
+                          const T* spec, const cplx<T>* tw, hipStream_t s);
+
 // Spectra of the gradient-kernel fields: s[0] the kernel spectrum octant,
 // s[1 + a] the octant of T_a (the 2N spectrum of the odd gradient kernel of
 // axis a is -i T_a), all in plan precision, divided by prod_a P_a. A fused

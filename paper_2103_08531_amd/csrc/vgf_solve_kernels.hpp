@@ -894,6 +894,331 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
 }
 
 // ---------------------------------------------------------------------------
+// Layout with the multiply along the contiguous axis. The real-to-complex
+// transform runs along axis 0 over strided columns (k_r2c_s), the complex
+// passes follow, the multiply-and-inverse pass runs along the contiguous
+// last axis with one wavefront per line group (k_fused_c), and the final
+// complex-to-real transform is again along axis 0 (k_c2r_s).
+//
+// Axis-0 real transforms: two adjacent real columns travel as one complex
+// column z = x_a + i x_b; after the transform
+//   X_a[k] = (Z[k] + conj Z[P-k]) / 2,  X_b[k] = -i (Z[k] - conj Z[P-k]) / 2,
+// exchanged through the LDS tile; the inverse builds Z from X_a, X_b the same
+// way. A workgroup covers NL column pairs (one 128-byte row segment of the
+// real array); blockIdx.y is the entry.
+// ---------------------------------------------------------------------------
+template <typename T, int P, int NTERM, int V>
+__global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void k_r2c_s(R2CSArgs<T> a,
+                                                                   const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TL = TileV<T, P, V>;
+  constexpr int NL = TL::NL, NT = TL::NT, LP = NL, N = P / 2, H = N + 1;
+  constexpr int NSTG = n_stages(P);
+  constexpr int NQ = NT / NL;
+  constexpr int NSLOT = (H + NQ - 1) / NQ;
+  using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
+  using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
+  __shared__ C lds[P * LP];
+  __shared__ C twl[P];
+  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  const int e = (int)blockIdx.y;
+  const int64_t npairs = a.ncols / 2;
+  const ColIO ci((int64_t)blockIdx.x * NL + l, npairs, npairs);
+  stage_twiddles<C, P, NT>(twl, tw, tid);
+
+  C acc_a[NSLOT], acc_b[NSLOT];
+#pragma unroll
+  for (int term = 0; term < NTERM; ++term) {
+    const T* base = a.in_tab[term] ? a.in_tab[term][e] + a.in_off[term] : a.in[term];
+    const C* __restrict__ src = reinterpret_cast<const C*>(base);
+    const int code = a.d.code[term];
+    if (term > 0) __syncthreads();  // the previous term's reads of the tile are done
+    typename S0::Regs g0;
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
+    S0::butterflies(g0, q);
+    S0::lds_out(g0, lds, l, q);
+    __syncthreads();
+    typename SL::Regs gl;
+    middle_and_last<T, P, NT, NL, LP, -1>(gl, lds, twl, l, q);
+    __syncthreads();
+    SL::lds_out(gl, lds, l, q);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const int k = q + NQ * s;
+      if (k >= H) continue;
+      const C z = lds[lds_index<0, LP>(k, l)];
+      const C zm = lds[lds_index<0, LP>((P - k) % P, l)];
+      C xa = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+      C xb = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
+      if (code != 0) {
+        const T kk = a.d.ks * (T)(k < N ? k : 0);
+        xa = deriv(xa, code, kk);
+        xb = deriv(xb, code, kk);
+      }
+      if (term == 0) {
+        acc_a[s] = xa;
+        acc_b[s] = xb;
+      } else {
+        acc_a[s].x += xa.x; acc_a[s].y += xa.y;
+        acc_b[s].x += xb.x; acc_b[s].y += xb.y;
+      }
+    }
+  }
+  if (!ci.valid) return;
+  C* __restrict__ out = a.out + e * a.out_es + 2 * (int64_t)ci.col;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int k = q + NQ * s;
+    if (k >= H) continue;
+    out[k * a.ncols] = acc_a[s];
+    out[k * a.ncols + 1] = acc_b[s];
+  }
+}
+
+template <typename T, int P, int NOUT, int V>
+__global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void k_c2r_s(C2RSArgs<T> a,
+                                                                   const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TL = TileV<T, P, V>;
+  constexpr int NL = TL::NL, NT = TL::NT, LP = NL, N = P / 2, H = N + 1;
+  constexpr int NSTG = n_stages(P);
+  constexpr int NQ = NT / NL;
+  constexpr int NSLOT = (H + NQ - 1) / NQ;
+  using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
+  using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
+  __shared__ C lds[P * LP];
+  __shared__ C twl[P];
+  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  const int e = (int)blockIdx.y;
+  const int64_t npairs = a.ncols / 2;
+  const ColIO ci((int64_t)blockIdx.x * NL + l, npairs, npairs);
+  const C* __restrict__ in = a.in + e * a.in_es + 2 * (int64_t)ci.col;
+  C xs[NSLOT], ys[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int k = q + NQ * s;
+    xs[s] = ys[s] = C{T(0), T(0)};
+    if (k >= H) continue;
+    xs[s] = in[k * a.ncols];
+    ys[s] = in[k * a.ncols + 1];
+  }
+  stage_twiddles<C, P, NT>(twl, tw, tid);
+
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int code = a.d.code[o];
+    __syncthreads();  // twiddles staged / the previous output's reads are done
+    // Z[k] = X[k] + i Y[k], Z[P-k] = conj X[k] + i conj Y[k]; the imaginary
+    // parts of X, Y at k = 0 and k = N are dropped (real by symmetry)
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const int k = q + NQ * s;
+      if (k >= H) continue;
+      C X = xs[s], Y = ys[s];
+      if (code != 0) {
+        const T kk = a.d.ks * (T)(k < N ? k : 0);
+        X = deriv(X, code, kk);
+        Y = deriv(Y, code, kk);
+      }
+      if (k == 0 || k == N) {
+        lds[lds_index<0, LP>(k, l)] = C{X.x, Y.x};
+      } else {
+        lds[lds_index<0, LP>(k, l)] = C{X.x - Y.y, X.y + Y.x};
+        lds[lds_index<0, LP>(P - k, l)] = C{X.x + Y.y, Y.x - X.y};
+      }
+    }
+    __syncthreads();
+    typename S0::Regs g0;
+    S0::template load_first<false>(g0, q, [&](int j, int r) { return lds[lds_index<0, LP>(S0::in_pos(j, r), l)]; });
+    S0::butterflies(g0, q);
+    __syncthreads();
+    S0::lds_out(g0, lds, l, q);
+    __syncthreads();
+    typename SL::Regs gl;
+    middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
+    if (ci.valid) {
+      T* base = a.out_tab[o] ? a.out_tab[o][e] + a.out_off[o] : a.out[o];
+      C* __restrict__ dst = reinterpret_cast<C*>(base);
+      SL::template store_last<true>(gl, q, [&](int j, int r, C v) { dst[ci.off<SL::NB>(j, r)] = v; });
+    }
+  }
+}
+
+// Multiply-and-inverse pass along the contiguous last axis: one wavefront per
+// group of LPW lines (lanes along the line, every exchange inside the
+// wavefront). Line (k0, k1) of length n_last is transformed forward (pruned
+// input), multiplied by the kernel-spectrum octant row (k0, fold(k1)) at
+// fold(k_last), and inverted (pruned output) as phi's spectrum and, when
+// requested, as -i k_last times it (E_last).
+template <typename T, int P>
+__global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c(const cplx<T>* __restrict__ in,
+                                                              cplx<T>* __restrict__ out, FusedCGeom<T> g,
+                                                              const T* __restrict__ spec,
+                                                              const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TW = TileW<T, P>;
+  constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
+  constexpr int NSTG = n_stages(P);
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+  __shared__ C tiles[TW::WPB * LPW * LP];
+  __shared__ C twl[P];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = lane / NQ, q = lane % NQ;
+  C* tile = tiles + w * LPW * LP;
+  const int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
+  const bool valid = line < g.nlines;
+  const EntryLine el(valid ? line : 0, g.lpe, g.nlines);
+  const int64_t ll = el.line;
+  int64_t row;  // octant row of this line
+  if (g.dim == 3) {
+    const int P1 = 2 * g.n1;
+    const int k0 = (int)(ll / P1), k1 = (int)(ll - (int64_t)k0 * P1);
+    row = (int64_t)k0 * (g.n1 + 1) + (k1 <= g.n1 ? k1 : P1 - k1);
+  } else {
+    row = ll;
+  }
+  const T* __restrict__ srow = spec + row * (N + 1);
+  const C* __restrict__ src = in + el.e * g.in_es + ll * N;
+  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
+
+  typename S0::Regs g0;
+  S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+  S0::butterflies(g0, q);
+  S0::lds_out(g0, tile, l, q);
+  wave_sync();
+  typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
+  middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t) {
+    if (!SL::active(t, q)) continue;
+    const int j = q + t * SL::NQ;
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) {
+      const int p = j + r * SL::NB;
+      const T sv = srow[p <= N ? p : P - p];
+      rh.v[t][r].x *= sv;
+      rh.v[t][r].y *= sv;
+    }
+  }
+  for (int fi = 0; fi < g.nf; ++fi) {
+    typename IS0::Regs v;
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
+      const int j = q + t * SL::NQ;
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r)
+        v.v[t][r] = fi == 0 ? rh.v[t][r] : deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks, j, r));
+    }
+    IS0::butterflies(v, q);
+    wave_sync();  // the previous transform's reads of the tile are done
+    IS0::lds_out(v, tile, l, q);
+    wave_sync();
+    typename ISL::Regs o;
+    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, twl, l, q);
+    if (valid) {
+      C* __restrict__ dst = out + el.e * g.out_es + fi * g.fs + ll * N;
+      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
+    }
+  }
+}
+
+// adjoint: acc = sum_f conj(m_f) FFT(in_f) (m_f = 1 or -i k_last), times the
+// real kernel spectrum, inverted with pruned output
+template <typename T, int P>
+__global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>* __restrict__ in,
+                                                                  cplx<T>* __restrict__ out, FusedCGeom<T> g,
+                                                                  const T* __restrict__ spec,
+                                                                  const cplx<T>* __restrict__ tw) {
+  using C = cplx<T>;
+  using TW = TileW<T, P>;
+  constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
+  constexpr int NSTG = n_stages(P);
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+  __shared__ C tiles[TW::WPB * LPW * LP];
+  __shared__ C twl[P];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = lane / NQ, q = lane % NQ;
+  C* tile = tiles + w * LPW * LP;
+  const int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
+  const bool valid = line < g.nlines;
+  const EntryLine el(valid ? line : 0, g.lpe, g.nlines);
+  const int64_t ll = el.line;
+  int64_t row;
+  if (g.dim == 3) {
+    const int P1 = 2 * g.n1;
+    const int k0 = (int)(ll / P1), k1 = (int)(ll - (int64_t)k0 * P1);
+    row = (int64_t)k0 * (g.n1 + 1) + (k1 <= g.n1 ? k1 : P1 - k1);
+  } else {
+    row = ll;
+  }
+  const T* __restrict__ srow = spec + row * (N + 1);
+  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
+
+  typename IS0::Regs acc;
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t)
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
+  for (int fi = 0; fi < g.nf; ++fi) {
+    const C* __restrict__ src = in + el.e * g.in_es + fi * g.fs + ll * N;
+    typename S0::Regs g0;
+    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+    S0::butterflies(g0, q);
+    wave_sync();  // the previous field's reads of the tile are done
+    S0::lds_out(g0, tile, l, q);
+    wave_sync();
+    typename SL::Regs rh;
+    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+    const bool d = g.fields[fi] != 0;
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
+      const int j = q + t * SL::NQ;
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        const C m = d ? deriv(rh.v[t][r], 1, axis_k<T, SL::R, SL::NB>(g.ks, j, r)) : rh.v[t][r];
+        acc.v[t][r].x += m.x;
+        acc.v[t][r].y += m.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < SL::NTASK; ++t) {
+    if (!SL::active(t, q)) continue;
+    const int j = q + t * SL::NQ;
+#pragma unroll
+    for (int r = 0; r < SL::R; ++r) {
+      const int p = j + r * SL::NB;
+      const T sv = srow[p <= N ? p : P - p];
+      acc.v[t][r].x *= sv;
+      acc.v[t][r].y *= sv;
+    }
+  }
+  IS0::butterflies(acc, q);
+  wave_sync();
+  IS0::lds_out(acc, tile, l, q);
+  wave_sync();
+  typename ISL::Regs o;
+  middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, twl, l, q);
+  if (valid) {
+    C* __restrict__ dst = out + el.e * g.out_es + ll * N;
+    ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 #define VGF_FOR_EACH_P(X) \
@@ -1029,6 +1354,64 @@ hipError_t launch_fused_grad_p(bool adjoint, const cplx<T>* in, cplx<T>* out, co
   return hipGetLastError();
 }
 
+template <typename T, int P, int V>
+hipError_t launch_r2c_s_v(const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  using TL = TileV<T, P, V>;
+  if (a.ncols % 2 != 0) return hipErrorInvalidValue;
+  const int64_t bx = (a.ncols / 2 + TL::NL - 1) / TL::NL;
+  if (bx == 0 || a.nentry == 0 || a.d.n == 0) return hipSuccess;
+  if (a.nentry > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)bx, (unsigned)a.nentry);
+  if (a.d.n == 2)
+    hipLaunchKernelGGL((k_r2c_s<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL((k_r2c_s<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int P, int V>
+hipError_t launch_c2r_s_v(const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  using TL = TileV<T, P, V>;
+  if (a.ncols % 2 != 0) return hipErrorInvalidValue;
+  const int64_t bx = (a.ncols / 2 + TL::NL - 1) / TL::NL;
+  if (bx == 0 || a.nentry == 0 || a.d.n == 0) return hipSuccess;
+  if (a.nentry > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)bx, (unsigned)a.nentry);
+  if (a.d.n == 2)
+    hipLaunchKernelGGL((k_c2r_s<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  else
+    hipLaunchKernelGGL((k_c2r_s<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_r2c_s_p(int variant, const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  return variant == 1 ? launch_r2c_s_v<T, P, 1>(a, tw, s) : launch_r2c_s_v<T, P, 0>(a, tw, s);
+}
+
+template <typename T, int P>
+hipError_t launch_c2r_s_p(int variant, const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  return variant == 1 ? launch_c2r_s_v<T, P, 1>(a, tw, s) : launch_c2r_s_v<T, P, 0>(a, tw, s);
+}
+
+template <typename T, int P>
+hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
+                            const T* spec, const cplx<T>* tw, hipStream_t s) {
+  using TW = TileW<T, P>;
+  if (g.nf == 0 || g.nlines == 0) return hipSuccess;
+  if (g.nf > 2 || (g.lpe > 0 && g.nlines % g.lpe != 0)) return hipErrorInvalidValue;
+  const int64_t per_block = (int64_t)TW::WPB * TW::LPW;
+  const int64_t blocks = (g.nlines + per_block - 1) / per_block;
+  if (adjoint)
+    hipLaunchKernelGGL((k_fused_c_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw);
+  else
+    hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw);
+  return hipGetLastError();
+}
+
+#define VGF_CASE_R2CS(PP) case PP: return launch_r2c_s_p<VGF_T, PP>(variant, a, tw, s);
+#define VGF_CASE_C2RS(PP) case PP: return launch_c2r_s_p<VGF_T, PP>(variant, a, tw, s);
+#define VGF_CASE_FC(PP) case PP: return launch_fused_c_p<VGF_T, PP>(adjoint, in, out, g, spec, tw, s);
 #define VGF_CASE_R2C(PP) case PP: return launch_r2c_p<VGF_T, PP>(a, tw, s);
 #define VGF_CASE_FGRAD(PP) case PP: return launch_fused_grad_p<VGF_T, PP>(adjoint, in, out, g, sp, tw, s);
 #define VGF_CASE_C2R(PP) case PP: return launch_c2r_p<VGF_T, PP>(a, tw, s);
@@ -1060,6 +1443,22 @@ hipError_t launch_fused_grad_p(bool adjoint, const cplx<T>* in, cplx<T>* out, co
                              const FusedGeom<T>& g, const T* spec, const cplx<T>* tw,           \
                              hipStream_t s) {                                                   \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_FUSED) default: return hipErrorInvalidValue; }         \
+  }                                                                                             \
+  template <>                                                                                   \
+  hipError_t launch_r2c_s<T>(int P, int variant, const R2CSArgs<T>& a, const cplx<T>* tw,      \
+                             hipStream_t s) {                                                   \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_R2CS) default: return hipErrorInvalidValue; }          \
+  }                                                                                             \
+  template <>                                                                                   \
+  hipError_t launch_c2r_s<T>(int P, int variant, const C2RSArgs<T>& a, const cplx<T>* tw,      \
+                             hipStream_t s) {                                                   \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2RS) default: return hipErrorInvalidValue; }          \
+  }                                                                                             \
+  template <>                                                                                   \
+  hipError_t launch_fused_c<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,            \
+                               const FusedCGeom<T>& g, const T* spec, const cplx<T>* tw,        \
+                               hipStream_t s) {                                                 \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FC) default: return hipErrorInvalidValue; }            \
   }                                                                                             \
   template <>                                                                                   \
   hipError_t launch_fused_grad<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,         \

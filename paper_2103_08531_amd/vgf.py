@@ -20,7 +20,7 @@ STATUS = {0: "VGF_OK", -1: "VGF_ERR_INVALID_ARG", -2: "VGF_ERR_UNSUPPORTED_SIZE"
           -6: "VGF_ERR_NOT_REQUESTED"}
 METHODS = {"vgf": 0, "he": 1, "he_nearby": 2, "he_cellavg": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
-OUT_PHI, OUT_E, FIELD_CENTERED, FIELD_GRADIENT_KERNEL = 1, 2, 16, 32
+OUT_PHI, OUT_E, FIELD_CENTERED, FIELD_GRADIENT_KERNEL, LAYOUT_AXIS0 = 1, 2, 16, 32, 64
 EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batched",
            "vgf_plan_get_L", "vgf_plan_workspace_bytes", "vgf_plan_get_kernel",
            "vgf_plan_get_spectrum", "vgf_plan_hip_error", "vgf_plan_destroy",
@@ -30,8 +30,8 @@ EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batch
            "vgf_plan_set_schedule", "vgf_batch_autotune", "vgf_batch_get_schedule",
            "vgf_plan_get_gradient_kernel", "vgf_plan_get_gradient_spectrum"]
 BATCH_GRAPH = 1
-PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused_axis0", "c2c_inv", "c2r"],
-              2: ["r2c", "fused_axis0", "c2r"]}
+PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused", "c2c_inv", "c2r"],
+              2: ["r2c", "fused", "c2r"]}
 
 
 class VGFError(RuntimeError):
@@ -139,11 +139,14 @@ class Plan:
     precision 'f64' or 'f32'; L: VGF truncation radius (None: 1.1 x diameter);
     outputs: subset of {'phi', 'E'}; field: 'fourier' (default), 'centered'
     (E by second-order finite differences of phi) or 'gradient_kernel' (E_a =
-    w_a * rho with the restricted 4N transform of -i k_a Ghat; VGF only).
+    w_a * rho with the restricted 4N transform of -i k_a Ghat; VGF only);
+    layout: 'contiguous' (default: the spectral multiply runs along the
+    contiguous last axis) or 'axis0' (inside the strided axis-0 pass; the
+    layout gradient-kernel plans always use).
     """
 
     def __init__(self, n, h, method="vgf", precision="f64", L=None, outputs=("phi", "E"),
-                 stream=None, field="fourier"):
+                 stream=None, field="fourier", layout="contiguous"):
         torch = _torch()
         self.n = tuple(int(x) for x in n)
         self.h = tuple(float(x) for x in h)
@@ -160,6 +163,10 @@ class Plan:
             flags |= FIELD_CENTERED
         elif field == "gradient_kernel":
             flags |= FIELD_GRADIENT_KERNEL
+        if layout not in ("contiguous", "axis0"):
+            raise ValueError("layout must be 'contiguous' or 'axis0'")
+        if layout == "axis0":
+            flags |= LAYOUT_AXIS0
         n_arr = (C.c_int64 * self.dim)(*self.n)
         h_arr = (C.c_double * self.dim)(*self.h)
         handle = C.c_void_p()

@@ -138,7 +138,7 @@ def test_field_mode_flags_are_checked(V):
     assert _create(V, outputs=1 | 32)[0] == -1
     assert _create(V, outputs=3 | 16 | 32)[0] == -1
     assert _create(V, method=1, outputs=3 | 32)[0] == -1
-    assert _create(V, outputs=3 | 64)[0] == -1
+    assert _create(V, outputs=3 | 128)[0] == -1
     L = V.lib()
     out = (C.c_double * 8)()
     assert L.vgf_plan_get_gradient_kernel(None, 0, out) == -1
