@@ -3,22 +3,22 @@
 Workload (synthetic, seeded): beam_3d_256 -- 3D grid of 256^3 points on
 [-1,1]^3, one unit anisotropic Gaussian sigma = (0.05, 0.05, 0.3) whose
 centroid is drawn uniformly in the ball of radius 0.05 (seed 0). One step is
-one VGF solve on a fixed plan: pruned R2C along axis 2, C2C along axis 1, the
-fused axis-0 pass (forward FFT, spectral multiply by the kernel spectrum and
-by -i k_0 times it, two inverse FFTs), inverse C2C along axis 1 (phi's
-spectrum also yields E_1) and C2R along axis 2 (phi's spectrum also yields
-E_2), producing phi and E (the one-time FP64 kernel precompute runs
-at plan creation and is not part of a step). rho is resident in HBM before
-the timed region.
+one VGF solve on a fixed plan: pruned R2C along axis 0, C2C along axis 1,
+the multiply pass along the contiguous axis 2 (forward FFT, multiply by the
+kernel spectrum and by -i k_2 times it, two inverse FFTs), inverse C2C along
+axis 1 (phi's spectrum also yields E_1) and C2R along axis 0 (phi's spectrum
+also yields E_0), producing phi and E (the one-time FP64 kernel precompute
+runs at plan creation and is not part of a step). rho is resident in HBM
+before the timed region.
 
 Printed JSON line (one, rank 0):
   value        FP32 solves/s (whole job, one GPU)
   fp64         the same for FP64 solves
-  roofline     for the dominant kernel (the pass with the largest mean
+  roofline     for the dominant kernel (the launch with the largest mean
                duration): its algorithmic bytes per launch divided by its mean
-               duration measured with HIP events recorded by the library on
-               the solve stream during the timed region, against the MI355X's
-               8 TB/s HBM peak
+               duration measured with HIP events recorded by the library after
+               every launch on the solve stream during the timed region,
+               against the MI355X's 8 TB/s HBM peak
   pass_model   the whole solve against the same peak, using one HBM read and
                write per axis pass of the pruned arrays
   cpu_baseline the FP64 CPU oracle's 2N FFT path on the same input, timed on
@@ -38,7 +38,7 @@ rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
 same counter reads for a plain 256 MiB device-to-device copy in the same run
 (--copy-calibration). `--digest-counters FETCH_CSV FETCH_OUT WRITE_CSV WRITE_OUT` turns the two
 counter files (with the two profiled runs' outputs, which must carry the
-current source hash) into profiles/k_fused_beam_3d_256_traffic.{json,md},
+current source hash) into profiles/vgf_solve_beam_3d_256_traffic.{json,md},
 stamped with a hash of the library sources; a bench run reports the traffic
 only while the sources still hash the same, else null. `--digest-trace STATS_CSV` turns a
 `rocprofv3 --kernel-trace --stats` summary into
@@ -61,14 +61,9 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 METRIC = "3D VGF solves/s at N=256^3 FP32 vs FP64 + HBM GB/s, at stated rel-L2 error"
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_JSON = os.path.join(PROFILES, "k_fused_beam_3d_256_traffic.json")
+TRAFFIC_JSON = os.path.join(PROFILES, "vgf_solve_beam_3d_256_traffic.json")
 TRACE_MD = os.path.join(PROFILES, "vgf_solve_beam_3d_256_kernel_trace.md")
 CALIB_BYTES = 256 * 1024 * 1024
-# pass name -> kernel name prefix in rocprofv3 output (256^3: P = 512)
-PASS_KERNELS = {"r2c": "k_r2c_s<", "c2c_fwd": "k_c2c_fwd<", "fused": "k_fused_c<",
-                "c2c_inv": "k_c2c_inv<", "c2r": "k_c2r_s<"}
-
-
 def kernel_source_hash():
     """sha256 over the library's sources and build flags: counter data taken
     from other sources no longer describe the kernels that run."""
@@ -151,32 +146,6 @@ def load_traffic():
 
 
 PASS_INDEX = {"r2c": 0, "c2c_fwd": 1, "fused": 2, "c2c_inv": 3, "c2r": 4}
-TUNABLE = ("r2c", "c2c_fwd", "c2c_inv", "c2r")
-
-
-def _pass_kernels(kernels, pass_name, t, variant):
-    """Kernels (name -> data) of one pass at precision t ('float'/'double'),
-    P = 512, restricted to the tile-schedule variant for tunable passes."""
-    out = {}
-    for k, v in kernels.items():
-        if not k.startswith(PASS_KERNELS[pass_name]) or ("<%s, 512" % t) not in k:
-            continue
-        if pass_name in TUNABLE and not k.endswith(", %d>" % variant):
-            continue
-        out[k] = v
-    return out
-
-
-def traffic_of(traffic, pass_name, prec, schedule):
-    """Scaled HBM bytes per launch of a pass's kernel (256^3, P = 512) under
-    the tile schedule the timed solves used."""
-    if traffic is None or pass_name != "fused_axis0":
-        return None
-    t = "float" if prec == "f32" else "double"
-    hits = _pass_kernels(traffic["kernels"], pass_name, t, schedule[PASS_INDEX[pass_name]])
-    if len(hits) != 1:
-        return None
-    return next(iter(hits.values()))["traffic_bytes"]
 
 
 def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
@@ -186,7 +155,12 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
         f.write("\n")
-    kb = {"float": kernel_bytes((256, 256, 256), 4), "double": kernel_bytes((256, 256, 256), 8)}
+    # algorithmic bytes per launch of every kernel a solve launches, both tile variants
+    alg_of = {}
+    for prec in ("f32", "f64"):
+        for pname, pattern, nbytes in launch_model((256, 256, 256), 4 if prec == "f32" else 8):
+            for v in (0, 1):
+                alg_of[launch_kernel_name(pattern, prec, [v] * 5, pname)] = nbytes
     md = [ "# HBM traffic per launch: VGF solve kernels, beam_3d_256 (3D 256^3, phi+E), FP32 and FP64", "",
           "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 run each, averaged over "
           "the dispatches of each kernel. Each is scaled by the factor that maps its reading for a plain "
@@ -202,33 +176,28 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
           "|---|---|---|---|---|---|---|"]
     for name in sorted(d["kernels"]):
         v = d["kernels"][name]
-        alg = None
-        for pname, prefix in PASS_KERNELS.items():
-            for t in ("float", "double"):
-                if name.startswith(prefix) and ("<%s, 512" % t) in name:
-                    alg = kb[t][pname]  # per launch for the single-launch passes
-        # c2c_inv and c2r run as several launches (fields split between them): see the per-pass table
-        ratio = "%.3f" % (v["traffic_bytes"] / alg) if alg and not name.startswith(("k_c2c_inv", "k_c2r")) else "-"
+        alg = alg_of.get(name)
         md.append("| %s | %d | %.1f | %.1f | %.1f | %s | %s |" % (
             name, v["dispatches"], v["read_bytes"] / 1e6, v["write_bytes"] / 1e6, v["traffic_bytes"] / 1e6,
-            "%.1f" % (alg / 1e6) if alg and ratio != "-" else "-", ratio))
+            "%.1f" % (alg / 1e6) if alg else "-", "%.3f" % (v["traffic_bytes"] / alg) if alg else "-"))
     md += ["", "The run autotunes each plan's tile schedule first, so both variants of the strided kernels "
-           "(last template argument) appear above. Per solve and pass, with the schedule the timed solves "
-           "used (%s): one launch of each kernel per solve, except k_c2r<., ., 1>, launched twice "
-           "(E_1 and E_0):" % json.dumps(d["schedule"]), "",
+           "(last template argument) appear above. Per solve and pass, with the launches of one solve and "
+           "the schedule the timed solves used (%s):" % json.dumps(d["schedule"]), "",
            "| pass | precision | traffic MB | algorithmic MB | traffic / algorithmic |", "|---|---|---|---|---|"]
-    for t, prec in (("float", "FP32"), ("double", "FP64")):
-        sched = (d["schedule"] or {}).get("f32" if t == "float" else "f64")
+    for prec, label in (("f32", "FP32"), ("f64", "FP64")):
+        sched = (d["schedule"] or {}).get(prec)
         if not sched:
             continue
-        for pname in PASS_KERNELS:
-            ks = _pass_kernels(d["kernels"], pname, t, sched[PASS_INDEX[pname]])
-            if not ks:
+        tot, alg = {}, {}
+        for pname, pattern, nbytes in launch_model((256, 256, 256), 4 if prec == "f32" else 8):
+            v = d["kernels"].get(launch_kernel_name(pattern, prec, sched, pname))
+            if v is None:
                 continue
-            tot = sum(v["traffic_bytes"] * (2 if (k.startswith("k_c2r") and k.endswith(", 1>")) else 1)
-                      for k, v in ks.items())
-            md.append("| %s | %s | %.1f | %.1f | %.3f |" % (pname, prec, tot / 1e6, kb[t][pname] / 1e6,
-                                                           tot / kb[t][pname]))
+            tot[pname] = tot.get(pname, 0.0) + v["traffic_bytes"]
+            alg[pname] = alg.get(pname, 0) + nbytes
+        for pname in tot:
+            md.append("| %s | %s | %.1f | %.1f | %.3f |" % (pname, label, tot[pname] / 1e6, alg[pname] / 1e6,
+                                                           tot[pname] / alg[pname]))
     md += ["", "Source hash (sha256 of the library sources and build flags the counters describe): `%s`"
            % d["source_hash"], ""]
     with open(TRAFFIC_JSON[:-5] + ".md", "w") as f:
@@ -289,25 +258,43 @@ def pass_model_bytes(n, prec_bytes, nf=4):
     return (real + x1) + (x1 + x2) + (x2 + spec + nf * x2) + nf * (x2 + x1) + nf * (x1 + real)
 
 
-def kernel_bytes(n, prec_bytes):
-    """Algorithmic HBM bytes of each pass as this library structures the solve
-    (phi + E): the axis-0 pass writes the spectra of phi and E_0 only, the
-    axis-1 inverse writes phi, E_1 (from phi) and E_0, and the last pass
-    writes phi, E_2 (from phi), E_1 and E_0."""
+def launch_model(n, prec_bytes):
+    """The launches of one 3D solve (phi + E) in the default layout, in order:
+    (pass, kernel name pattern at P = 2N, algorithmic HBM bytes). The
+    multiply pass runs along the last axis and writes the spectra of phi and
+    E_2; the axis-1 inverse writes phi and E_1 (from phi), then E_2; the
+    axis-0 complex-to-real pass writes phi and E_0 (from phi), then E_1, then
+    E_2. Arrays: X1 = [N0+1][N1][N2], X2 = [N0+1][2 N1][N2] complex."""
     N0, N1, N2 = n
-    P1, H = 2 * N1, N2 + 1
+    P = 2 * N2
     rb, cb = prec_bytes, 2 * prec_bytes
-    x1 = N0 * N1 * H * cb
-    x2 = N0 * P1 * H * cb
+    x1 = (N0 + 1) * N1 * N2 * cb
+    x2 = (N0 + 1) * 2 * N1 * N2 * cb
     spec = (N0 + 1) * (N1 + 1) * (N2 + 1) * rb
     real = N0 * N1 * N2 * rb
-    return {
-        "r2c": real + x1,
-        "c2c_fwd": x1 + x2,
-        "fused": x2 + spec + 2 * x2,
-        "c2c_inv": 2 * x2 + 3 * x1,
-        "c2r": 3 * x1 + 4 * real,
-    }
+    return [
+        ("r2c", "k_r2c_s<{t}, %d, 1, {v}>" % P, real + x1),
+        ("c2c_fwd", "k_c2c_fwd<{t}, %d, 1, {v}>" % P, x1 + x2),
+        ("fused", "k_fused_c<{t}, %d>" % P, x2 + spec + 2 * x2),
+        ("c2c_inv", "k_c2c_inv<{t}, %d, 2, {v}>" % P, x2 + 2 * x1),
+        ("c2c_inv", "k_c2c_inv<{t}, %d, 1, {v}>" % P, x2 + x1),
+        ("c2r", "k_c2r_s<{t}, %d, 2, {v}>" % P, x1 + 2 * real),
+        ("c2r", "k_c2r_s<{t}, %d, 1, {v}>" % P, x1 + real),
+        ("c2r", "k_c2r_s<{t}, %d, 1, {v}>" % P, x1 + real),
+    ]
+
+
+def kernel_bytes(n, prec_bytes):
+    """Algorithmic HBM bytes of each pass (sum over its launches)."""
+    out = {}
+    for pname, _, b in launch_model(n, prec_bytes):
+        out[pname] = out.get(pname, 0) + b
+    return out
+
+
+def launch_kernel_name(name_pattern, prec, schedule, pass_name):
+    """Concrete kernel name of a launch under a tile schedule."""
+    return name_pattern.format(t="float" if prec == "f32" else "double", v=schedule[PASS_INDEX[pass_name]])
 
 
 def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
@@ -332,7 +319,7 @@ def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
     ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    passes, nsolves = plan.profile_end()
+    passes, launches, nsolves = plan.profile_end()
     wall_ms = (t1 - t0) * 1e3 / steps
     ev_ms = ev0.elapsed_time(ev1) / steps
     out = {"phi": phi.double().cpu().numpy(), "E": E.double().cpu().numpy()}
@@ -340,8 +327,8 @@ def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
     plan.close()
     del rho, phi, E
     torch.cuda.empty_cache()
-    return {"wall_ms": wall_ms, "event_ms": ev_ms, "passes": passes, "nsolves": nsolves,
-            "out": out, "L": L, "schedule": list(schedule)}
+    return {"wall_ms": wall_ms, "event_ms": ev_ms, "passes": passes, "launches": launches,
+            "nsolves": nsolves, "out": out, "L": L, "schedule": list(schedule)}
 
 
 def run_batch(vgf, torch, workloads, steps, warmup, seed):
@@ -543,15 +530,28 @@ def main():
     kb64 = kernel_bytes(ch.n, 8)
     pm32 = pass_model_bytes(ch.n, 4)
     pm64 = pass_model_bytes(ch.n, 8)
-    # dominant kernel: the pass with the largest mean duration
-    dom = max(f32["passes"], key=lambda k: f32["passes"][k])
-    dom_ms = f32["passes"][dom]
-    achieved = kb32[dom] / (dom_ms * 1e-3) / 1e9
-    dom64 = max(f64["passes"], key=lambda k: f64["passes"][k])
-    ach64 = kb64[dom64] / (f64["passes"][dom64] * 1e-3) / 1e9
     traffic = load_traffic()
-    tr32 = traffic_of(traffic, dom, "f32", f32["schedule"])
-    tr64 = traffic_of(traffic, dom64, "f64", f64["schedule"])
+
+    def dominant(res, prec):
+        """The launch with the largest mean duration, its algorithmic bytes
+        and, when the committed counters describe these sources, its HBM
+        traffic per launch."""
+        model = launch_model(ch.n, 4 if prec == "f32" else 8)
+        if len(res["launches"]) != len(model):
+            raise SystemExit("unexpected launch sequence %s" % res["launches"])
+        k = max(range(len(model)), key=lambda i: res["launches"][i][1])
+        pname, pattern, nbytes = model[k]
+        assert res["launches"][k][0] == pname, (res["launches"], model)
+        ms = res["launches"][k][1]
+        name = launch_kernel_name(pattern, prec, res["schedule"], pname)
+        tr = None
+        if traffic is not None and name in traffic["kernels"]:
+            tr = traffic["kernels"][name]["traffic_bytes"]
+        return {"kernel": name, "pass": pname, "launch": k, "achieved": nbytes / (ms * 1e-3) / 1e9,
+                "mean_launch_ms": ms, "algorithmic_bytes_per_launch": nbytes, "traffic": tr}
+
+    d32 = dominant(f32, "f32")
+    d64 = dominant(f64, "f64")
 
     line = {
         "metric": METRIC,
@@ -573,14 +573,13 @@ def main():
         "fp64": {"value": 1e3 / f64["wall_ms"], "unit": "solves/s", "ms_per_step": f64["wall_ms"],
                  "dtype": "f64"},
         "schedule": {"f32": f32["schedule"], "f64": f64["schedule"]},
-        "roofline": {"bound": "hbm", "kernel": dom,
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": tr32,
+        "roofline": {"bound": "hbm", "kernel": d32["kernel"],
+                     "achieved": d32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": d32["achieved"] / HBM_PEAK_GBS, "traffic": d32["traffic"],
                      "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes_per_launch": kb32[dom], "mean_launch_ms": dom_ms,
-                     "fp64": {"kernel": dom64, "achieved": ach64, "mean_launch_ms": f64["passes"][dom64],
-                              "algorithmic_bytes_per_launch": kb64[dom64],
-                              "frac": ach64 / HBM_PEAK_GBS, "traffic": tr64}},
+                     "algorithmic_bytes_per_launch": d32["algorithmic_bytes_per_launch"],
+                     "mean_launch_ms": d32["mean_launch_ms"],
+                     "fp64": dict(d64, peak=HBM_PEAK_GBS, frac=d64["achieved"] / HBM_PEAK_GBS)},
         "pass_model": {"bytes_per_solve_f32": pm32, "bytes_per_solve_f64": pm64,
                        "frac_f32": pm32 / (f32["wall_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "frac_f64": pm64 / (f64["wall_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
@@ -588,6 +587,7 @@ def main():
                    "moved_bytes_per_solve_f32": sum(kb32.values()),
                    "moved_bytes_per_solve_f64": sum(kb64.values()),
                    "ms_f32": f32["passes"], "ms_f64": f64["passes"],
+                   "launches_ms_f32": f32["launches"], "launches_ms_f64": f64["launches"],
                    "gbs_f32": {k: kb32[k] / (f32["passes"][k] * 1e-3) / 1e9 for k in kb32},
                    "gbs_f64": {k: kb64[k] / (f64["passes"][k] * 1e-3) / 1e9 for k in kb64}},
         "accuracy": {"f32_vs_f64_gpu": {"phi": rel_l2(f32["out"]["phi"], f64["out"]["phi"]),

@@ -270,19 +270,22 @@ vgf_status vgf_plan_get_kernel(vgf_plan plan, double* host_out);
  * Synchronous. */
 vgf_status vgf_plan_get_spectrum(vgf_plan plan, double* host_out);
 
-/* Per-pass timing (tracing support for benchmarks and profiling).
- * vgf_plan_profile_begin creates max_solves * 6 HIP events (host call, not
- * stream-ordered); each following vgf_solve on this plan, up to max_solves,
- * records one event before its first pass and one after each pass, on the
- * solve's own stream. vgf_plan_profile_end waits for the recorded events,
- * writes the mean duration in milliseconds of each pass to pass_ms (3D: r2c,
- * c2c forward, fused axis-0, c2c inverse, c2r; 2D: r2c, fused axis-0, c2r),
- * the number of passes to *npasses and the number of timed solves to
- * *nsolves, destroys the events and stops recording. pass_ms must hold 8
- * doubles. begin while already recording returns INVALID_ARG; end without
+/* Per-launch timing (tracing support for benchmarks and profiling).
+ * vgf_plan_profile_begin creates max_solves * (VGF_MAX_LAUNCHES + 1) HIP
+ * events (host call, not stream-ordered); each following vgf_solve on this
+ * plan, up to max_solves, records one event before its first launch and one
+ * after each launch, on the solve's own stream. vgf_plan_profile_end waits
+ * for the recorded events and writes, for each launch k of a solve, the mean
+ * duration in milliseconds to launch_ms[k] and its pass (VGF_PASS_*) to
+ * launch_pass[k]; the number of launches per solve to *nlaunch and the
+ * number of timed solves to *nsolves; then destroys the events and stops
+ * recording. Both arrays must hold VGF_MAX_LAUNCHES entries (unused ones are
+ * 0 and -1). begin while already recording returns INVALID_ARG; end without
  * begin returns INVALID_ARG. */
+enum { VGF_MAX_LAUNCHES = 16 };
 vgf_status vgf_plan_profile_begin(vgf_plan plan, int max_solves);
-vgf_status vgf_plan_profile_end(vgf_plan plan, double* pass_ms, int* npasses, int* nsolves);
+vgf_status vgf_plan_profile_end(vgf_plan plan, double* launch_ms, int* launch_pass, int* nlaunch,
+                                int* nsolves);
 
 /* The last HIP error code recorded by a call on this plan (hipSuccess if
  * none). */

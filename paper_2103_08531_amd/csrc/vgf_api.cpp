@@ -68,8 +68,9 @@ struct vgf_plan_s {
 
   // per-pass timing (vgf_plan_profile_begin / _end)
   bool profiling = false;
-  int prof_cap = 0, prof_used = 0, prof_npass = 0;
+  int prof_cap = 0, prof_used = 0, prof_nlaunch = 0;
   std::vector<hipEvent_t> prof_events;  // prof_cap x kMaxMarks
+  std::vector<int> prof_tags;           // pass of each launch, prof_cap x kMaxMarks
 };
 
 namespace {
@@ -286,30 +287,43 @@ vgf_status hip_status(vgf_plan p, hipError_t e) {
   return VGF_ERR_HIP;
 }
 
-constexpr int kMaxMarks = 6;
+constexpr int kMaxLaunches = 16;           // per solve, as reported by profiling
+constexpr int kMaxMarks = kMaxLaunches + 1;  // an event at the start and after every launch
 constexpr int vgf_tile_variants() { return vgf::kTileVariantsHost; }
 
-// Records the pass boundaries of one solve: into the plan's profiling
-// events when the plan is profiling, or into caller-given events (tuning).
+// Records an event at the start of a solve and after each of its launches,
+// tagged with the launch's pass: into the plan's profiling slots when the
+// plan is profiling, or into caller-given arrays (tuning).
 struct Marks {
   vgf_plan p;
   hipStream_t s;
   hipEvent_t* ev = nullptr;
+  int* tags = nullptr;
   bool own = false;  // plan profiling slot
   int n = 0;
-  Marks(vgf_plan p_, hipStream_t s_, bool on, hipEvent_t* given) : p(p_), s(s_) {
+  Marks(vgf_plan p_, hipStream_t s_, bool on, hipEvent_t* given, int* given_tags) : p(p_), s(s_) {
     if (given) {
       ev = given;
+      tags = given_tags;
     } else if (on && p->profiling && p->prof_used < p->prof_cap) {
-      ev = &p->prof_events[(size_t)p->prof_used++ * kMaxMarks];
+      ev = &p->prof_events[(size_t)p->prof_used * kMaxMarks];
+      tags = &p->prof_tags[(size_t)p->prof_used * kMaxMarks];
+      ++p->prof_used;
       own = true;
     }
+    if (ev) {
+      (void)hipEventRecord(ev[0], s);
+      n = 1;
+    }
   }
-  void mark() {
-    if (ev && n < kMaxMarks) (void)hipEventRecord(ev[n++], s);
+  void mark(int pass) {
+    if (ev && n < kMaxMarks) {
+      tags[n - 1] = pass;
+      (void)hipEventRecord(ev[n++], s);
+    }
   }
   ~Marks() {
-    if (own) p->prof_npass = n - 1;
+    if (own) p->prof_nlaunch = n - 1;
   }
 };
 
@@ -406,6 +420,14 @@ template <typename T> vgf::Deriv<T> deriv2(vgf_plan p, int axis, int code0, int 
     if (e_ != hipSuccess) return hip_status(p, e_);    \
   } while (0)
 
+// a launch of pass `pass` inside a solve: run, check, mark its end
+#define VGF_LAUNCH(pass, expr)                         \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_status(p, e_);    \
+    mk.mark(pass);                                     \
+  } while (0)
+
 // The arrays of the entries (right-hand sides of one plan) that one launch
 // of each pass covers. One entry: direct pointers and the plan workspace.
 // Several: device tables of per-entry base pointers (rho, phi, E) and
@@ -456,7 +478,7 @@ vgf::GradSpec<T> grad_spec(vgf_plan p) {
 // spectrum; every field is then inverted on its own.
 template <typename T>
 vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks, const int* sched,
-                              hipEvent_t* mark_events) {
+                              hipEvent_t* mark_events, int* mark_tags) {
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -471,27 +493,23 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
     for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
   T* outs[4];
   for (int f = 0; f < g.nf; ++f) outs[f] = g.fields[f] == 0 ? en.phi : en.E + (g.fields[f] - 1) * vol;
-  Marks mk(p, s, marks, mark_events);
-  mk.mark();
+  Marks mk(p, s, marks, mark_events, mark_tags);
   const int64_t lpe = d == 3 ? N0 * N1 : N0;
   vgf::R2CArgs<T> ra{{en.rho, nullptr}, b.x1, lpe, Hs, deriv1<T>(p, d - 1, 0)};
   ra.lpe = lpe;
-  VGF_RUN(vgf::launch_r2c<T>((int)p->P[d - 1], ra, tw(d - 1), s));
-  mk.mark();
+  VGF_LAUNCH(kPassR2C, vgf::launch_r2c<T>((int)p->P[d - 1], ra, tw(d - 1), s));
   const cplx<T>* fused_in = b.x1;
   if (d == 3) {
     const int64_t P1 = p->P[1];
     const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
-    mk.mark();
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
     fused_in = b.x2;
     g.out_fs = N0 * P1 * Hs;
   } else {
     g.out_fs = N0 * Hs;
   }
-  VGF_RUN(vgf::launch_fused_grad<T>((int)p->P[0], false, fused_in, b.y, g, grad_spec<T>(p), tw(0), s));
-  mk.mark();
+  VGF_LAUNCH(kPassFused, vgf::launch_fused_grad<T>((int)p->P[0], false, fused_in, b.y, g, grad_spec<T>(p), tw(0), s));
   const cplx<T>* lastin = b.y;
   int64_t last_fs = g.out_fs;
   if (d == 3) {
@@ -499,18 +517,16 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
     const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     for (int f = 0; f < g.nf; ++f) {
       vgf::C2CInvArgs<T> ia{b.y + f * g.out_fs, {b.z + f * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
     }
-    mk.mark();
     lastin = b.z;
     last_fs = zfs;
   }
   for (int f = 0; f < g.nf; ++f) {
     vgf::C2RArgs<T> ca{lastin + f * last_fs, {outs[f], nullptr}, lpe, Hs, deriv1<T>(p, d - 1, 0)};
     ca.lpe = lpe;
-    VGF_RUN(vgf::launch_c2r<T>((int)p->P[d - 1], ca, tw(d - 1), s));
+    VGF_LAUNCH(kPassC2R, vgf::launch_c2r<T>((int)p->P[d - 1], ca, tw(d - 1), s));
   }
-  mk.mark();
   return VGF_OK;
 }
 
@@ -535,7 +551,7 @@ void c2r_s_out(vgf::C2RSArgs<T>& ca, int o, const Entries<T>& en, int field, int
 // Each pass again applies the derivative of its own axis.
 template <typename T>
 vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks, const int* sched,
-                           hipEvent_t* mark_events) {
+                           hipEvent_t* mark_events, int* mark_tags) {
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H0 = N0 + 1, NL = p->n[d - 1];
   const int64_t vol = prod(p->n, d);
@@ -544,8 +560,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   Bufs<T> b{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2), (cplx<T>*)(base + p->off_y),
             (cplx<T>*)(base + p->off_z)};
   auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
-  Marks mk(p, s, marks, mark_events);
-  mk.mark();
+  Marks mk(p, s, marks, mark_events, mark_tags);
   vgf::R2CSArgs<T> ra{};
   if (en.rho_tab) ra.in_tab[0] = en.rho_tab;
   else ra.in[0] = en.rho;
@@ -554,8 +569,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   ra.ncols = vol / N0;
   ra.nentry = en.count;
   ra.d = deriv1<T>(p, 0, 0);
-  VGF_RUN(vgf::launch_r2c_s<T>((int)p->P[0], sched[kPassR2C], ra, tw(0), s));
-  mk.mark();
+  VGF_LAUNCH(kPassR2C, vgf::launch_r2c_s<T>((int)p->P[0], sched[kPassR2C], ra, tw(0), s));
   const cplx<T>* fin = b.x1;
   vgf::FusedCGeom<T> g{};
   g.dim = d;
@@ -574,12 +588,10 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     fg.nentry = en.count;
     fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
-    mk.mark();
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
     fin = b.x2;
   }
-  VGF_RUN(vgf::launch_fused_c<T>((int)p->P[d - 1], false, fin, b.y, g, (const T*)p->spec, tw(d - 1), s));
-  mk.mark();
+  VGF_LAUNCH(kPassFused, vgf::launch_fused_c<T>((int)p->P[d - 1], false, fin, b.y, g, (const T*)p->spec, tw(d - 1), s));
   // axis-0 inputs: phi's spectrum, and the spectra of E_1 (3D) and E_last
   const cplx<T>* zphi = b.y;
   const cplx<T>* zf[2] = {nullptr, nullptr};  // E_1, E_2 (3D) or E_1 (2D)
@@ -590,12 +602,11 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
     vgf::C2CInvArgs<T> ia{b.y, {b.z, b.z + zfs}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
     if (want_E) {
       vgf::C2CInvArgs<T> ia2{b.y + g.fs, {b.z + 2 * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia2, tw(1), s));
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia2, tw(1), s));
     }
-    mk.mark();
     zphi = b.z;
     zf[0] = b.z + zfs;
     zf[1] = b.z + 2 * zfs;
@@ -615,22 +626,21 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     if (f1 != -2) c2r_s_out(ca, 1, en, f1, vol);
     return vgf::launch_c2r_s<T>((int)p->P[0], sched[kPassC2R], ca, tw(0), s);
   };
-  if (want_phi && want_E) VGF_RUN(c2r(zphi, -1, 0, 0, -1));
-  else if (want_phi) VGF_RUN(c2r(zphi, -1, 0, -2, 0));
-  else VGF_RUN(c2r(zphi, 0, -1, -2, 0));
+  if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(zphi, -1, 0, 0, -1));
+  else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(zphi, -1, 0, -2, 0));
+  else VGF_LAUNCH(kPassC2R, c2r(zphi, 0, -1, -2, 0));
   if (want_E) {
-    VGF_RUN(c2r(zf[0], 1, 0, -2, 0));
-    if (d == 3) VGF_RUN(c2r(zf[1], 2, 0, -2, 0));
+    VGF_LAUNCH(kPassC2R, c2r(zf[0], 1, 0, -2, 0));
+    if (d == 3) VGF_LAUNCH(kPassC2R, c2r(zf[1], 2, 0, -2, 0));
   }
-  mk.mark();
   return VGF_OK;
 }
 
 template <typename T>
 vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks,
-                         const int* sched, hipEvent_t* mark_events = nullptr) {
-  if (p->gradk) return enqueue_solve_grad<T>(p, en, s, marks, sched, mark_events);
-  if (p->contig) return enqueue_solve_c<T>(p, en, s, marks, sched, mark_events);
+                         const int* sched, hipEvent_t* mark_events = nullptr, int* mark_tags = nullptr) {
+  if (p->gradk) return enqueue_solve_grad<T>(p, en, s, marks, sched, mark_events, mark_tags);
+  if (p->contig) return enqueue_solve_c<T>(p, en, s, marks, sched, mark_events, mark_tags);
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H = p->H, Hs = p->Hs;
   const int64_t vol = prod(p->n, d);
@@ -646,8 +656,7 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
   if (want_E) g.fields[g.nf++] = 1;
   g.nentry = en.count;
   g.in_es = g.out_es = en.es;
-  Marks mk(p, s, marks, mark_events);
-  mk.mark();
+  Marks mk(p, s, marks, mark_events, mark_tags);
   const int64_t lpe = d == 3 ? N0 * N1 : N0;  // contiguous lines per entry
   vgf::R2CArgs<T> ra{};
   ra.nlines = lpe * en.count;
@@ -675,16 +684,13 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     const int64_t P1 = p->P[1];
     const int64_t yfs = N0 * P1 * Hs, zfs = N0 * N1 * Hs;
     g.out_fs = yfs;
-    VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
-    mk.mark();
+    VGF_LAUNCH(kPassR2C, vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
     vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     fg.nentry = en.count;
     fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
-    mk.mark();
-    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x2, b.y, g, spec, tw(0), s));
-    mk.mark();
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    VGF_LAUNCH(kPassFused, vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x2, b.y, g, spec, tw(0), s));
     // Yp -> Zp (phi, and E_2 later) and Z1 = -i k_1 Zp; Y0 -> Z0
     vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     ig.nentry = en.count;
@@ -693,32 +699,27 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     cplx<T>* z1 = b.z + zfs;
     cplx<T>* z0 = b.z + 2 * zfs;
     vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
     if (want_E) {
       vgf::C2CInvArgs<T> ia0{b.y + yfs, {z0, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia0, tw(1), s));
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia0, tw(1), s));
     }
-    mk.mark();
-    if (want_phi && want_E) VGF_RUN(c2r(zp, -1, 0, 2, -1));
-    else if (want_phi) VGF_RUN(c2r(zp, -1, 0, -2, 0));
-    else VGF_RUN(c2r(zp, 2, -1, -2, 0));
+    if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(zp, -1, 0, 2, -1));
+    else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(zp, -1, 0, -2, 0));
+    else VGF_LAUNCH(kPassC2R, c2r(zp, 2, -1, -2, 0));
     if (want_E) {
-      VGF_RUN(c2r(z1, 1, 0, -2, 0));
-      VGF_RUN(c2r(z0, 0, 0, -2, 0));
+      VGF_LAUNCH(kPassC2R, c2r(z1, 1, 0, -2, 0));
+      VGF_LAUNCH(kPassC2R, c2r(z0, 0, 0, -2, 0));
     }
-    mk.mark();
   } else {
     const int64_t yfs = N0 * Hs;
     g.out_fs = yfs;
-    VGF_RUN(vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
-    mk.mark();
-    VGF_RUN(vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x1, b.y, g, spec, tw(0), s));
-    mk.mark();
-    if (want_phi && want_E) VGF_RUN(c2r(b.y, -1, 0, 1, -1));
-    else if (want_phi) VGF_RUN(c2r(b.y, -1, 0, -2, 0));
-    else VGF_RUN(c2r(b.y, 1, -1, -2, 0));
-    if (want_E) VGF_RUN(c2r(b.y + yfs, 0, 0, -2, 0));
-    mk.mark();
+    VGF_LAUNCH(kPassR2C, vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
+    VGF_LAUNCH(kPassFused, vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x1, b.y, g, spec, tw(0), s));
+    if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(b.y, -1, 0, 1, -1));
+    else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(b.y, -1, 0, -2, 0));
+    else VGF_LAUNCH(kPassC2R, c2r(b.y, 1, -1, -2, 0));
+    if (want_E) VGF_LAUNCH(kPassC2R, c2r(b.y + yfs, 0, 0, -2, 0));
   }
   return VGF_OK;
 }
@@ -763,12 +764,10 @@ template <class Run>
 vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best, hipError_t* herr) {
   const int dim = p->dim;
   constexpr int NV = vgf_tile_variants();
-  const int nint = dim == 3 ? 5 : 3;
-  static const int pass3[5] = {kPassR2C, kPassC2CF, kPassFused, kPassC2CI, kPassC2R};
-  static const int pass2[3] = {kPassR2C, kPassFused, kPassC2R};
-  const int* pass_of = dim == 3 ? pass3 : pass2;
-  // events [rep][variant][mark]
+  // events and launch tags [rep][variant][mark]
   std::vector<hipEvent_t> ev((size_t)reps * NV * kMaxMarks, nullptr);
+  std::vector<int> tags((size_t)reps * NV * kMaxMarks, -1);
+  std::vector<int> nmark((size_t)reps * NV, 0);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
   int sched[NV][kPasses];
@@ -778,9 +777,12 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
   // warm-up of every variant, then the variants interleaved rep by rep so
   // that clock ramps and cache state bias none of them
   for (int w = 0; w < 2 && st == VGF_OK && e == hipSuccess; ++w)
-    for (int v = 0; v < NV && st == VGF_OK; ++v) st = run(sched[v], nullptr);
+    for (int v = 0; v < NV && st == VGF_OK; ++v) st = run(sched[v], nullptr, nullptr);
   for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
-    for (int v = 0; v < NV && st == VGF_OK; ++v) st = run(sched[v], &ev[((size_t)r * NV + v) * kMaxMarks]);
+    for (int v = 0; v < NV && st == VGF_OK; ++v) {
+      const size_t o = ((size_t)r * NV + v) * kMaxMarks;
+      st = run(sched[v], &ev[o], &tags[o]);
+    }
   // fastest repetition of each pass under each variant
   double t[NV][kPasses];
   for (int v = 0; v < NV; ++v)
@@ -788,12 +790,14 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
   if (st == VGF_OK && e == hipSuccess) e = hipStreamSynchronize(s);
   for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
     for (int v = 0; v < NV && e == hipSuccess; ++v) {
-      hipEvent_t* m = &ev[((size_t)r * NV + v) * kMaxMarks];
-      for (int i = 0; i < nint && e == hipSuccess; ++i) {
+      const size_t o = ((size_t)r * NV + v) * kMaxMarks;
+      double pass_ms[kPasses] = {};
+      for (int i = 0; i + 1 < kMaxMarks && tags[o + i] >= 0 && e == hipSuccess; ++i) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, m[i], m[i + 1]);
-        t[v][pass_of[i]] = std::min(t[v][pass_of[i]], (double)ms);
+        e = hipEventElapsedTime(&ms, ev[o + i], ev[o + i + 1]);
+        pass_ms[tags[o + i]] += ms;
       }
+      for (int k = 0; k < kPasses; ++k) t[v][k] = std::min(t[v][k], pass_ms[k]);
     }
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
@@ -1308,7 +1312,7 @@ vgf_status vgf_plan_autotune(vgf_plan p, const void* rho, void* phi, void* E, in
     if (!phi) phi = (char*)p->ws + p->off_phi;
     E = nullptr;
   }
-  auto run = [&](const int* sched, hipEvent_t* ev) -> vgf_status {
+  auto run = [&](const int* sched, hipEvent_t* ev, int* tg) -> vgf_status {
     if (p->prec == VGF_F32) {
       Entries<float> en;
       en.ws = (char*)p->ws;
@@ -1317,7 +1321,7 @@ vgf_status vgf_plan_autotune(vgf_plan p, const void* rho, void* phi, void* E, in
       en.E = (float*)E;
       en.want_phi = phi != nullptr;
       en.want_E = E != nullptr;
-      return enqueue_solve<float>(p, en, stream, false, sched, ev);
+      return enqueue_solve<float>(p, en, stream, false, sched, ev, tg);
     }
     Entries<double> en;
     en.ws = (char*)p->ws;
@@ -1326,7 +1330,7 @@ vgf_status vgf_plan_autotune(vgf_plan p, const void* rho, void* phi, void* E, in
     en.E = (double*)E;
     en.want_phi = phi != nullptr;
     en.want_E = E != nullptr;
-    return enqueue_solve<double>(p, en, stream, false, sched, ev);
+    return enqueue_solve<double>(p, en, stream, false, sched, ev, tg);
   };
   hipError_t herr = hipSuccess;
   st = tune_cached(p, phi != nullptr, E != nullptr, 1, reps, stream, run, p->schedule, &herr);
@@ -1395,6 +1399,7 @@ vgf_status vgf_plan_get_gradient_spectrum(vgf_plan p, int axis, double* host_out
 vgf_status vgf_plan_profile_begin(vgf_plan p, int max_solves) {
   if (!p || max_solves <= 0 || p->profiling) return VGF_ERR_INVALID_ARG;
   p->prof_events.assign((size_t)max_solves * kMaxMarks, nullptr);
+  p->prof_tags.assign((size_t)max_solves * kMaxMarks, -1);
   for (size_t i = 0; i < p->prof_events.size(); ++i) {
     hipError_t e = hipEventCreate(&p->prof_events[i]);
     if (e != hipSuccess) {
@@ -1405,31 +1410,38 @@ vgf_status vgf_plan_profile_begin(vgf_plan p, int max_solves) {
   }
   p->prof_cap = max_solves;
   p->prof_used = 0;
-  p->prof_npass = 0;
+  p->prof_nlaunch = 0;
   p->profiling = true;
   return VGF_OK;
 }
 
-vgf_status vgf_plan_profile_end(vgf_plan p, double* pass_ms, int* npasses, int* nsolves) {
-  if (!p || !pass_ms || !npasses || !nsolves || !p->profiling) return VGF_ERR_INVALID_ARG;
+vgf_status vgf_plan_profile_end(vgf_plan p, double* launch_ms, int* launch_pass, int* nlaunch, int* nsolves) {
+  if (!p || !launch_ms || !launch_pass || !nlaunch || !nsolves || !p->profiling) return VGF_ERR_INVALID_ARG;
   hipError_t err = hipSuccess;
-  const int np = p->prof_npass;
-  for (int k = 0; k < 8; ++k) pass_ms[k] = 0.0;
+  const int nl = p->prof_nlaunch;
+  for (int k = 0; k < kMaxLaunches; ++k) {
+    launch_ms[k] = 0.0;
+    launch_pass[k] = -1;
+  }
   for (int sIdx = 0; sIdx < p->prof_used && err == hipSuccess; ++sIdx) {
     hipEvent_t* ev = &p->prof_events[(size_t)sIdx * kMaxMarks];
-    err = hipEventSynchronize(ev[np]);
-    for (int k = 0; k < np && err == hipSuccess; ++k) {
+    err = hipEventSynchronize(ev[nl]);
+    for (int k = 0; k < nl && err == hipSuccess; ++k) {
       float ms = 0.f;
       err = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      pass_ms[k] += ms;
+      launch_ms[k] += ms;
     }
   }
   if (err == hipSuccess && p->prof_used > 0)
-    for (int k = 0; k < np; ++k) pass_ms[k] /= p->prof_used;
-  *npasses = np;
+    for (int k = 0; k < nl; ++k) {
+      launch_ms[k] /= p->prof_used;
+      launch_pass[k] = p->prof_tags[k];
+    }
+  *nlaunch = nl;
   *nsolves = p->prof_used;
   for (hipEvent_t ev : p->prof_events) (void)hipEventDestroy(ev);
   p->prof_events.clear();
+  p->prof_tags.clear();
   p->profiling = false;
   p->prof_cap = p->prof_used = 0;
   return hip_status(p, err);
@@ -1508,7 +1520,7 @@ void batch_release(vgf_batch b) {
 // the passes of one group, all entries per launch
 template <typename T>
 vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool want_E, hipStream_t s,
-                               const int* sched = nullptr, hipEvent_t* marks = nullptr) {
+                               const int* sched = nullptr, hipEvent_t* marks = nullptr, int* tags = nullptr) {
   const vgf_plan p = g.plan;
   const int c = (int)g.idx.size();
   Entries<T> en;
@@ -1520,7 +1532,7 @@ vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool 
   en.E_tab = want_E ? (T* const*)(g.tab + 2 * c) : nullptr;
   en.want_phi = want_phi;
   en.want_E = want_E;
-  return enqueue_solve<T>(p, en, s, false, sched ? sched : g.schedule, marks);
+  return enqueue_solve<T>(p, en, s, false, sched ? sched : g.schedule, marks, tags);
 }
 
 vgf_status batch_enqueue_groups(vgf_batch b, bool want_phi, bool want_E, bool branches, hipStream_t s) {
@@ -1691,9 +1703,10 @@ vgf_status vgf_batch_autotune(vgf_batch b, const void* const* rho, void* const* 
   const bool want_phi = phi != nullptr, want_E = E != nullptr;
   for (auto& g : b->groups) {
     const int count = (int)g.idx.size();
-    auto run = [&](const int* sched, hipEvent_t* ev) -> vgf_status {
-      vgf_status r = g.plan->prec == VGF_F32 ? batch_group_enqueue<float>(g, want_phi, want_E, stream, sched, ev)
-                                             : batch_group_enqueue<double>(g, want_phi, want_E, stream, sched, ev);
+    auto run = [&](const int* sched, hipEvent_t* ev, int* tg) -> vgf_status {
+      vgf_status r = g.plan->prec == VGF_F32
+                         ? batch_group_enqueue<float>(g, want_phi, want_E, stream, sched, ev, tg)
+                         : batch_group_enqueue<double>(g, want_phi, want_E, stream, sched, ev, tg);
       if (r == VGF_ERR_HIP) b->last_err = g.plan->last_err;
       return r;
     };

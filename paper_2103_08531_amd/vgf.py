@@ -32,6 +32,8 @@ EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batch
 BATCH_GRAPH = 1
 PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused", "c2c_inv", "c2r"],
               2: ["r2c", "fused", "c2r"]}
+PASS_IDS = ["r2c", "c2c_fwd", "fused", "c2c_inv", "c2r"]  # VGF_PASS_* order
+MAX_LAUNCHES = 16
 
 
 class VGFError(RuntimeError):
@@ -76,7 +78,8 @@ def lib():
         L.vgf_plan_profile_begin.restype = C.c_int
         L.vgf_plan_profile_begin.argtypes = [vp, C.c_int]
         L.vgf_plan_profile_end.restype = C.c_int
-        L.vgf_plan_profile_end.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.vgf_plan_profile_end.argtypes = [vp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                           C.POINTER(C.c_int)]
         L.vgf_status_string.restype = C.c_char_p
         L.vgf_status_string.argtypes = [C.c_int]
         L.vgf_batch_create.restype = C.c_int
@@ -293,13 +296,18 @@ class Plan:
         _check(lib().vgf_plan_profile_begin(self.handle, int(max_solves)), "vgf_plan_profile_begin")
 
     def profile_end(self):
-        """{pass name: mean ms} over the solves recorded since profile_begin, and their count."""
-        ms = (C.c_double * 8)()
-        npass, nsol = C.c_int(), C.c_int()
-        _check(lib().vgf_plan_profile_end(self.handle, ms, C.byref(npass), C.byref(nsol)),
+        """({pass name: mean ms}, [(pass name, mean ms) per launch], solves recorded)
+        over the solves recorded since profile_begin."""
+        ms = (C.c_double * MAX_LAUNCHES)()
+        tags = (C.c_int * MAX_LAUNCHES)()
+        nl, nsol = C.c_int(), C.c_int()
+        _check(lib().vgf_plan_profile_end(self.handle, ms, tags, C.byref(nl), C.byref(nsol)),
                "vgf_plan_profile_end")
-        names = PASS_NAMES[self.dim]
-        return {names[k]: ms[k] for k in range(min(npass.value, len(names)))}, nsol.value
+        launches = [(PASS_IDS[tags[k]], ms[k]) for k in range(nl.value)]
+        passes = {}
+        for name, t in launches:
+            passes[name] = passes.get(name, 0.0) + t
+        return passes, launches, nsol.value
 
     def close(self):
         if self._h is not None:

@@ -301,3 +301,34 @@ def test_largest_grid_512(precision):
     say("  512^3 %s vs analytic: phi %.3e E %.3e" % (precision, ep, eE))
     bound = 1e-12 if precision == "f64" else 1e-5
     assert ep <= bound and eE <= bound
+
+
+LAYOUT_CASES = [((16, 24, 32), "vgf"), ((24, 12, 48), "he"), ((64, 48), "vgf"), ((96, 64), "he_cellavg")]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("n,method", LAYOUT_CASES)
+def test_axis0_layout_matches_oracle(n, method, precision):
+    """The axis-0 layout (multiply inside the strided axis-0 pass), solve and
+    adjoint, against the oracle, next to the default layout."""
+    h = tuple((2.0 + 0.1 * a) / (x - 1) for a, x in enumerate(n))
+    torch, vgf = need_gpu()
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    rho = rounded_input(W.random_field(61, n), precision)
+    g_phi = rounded_input(W.random_field(62, n), precision)
+    g_E = rounded_input(W.random_field(63, (len(n),) + n), precision)
+    res = {}
+    for layout in ("axis0", "contiguous"):
+        plan = vgf.Plan(n, h, method=method, precision=precision, layout=layout)
+        w = oracle_kernel(method, n, h, plan.L)
+        phi_g, E_g = gpu_solve(plan, rho)
+        phi_o, E_o = orc.solve_fft2n(n, h, w, rho)
+        check_fields(phi_g, E_g, phi_o, E_o, tol, "%s %s %s %s" % (layout, n, method, precision))
+        gp = torch.from_numpy(g_phi).to("cuda", plan.dtype)
+        ge = torch.from_numpy(g_E).to("cuda", plan.dtype)
+        g_rho = plan.adjoint(gp, ge).double().cpu().numpy()
+        ref = orc.adjoint_fft2n(n, h, w, g_phi, g_E)
+        assert rel_l2(g_rho, ref) <= tol, (layout, rel_l2(g_rho, ref))
+        res[layout] = phi_g
+        plan.close()
+    assert rel_l2(res["axis0"], res["contiguous"]) <= 2 * tol
