@@ -77,6 +77,13 @@ template <int SIGN> constexpr int ns_at(int P, int s) {
   for (int i = 0; i < s; ++i) ns *= radix_at<SIGN>(P, i);
   return ns;
 }
+// forward and inverse run the same radix sequence (one twiddle table serves
+// both directions)
+template <int P> constexpr bool radix_palindrome() {
+  for (int s = 0; s < n_stages(P); ++s)
+    if (fwd_radix(P, s) != fwd_radix(P, n_stages(P) - 1 - s)) return false;
+  return true;
+}
 
 // ---------------------------------------------------------------------------
 // R-point DFTs in registers, y_k = sum_j x_j exp(S 2 pi i jk / R)
@@ -95,13 +102,28 @@ template <int S, typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, 
   a3 = c_sub(t1, t3);
 }
 
-template <int S, typename C> __device__ __forceinline__ void dft8_impl(C* v) {
+// dft4 with a2 = a3 = 0 (the zero half of a padded input; adding a zero
+// explicitly would not be folded away, since x + 0 is not x for x = -0)
+template <int S, typename C> __device__ __forceinline__ void dft4_half(C& a0, C& a1, C& a2, C& a3) {
+  const C b0 = a0, b1 = a1, t3 = c_muli<S>(a1);
+  a0 = c_add(b0, b1);
+  a2 = c_sub(b0, b1);
+  a1 = c_add(b0, t3);
+  a3 = c_sub(b0, t3);
+}
+
+template <int S, bool HALF, typename C> __device__ __forceinline__ void dft8_impl(C* v) {
   using T = decltype(v[0].x);
   // even / odd 4-point DFTs
   C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
   C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-  dft4<S>(e0, e1, e2, e3);
-  dft4<S>(o0, o1, o2, o3);
+  if constexpr (HALF) {
+    dft4_half<S>(e0, e1, e2, e3);
+    dft4_half<S>(o0, o1, o2, o3);
+  } else {
+    dft4<S>(e0, e1, e2, e3);
+    dft4<S>(o0, o1, o2, o3);
+  }
   // twiddles w8^k, w8 = exp(S 2 pi i / 8)
   const T c = K<T>::r12;
   C t1, t2, t3;
@@ -135,18 +157,23 @@ template <int S, typename C> __device__ __forceinline__ void dft3_impl(C* v) {
   v[2] = c_sub(m, u);
 }
 
+// run: full R-point DFT; run_half: the same with inputs R/2 .. R-1 zero
+// (never read)
 template <int R, int S, typename C> struct Dft;
 template <int S, typename C> struct Dft<2, S, C> {
   __device__ __forceinline__ static void run(C* v) { C a = v[0], b = v[1]; v[0] = c_add(a, b); v[1] = c_sub(a, b); }
+  __device__ __forceinline__ static void run_half(C* v) { v[1] = v[0]; }
 };
 template <int S, typename C> struct Dft<3, S, C> {
   __device__ __forceinline__ static void run(C* v) { dft3_impl<S>(v); }
 };
 template <int S, typename C> struct Dft<4, S, C> {
   __device__ __forceinline__ static void run(C* v) { dft4<S>(v[0], v[1], v[2], v[3]); }
+  __device__ __forceinline__ static void run_half(C* v) { dft4_half<S>(v[0], v[1], v[2], v[3]); }
 };
 template <int S, typename C> struct Dft<8, S, C> {
-  __device__ __forceinline__ static void run(C* v) { dft8_impl<S>(v); }
+  __device__ __forceinline__ static void run(C* v) { dft8_impl<S, false>(v); }
+  __device__ __forceinline__ static void run_half(C* v) { dft8_impl<S, true>(v); }
 };
 
 // ---------------------------------------------------------------------------
@@ -207,10 +234,30 @@ struct Stage {
     }
   }
 
-  __device__ __forceinline__ static void butterflies(Regs& g, int q) {
+  // HALF: the first stage of a pruned load (inputs r >= R/2 are zero)
+  template <bool HALF = false> __device__ __forceinline__ static void butterflies(Regs& g, int q) {
 #pragma unroll
-    for (int t = 0; t < NTASK; ++t)
-      if (active(t, q)) Dft<R, SIGN, C>::run(g.v[t]);
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      if constexpr (HALF) Dft<R, SIGN, C>::run_half(g.v[t]);
+      else Dft<R, SIGN, C>::run(g.v[t]);
+    }
+  }
+
+  // LDS index of in_pos(j, r) / out_pos(j, r) of line l, written as a
+  // per-(j, l) base plus r times a compile-time step wherever the layout
+  // allows it, so one address serves all R accesses (immediate offsets).
+  __device__ __forceinline__ static int in_index(int j, int r, int l) {
+    if constexpr (LAYOUT == 1 && NB % 8 == 0) return l * LP + j + (j >> 3) + r * (NB + NB / 8);
+    else return lds_index<LAYOUT, LP>(in_pos(j, r), l);
+  }
+  __device__ __forceinline__ static int out_index(int j, int r, int l) {
+    if constexpr (LAYOUT == 1 && (NS % 8 == 0 || (NS == 1 && 8 % R == 0))) {
+      const int u = (j / NS) * NS * R + (j % NS);
+      return l * LP + u + (u >> 3) + r * (NS == 1 ? 1 : NS + NS / 8);
+    } else {
+      return lds_index<LAYOUT, LP>(out_pos(j, r), l);
+    }
   }
 
   // read this stage's inputs from the LDS tile and apply the twiddles
@@ -220,11 +267,12 @@ struct Stage {
       if (!active(t, q)) continue;
       const int j = q + t * NQ;
 #pragma unroll
-      for (int r = 0; r < R; ++r) g.v[t][r] = lds[lds_index<LAYOUT, LP>(in_pos(j, r), l)];
+      for (int r = 0; r < R; ++r) g.v[t][r] = lds[in_index(j, r, l)];
       if constexpr (NS > 1) {
-        const int base = (j % NS) * (P / (NS * R));
+        // stage-major table: the R-1 twiddles of butterfly j are NS apart
+        const C* tb = tw + (NS - radix_at<SIGN>(P, 0)) + (j % NS);
 #pragma unroll
-        for (int r = 1; r < R; ++r) g.v[t][r] = c_mul(g.v[t][r], twiddle(tw, r * base));
+        for (int r = 1; r < R; ++r) g.v[t][r] = c_mul(g.v[t][r], twiddle(tb, (r - 1) * NS));
       }
     }
   }
@@ -235,7 +283,7 @@ struct Stage {
       if (!active(t, q)) continue;
       const int j = q + t * NQ;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_index<LAYOUT, LP>(out_pos(j, r), l)] = g.v[t][r];
+      for (int r = 0; r < R; ++r) lds[out_index(j, r, l)] = g.v[t][r];
     }
   }
 

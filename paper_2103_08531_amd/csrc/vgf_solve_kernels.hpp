@@ -83,9 +83,34 @@ __device__ __forceinline__ C deriv(C x, int code, T k) {
   return C{-k * x.y, k * x.x};
 }
 
-template <typename C, int P, int NT>
+// Twiddles of the stages of one direction in LDS, stage-major: stage s
+// (Ns > 1, radix R) keeps w^(r*m*P/(Ns*R)) for r = 1..R-1, m = 0..Ns-1 at
+// (Ns - R_0) + (r-1)*Ns + m, so the R-1 twiddles of one butterfly are read
+// from one per-thread base with immediate offsets; P - R_0 entries in all.
+// tw holds w^k, k < P, of the forward sign.
+template <typename C, int P, int NT, int SIGN>
 __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw, int tid) {
-  for (int i = tid; i < P; i += NT) twl[i] = tw[i];
+  constexpr int R0 = radix_at<SIGN>(P, 0);
+  for (int e = tid; e < P - R0; e += NT) {
+    int ns = R0, s = 1;
+    while (e >= ns * radix_at<SIGN>(P, s) - R0) ns *= radix_at<SIGN>(P, s++);
+    const int rad = radix_at<SIGN>(P, s);
+    const int off = e - (ns - R0), rm1 = off / ns, m = off - rm1 * ns;
+    twl[e] = tw[(rm1 + 1) * m * (P / (ns * rad))];
+  }
+}
+// LDS entries for the twiddles of a kernel that runs both directions, the
+// forward table first; the inverse table (tw_inverse) is a second one only
+// where the radix sequences differ.
+template <int P> constexpr int tw_both_size() { return radix_palindrome<P>() ? P : 2 * P; }
+template <typename C, int P, int NT>
+__device__ __forceinline__ void stage_twiddles_both(C* twl, const C* __restrict__ tw, int tid) {
+  stage_twiddles<C, P, NT, -1>(twl, tw, tid);
+  if constexpr (!radix_palindrome<P>()) stage_twiddles<C, P, NT, 1>(twl + P, tw, tid);
+}
+template <int P, typename C> __device__ __forceinline__ C* tw_inverse(C* twl) {
+  if constexpr (radix_palindrome<P>()) return twl;
+  else return twl + P;
 }
 
 // ---------------------------------------------------------------------------
@@ -100,6 +125,16 @@ template <int P> constexpr int wave_nq() {
   while (nq * 2 <= P / 8 && nq * 2 <= 64) nq *= 2;
   return nq;
 }
+#ifndef VGF_FC_MINW32
+#define VGF_FC_MINW32 1
+#endif
+#ifndef VGF_FC_MINW64
+#define VGF_FC_MINW64 1
+#endif
+#ifndef VGF_FC_GPW
+#define VGF_FC_GPW 4
+#endif
+constexpr int64_t kFusedCMinBlocks = 2048;
 template <typename T, int P> struct TileW {
   static constexpr int NQ = wave_nq<P>();  // lanes per line pair
   static constexpr int LPW = 64 / NQ;      // line pairs per wavefront
@@ -107,6 +142,8 @@ template <typename T, int P> struct TileW {
   static constexpr int NT = 64 * WPB;
   static constexpr int LP = line_pitch<P>();
   static constexpr int PAIRS = LPW * WPB;  // line pairs per workgroup
+  // minimum waves per SIMD asked of the register allocator by k_fused_c
+  static constexpr int MINW_FC = sizeof(T) == 4 ? VGF_FC_MINW32 : VGF_FC_MINW64;
   static_assert(n_stages(P) >= 2, "transform needs at least two stages");
 };
 
@@ -147,7 +184,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_r2c(R2CArgs<T> a,
   const int64_t la = 2 * pair, lb = la + 1;
   const bool va = la < a.nlines, vb = lb < a.nlines;
   const EntryLine el(va ? la : 0, a.lpe, a.nlines);
-  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  stage_twiddles<C, P, TW::NT, -1>(twl, tw, tid);
   __syncthreads();
 
   C acc_a[NSLOT], acc_b[NSLOT];
@@ -162,7 +199,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_r2c(R2CArgs<T> a,
       const int pos = S0::in_pos(j, r);
       return C{va ? xa[pos] : T(0), vb ? xb[pos] : T(0)};
     });
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     wave_sync();
     S0::lds_out(g0, tile, l, q);
     wave_sync();
@@ -238,7 +275,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_c2r(C2RArgs<T> a,
     if (va) xs[s] = in[k];
     if (vb) ys[s] = in[a.hs + k];
   }
-  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  stage_twiddles<C, P, TW::NT, 1>(twl, tw, tid);
   __syncthreads();
 
 #pragma unroll
@@ -340,7 +377,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles<C, P, NT, -1>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
   const ColIO ci((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_in);
@@ -355,7 +392,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
     if (term > 0) __syncthreads();
     typename S0::Regs g0;
     S0::template load_first<true>(g0, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
     typename SL::Regs gl;
@@ -399,7 +436,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const C* __restrict__ src = a.in + e * a.g.es_in + bb * a.g.bs_in;
   typename S0::Regs gin;
   S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
@@ -514,7 +551,7 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
   using ISL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C lds[2 * P * LP];
-  __shared__ C twl[P];
+  __shared__ C twl[tw_both_size<P>()];
   PingPong<C, P * LP> pp;
   pp.base = lds;
   pp.off = 0;
@@ -563,7 +600,7 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
     }
     return k1 * tiles_per_row + blk;
   };
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles_both<C, P, NT>(twl, tw, tid);
 
   // loads of one tile: the stage-0 inputs and the kernel spectrum at this
   // thread's forward-output rows (natural order j + r*NB)
@@ -604,7 +641,7 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
       load_tile(fcn, ent, g0n, svn);
     }
 
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     typename SL::Regs rh;  // forward spectrum times the kernel spectrum
     transform_pp<T, P, NT, NL, LP, -1>(g0, rh, pp, twl, l, q);
 #pragma unroll
@@ -619,7 +656,7 @@ __global__ __launch_bounds__((TileF<T, P, V>::NT), (TileF<T, P, V>::MINW_PP)) vo
     auto inverse_store = [&](typename IS0::Regs& v, int fi) {
       IS0::butterflies(v, q);
       typename ISL::Regs o;
-      transform_pp<T, P, NT, NL, LP, 1>(v, o, pp, twl, l, q);
+      transform_pp<T, P, NT, NL, LP, 1>(v, o, pp, tw_inverse<P>(twl), l, q);
       if (fc.io.valid) {
         C* __restrict__ dst = out + e * g.out_es + fi * g.out_fs;
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[fc.io.template off<ISL::NB>(j, r)] = val; });
@@ -682,11 +719,11 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
-  __shared__ C twl[P];
+  __shared__ C twl[tw_both_size<P>()];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
   const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
   const ColIO& cio = fc.io;
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles_both<C, P, NT>(twl, tw, tid);
 
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
@@ -705,7 +742,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
     const C* __restrict__ src = in + fi * g.in_fs;
     typename S0::Regs g0;
     S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     __syncthreads();
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
@@ -742,7 +779,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   IS0::lds_out(acc, lds, l, q);
   __syncthreads();
   typename ISL::Regs o;
-  middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
+  middle_and_last<T, P, NT, NL, LP, 1>(o, lds, tw_inverse<P>(twl), l, q);
   if (cio.valid)
     ISL::template store_last<true>(o, q, [&](int j, int r, C val) { out[cio.off<ISL::NB>(j, r)] = val; });
 }
@@ -799,12 +836,12 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
-  __shared__ C twl[P];
+  __shared__ C twl[tw_both_size<P>()];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
   const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
   const ColIO& cio = fc.io;
   const bool neg1 = g.dim == 3 && (int)(cio.col / (uint32_t)g.hs) > g.n1;
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles_both<C, P, NT>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
   using IS0 = Stage<T, P, NT, NL, LP, 1, 0>;
@@ -813,7 +850,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
 
   typename S0::Regs g0;
   S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
-  S0::butterflies(g0, q);
+  S0::template butterflies<true>(g0, q);
   S0::lds_out(g0, lds, l, q);
   __syncthreads();
   typename SL::Regs rh;
@@ -826,7 +863,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
     IS0::lds_out(v, lds, l, q);
     __syncthreads();
     typename ISL::Regs o;
-    middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
+    middle_and_last<T, P, NT, NL, LP, 1>(o, lds, tw_inverse<P>(twl), l, q);
     if (cio.valid) {
       C* __restrict__ dst = out + fi * g.out_fs;
       ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
@@ -844,12 +881,12 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   constexpr int NL = TL::NL, NT = TL::NT, LP = NL;
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
-  __shared__ C twl[P];
+  __shared__ C twl[tw_both_size<P>()];
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
   const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
   const ColIO& cio = fc.io;
   const bool neg1 = g.dim == 3 && (int)(cio.col / (uint32_t)g.hs) > g.n1;
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles_both<C, P, NT>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
   using IS0 = Stage<T, P, NT, NL, LP, 1, 0>;
@@ -865,7 +902,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
     const C* __restrict__ src = in + fi * g.in_fs;
     typename S0::Regs g0;
     S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     __syncthreads();
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
@@ -888,7 +925,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   IS0::lds_out(acc, lds, l, q);
   __syncthreads();
   typename ISL::Regs o;
-  middle_and_last<T, P, NT, NL, LP, 1>(o, lds, twl, l, q);
+  middle_and_last<T, P, NT, NL, LP, 1>(o, lds, tw_inverse<P>(twl), l, q);
   if (cio.valid)
     ISL::template store_last<true>(o, q, [&](int j, int r, C val) { out[cio.off<ISL::NB>(j, r)] = val; });
 }
@@ -924,7 +961,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const int e = (int)blockIdx.y;
   const int64_t npairs = a.ncols / 2;
   const ColIO ci((int64_t)blockIdx.x * NL + l, npairs, npairs);
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles<C, P, NT, -1>(twl, tw, tid);
 
   C acc_a[NSLOT], acc_b[NSLOT];
 #pragma unroll
@@ -935,7 +972,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
     if (term > 0) __syncthreads();  // the previous term's reads of the tile are done
     typename S0::Regs g0;
     S0::template load_first<true>(g0, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
     typename SL::Regs gl;
@@ -1003,7 +1040,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
     xs[s] = in[k * a.ncols];
     ys[s] = in[k * a.ncols + 1];
   }
-  stage_twiddles<C, P, NT>(twl, tw, tid);
+  stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
@@ -1045,17 +1082,36 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   }
 }
 
-// Multiply-and-inverse pass along the contiguous last axis: one wavefront per
-// group of LPW lines (lanes along the line, every exchange inside the
-// wavefront). Line (k0, k1) of length n_last is transformed forward (pruned
-// input), multiplied by the kernel-spectrum octant row (k0, fold(k1)) at
-// fold(k_last), and inverted (pruned output) as phi's spectrum and, when
-// requested, as -i k_last times it (E_last).
+// Position of a line of the multiply pass, walked without divisions: entry
+// e and (k0, k1) with entry-local line k0 * p1 + k1 (3D: k0 is the axis-0
+// row, k1 the axis-1 wavenumber index; 2D: one row block, k1 = the line).
+struct LineWalk {
+  int e, k0, k1;
+  int p1, h0;
+  __device__ __forceinline__ void advance(int by) {
+    k1 += by;
+    while (k1 >= p1) {
+      k1 -= p1;
+      if (++k0 == h0) {
+        k0 = 0;
+        ++e;
+      }
+    }
+  }
+};
+
+// Multiply-and-inverse pass along the contiguous last axis: each wavefront
+// walks gpw consecutive groups of LPW lines (lanes along the line, every
+// exchange inside the wavefront). Line (k0, k1) of length n_last is
+// transformed forward (pruned input), multiplied by the kernel-spectrum
+// octant row (k0, fold(k1)) at fold(k_last), and inverted (pruned output) as
+// phi's spectrum and, when requested, as -i k_last times it (E_last). The
+// walk over several groups shares the twiddle staging and the index set-up
+// among them and needs no per-line division.
 template <typename T, int P>
-__global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c(const cplx<T>* __restrict__ in,
-                                                              cplx<T>* __restrict__ out, FusedCGeom<T> g,
-                                                              const T* __restrict__ spec,
-                                                              const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_c(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, const T* __restrict__ spec,
+    const cplx<T>* __restrict__ tw, int gpw) {
   using C = cplx<T>;
   using TW = TileW<T, P>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
@@ -1066,65 +1122,94 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c(const cplx<T>* __
   using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LPW * LP];
-  __shared__ C twl[P];
+  __shared__ C twl[tw_both_size<P>()];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l = lane / NQ, q = lane % NQ;
   C* tile = tiles + w * LPW * LP;
-  const int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
-  const bool valid = line < g.nlines;
-  const EntryLine el(valid ? line : 0, g.lpe, g.nlines);
-  const int64_t ll = el.line;
-  int64_t row;  // octant row of this line
-  if (g.dim == 3) {
-    const int P1 = 2 * g.n1;
-    const int k0 = (int)(ll / P1), k1 = (int)(ll - (int64_t)k0 * P1);
-    row = (int64_t)k0 * (g.n1 + 1) + (k1 <= g.n1 ? k1 : P1 - k1);
-  } else {
-    row = ll;
+  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw * LPW + l;
+  LineWalk wk;
+  wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
+  wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
+  {
+    const EntryLine el(line < g.nlines ? line : 0, g.lpe, g.nlines);
+    wk.e = (int)el.e;
+    wk.k0 = (int)el.line / wk.p1;
+    wk.k1 = (int)el.line - wk.k0 * wk.p1;
   }
-  const T* __restrict__ srow = spec + row * (N + 1);
-  const C* __restrict__ src = in + el.e * g.in_es + ll * N;
-  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
   __syncthreads();
 
-  typename S0::Regs g0;
-  S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
-  S0::butterflies(g0, q);
-  S0::lds_out(g0, tile, l, q);
-  wave_sync();
-  typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
-  middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
-#pragma unroll
-  for (int t = 0; t < SL::NTASK; ++t) {
-    if (!SL::active(t, q)) continue;
-    const int j = q + t * SL::NQ;
-#pragma unroll
-    for (int r = 0; r < SL::R; ++r) {
-      const int p = j + r * SL::NB;
-      const T sv = srow[p <= N ? p : P - p];
-      rh.v[t][r].x *= sv;
-      rh.v[t][r].y *= sv;
-    }
-  }
-  for (int fi = 0; fi < g.nf; ++fi) {
-    typename IS0::Regs v;
+  // this lane's kernel-spectrum values of the line at the walk position
+  constexpr int NV = SL::NTASK * SL::R;
+  T sv[NV];
+  auto load_spec = [&](bool ok) {
+    const int row = !ok ? 0
+                        : g.dim == 3 ? wk.k0 * (g.n1 + 1) + (wk.k1 <= g.n1 ? wk.k1 : wk.p1 - wk.k1)
+                                     : wk.k1;
+    const T* __restrict__ srow = spec + (int64_t)row * (N + 1);
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
       if (!SL::active(t, q)) continue;
       const int j = q + t * SL::NQ;
 #pragma unroll
-      for (int r = 0; r < SL::R; ++r)
-        v.v[t][r] = fi == 0 ? rh.v[t][r] : deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks, j, r));
+      for (int r = 0; r < SL::R; ++r) {
+        const int p = j + r * SL::NB;
+        sv[t * SL::R + r] = srow[p <= N ? p : P - p];
+      }
     }
-    IS0::butterflies(v, q);
-    wave_sync();  // the previous transform's reads of the tile are done
-    IS0::lds_out(v, tile, l, q);
+  };
+  typename S0::Regs x;
+  auto load_input = [&](bool ok) {
+    const C* __restrict__ src = ok ? in + wk.e * g.in_es + ((int64_t)wk.k0 * wk.p1 + wk.k1) * N : in;
+    S0::template load_first<true>(x, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+  };
+  bool valid = line < g.nlines;
+  for (int it = 0; it < gpw; ++it) {
+    load_spec(valid);
+    load_input(valid);
+    const bool store = valid;
+    C* __restrict__ dst = store ? out + wk.e * g.out_es + ((int64_t)wk.k0 * wk.p1 + wk.k1) * N : out;
+    S0::template butterflies<true>(x, q);
+    wave_sync();  // the previous line's reads of the tile are done
+    S0::lds_out(x, tile, l, q);
+    line += LPW;
+    wk.advance(LPW);
+    valid = line < g.nlines;
     wave_sync();
-    typename ISL::Regs o;
-    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, twl, l, q);
-    if (valid) {
-      C* __restrict__ dst = out + el.e * g.out_es + fi * g.fs + ll * N;
-      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
+    typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
+    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        rh.v[t][r].x *= sv[t * SL::R + r];
+        rh.v[t][r].y *= sv[t * SL::R + r];
+      }
+    }
+    for (int fi = 0; fi < g.nf; ++fi) {
+      typename IS0::Regs v;
+#pragma unroll
+      for (int t = 0; t < SL::NTASK; ++t) {
+        if (!SL::active(t, q)) continue;
+        int j = q + t * SL::NQ;
+        // FP64: recompute the wavenumbers per line rather than hold them in
+        // registers across the loop (the compiler would hoist them)
+        if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(j));
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r)
+          v.v[t][r] = fi == 0 ? rh.v[t][r] : deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks, j, r));
+      }
+      IS0::butterflies(v, q);
+      wave_sync();  // the previous transform's reads of the tile are done
+      IS0::lds_out(v, tile, l, q);
+      wave_sync();
+      typename ISL::Regs o;
+      middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+      if (store) {
+        C* __restrict__ d = dst + fi * g.fs;
+        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
+      }
     }
   }
 }
@@ -1146,7 +1231,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>
   using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LPW * LP];
-  __shared__ C twl[P];
+  __shared__ C twl[tw_both_size<P>()];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l = lane / NQ, q = lane % NQ;
   C* tile = tiles + w * LPW * LP;
@@ -1163,7 +1248,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>
     row = ll;
   }
   const T* __restrict__ srow = spec + row * (N + 1);
-  stage_twiddles<C, P, TW::NT>(twl, tw, tid);
+  stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
   __syncthreads();
 
   typename IS0::Regs acc;
@@ -1175,7 +1260,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>
     const C* __restrict__ src = in + el.e * g.in_es + fi * g.fs + ll * N;
     typename S0::Regs g0;
     S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
-    S0::butterflies(g0, q);
+    S0::template butterflies<true>(g0, q);
     wave_sync();  // the previous field's reads of the tile are done
     S0::lds_out(g0, tile, l, q);
     wave_sync();
@@ -1211,7 +1296,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>
   IS0::lds_out(acc, tile, l, q);
   wave_sync();
   typename ISL::Regs o;
-  middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, twl, l, q);
+  middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
   if (valid) {
     C* __restrict__ dst = out + el.e * g.out_es + ll * N;
     ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
@@ -1400,12 +1485,19 @@ hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const
   using TW = TileW<T, P>;
   if (g.nf == 0 || g.nlines == 0) return hipSuccess;
   if (g.nf > 2 || (g.lpe > 0 && g.nlines % g.lpe != 0)) return hipErrorInvalidValue;
-  const int64_t per_block = (int64_t)TW::WPB * TW::LPW;
-  const int64_t blocks = (g.nlines + per_block - 1) / per_block;
-  if (adjoint)
+  if (adjoint) {
+    const int64_t per_block = (int64_t)TW::WPB * TW::LPW;
+    const int64_t blocks = (g.nlines + per_block - 1) / per_block;
     hipLaunchKernelGGL((k_fused_c_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw);
-  else
-    hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw);
+  } else {
+    // line groups per wavefront: up to VGF_FC_GPW, fewer where the grid
+    // would drop below kFusedCMinBlocks workgroups
+    const int64_t groups = (g.nlines + TW::LPW - 1) / TW::LPW;
+    int gpw = VGF_FC_GPW;
+    while (gpw > 1 && (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw) < kFusedCMinBlocks) gpw /= 2;
+    const int64_t blocks = (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw);
+    hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
+  }
   return hipGetLastError();
 }
 

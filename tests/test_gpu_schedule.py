@@ -13,21 +13,36 @@ from paper_2103_08531_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-CASES = [((32, 32, 32), "f32"), ((48, 48, 48), "f32"), ((24, 16, 32), "f64"), ((64, 48), "f64"),
-         ((128, 128), "f32"), ((64, 64, 64), "f64")]
+CASES = [((32, 32, 32), "f32", "contiguous"), ((48, 48, 48), "f32", "contiguous"),
+         ((24, 16, 32), "f64", "contiguous"), ((64, 48), "f64", "contiguous"),
+         ((128, 128), "f32", "contiguous"), ((64, 64, 64), "f64", "contiguous"),
+         ((32, 32, 32), "f32", "axis0"), ((24, 16, 32), "f64", "axis0"), ((64, 48), "f64", "axis0")]
 
 
-def _schedules(dim):
-    if dim == 2:
-        return [(0, 0, v, 0, 0) for v in (0, 1)]
-    return [(0, a, b, c, 0) for a, b, c in itertools.product((0, 1), repeat=3)]
+def _tunable(dim, layout):
+    """Passes with two tile schedules: the strided ones of each layout (the
+    axis-0 transforms of the default layout, the axis-0 multiply pass of the
+    axis-0 layout) and, in 3D, the axis-1 transforms."""
+    own = [2] if layout == "axis0" else [0, 4]
+    return own + ([1, 3] if dim == 3 else [])
 
 
-@pytest.mark.parametrize("n,prec", CASES)
-def test_every_schedule_is_bit_identical(n, prec):
+def _schedules(dim, layout):
+    tun = _tunable(dim, layout)
+    out = []
+    for bits in itertools.product((0, 1), repeat=len(tun)):
+        s = [0] * 5
+        for k, b in zip(tun, bits):
+            s[k] = b
+        out.append(tuple(s))
+    return out
+
+
+@pytest.mark.parametrize("n,prec,layout", CASES)
+def test_every_schedule_is_bit_identical(n, prec, layout):
     torch, vgf = need_gpu()
     h = tuple(2.0 / (x - 1) for x in n)
-    plan = vgf.Plan(n, h, precision=prec)
+    plan = vgf.Plan(n, h, precision=prec, layout=layout)
     assert plan.schedule == (0, 0, 0, 0, 0)
     rho = torch.from_numpy(W.random_field(3, n)).to("cuda", plan.dtype)
     g_phi = torch.from_numpy(W.random_field(4, n)).to("cuda", plan.dtype)
@@ -35,7 +50,7 @@ def test_every_schedule_is_bit_identical(n, prec):
     phi0, E0 = plan.solve(rho)
     adj0 = plan.adjoint(g_phi, g_E)
     torch.cuda.synchronize()
-    for sched in _schedules(len(n)):
+    for sched in _schedules(len(n), layout):
         plan.schedule = sched
         assert plan.schedule == sched
         phi, E = plan.solve(rho)
@@ -43,14 +58,13 @@ def test_every_schedule_is_bit_identical(n, prec):
         torch.cuda.synchronize()
         assert torch.equal(phi, phi0) and torch.equal(E, E0), sched
         assert torch.equal(adj, adj0), sched
-    say("%s %s: %d schedules bit-identical" % (n, prec, len(_schedules(len(n)))))
+    say("%s %s %s: %d schedules bit-identical" % (n, prec, layout, len(_schedules(len(n), layout))))
+    for k in range(5):
+        if k not in _tunable(len(n), layout):
+            with pytest.raises(vgf.VGFError):
+                plan.schedule = tuple(1 if i == k else 0 for i in range(5))  # one schedule only
     with pytest.raises(vgf.VGFError):
-        plan.schedule = (1, 0, 0, 0, 0)  # r2c has one schedule only
-    with pytest.raises(vgf.VGFError):
-        plan.schedule = (0, 0, 2, 0, 0)
-    if len(n) == 2:
-        with pytest.raises(vgf.VGFError):
-            plan.schedule = (0, 1, 0, 0, 0)  # no middle pass in 2D
+        plan.schedule = (2, 0, 0, 0, 0)
     plan.close()
 
 
@@ -65,7 +79,7 @@ def test_plan_autotune_is_cached_and_exact():
     sched = plan.autotune(rho, reps=3)
     t_tune = time.perf_counter() - t0
     say("autotuned 128^3 f32 schedule %s in %.1f ms" % (sched, 1e3 * t_tune))
-    assert len(sched) == 5 and sched[0] == 0 and sched[4] == 0 and all(v in (0, 1) for v in sched)
+    assert len(sched) == 5 and sched[2] == 0 and all(v in (0, 1) for v in sched)
     phi, E = plan.solve(rho)
     torch.cuda.synchronize()
     assert torch.equal(phi, phi0) and torch.equal(E, E0)
