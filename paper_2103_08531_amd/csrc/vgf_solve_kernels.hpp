@@ -441,7 +441,15 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int code = a.d.code[o];
-    if (o > 0) __syncthreads();
+    if (o > 0) {
+      __syncthreads();
+      // read the column again (from cache) rather than hold it in registers
+      // through the previous output's transform: that keeps the kernel at
+      // the occupancy its LDS tile allows
+      uint32_t z = 0;
+      asm volatile("" : "+s"(z));
+      S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r) + z]; });
+    }
     typename S0::Regs g0;
     if (code == 0) {
       g0 = gin;
@@ -449,7 +457,8 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
 #pragma unroll
       for (int t = 0; t < S0::NTASK; ++t) {
         if (!S0::active(t, q)) continue;
-        const int j = q + t * S0::NQ;
+        int j = q + t * S0::NQ;
+        asm volatile("" : "+v"(j));  // wavenumbers computed here, not held from the start
 #pragma unroll
         for (int r = 0; r < S0::R; ++r)
           g0.v[t][r] = deriv(gin.v[t][r], code, axis_k<T, S0::R, S0::NB>(a.d.ks, j, r));
@@ -1032,19 +1041,29 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const ColIO ci((int64_t)blockIdx.x * NL + l, npairs, npairs);
   const C* __restrict__ in = a.in + e * a.in_es + 2 * (int64_t)ci.col;
   C xs[NSLOT], ys[NSLOT];
+  auto load = [&](const C* __restrict__ src) {
 #pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const int k = q + NQ * s;
-    xs[s] = ys[s] = C{T(0), T(0)};
-    if (k >= H) continue;
-    xs[s] = in[k * a.ncols];
-    ys[s] = in[k * a.ncols + 1];
-  }
+    for (int s = 0; s < NSLOT; ++s) {
+      const int k = q + NQ * s;
+      xs[s] = ys[s] = C{T(0), T(0)};
+      if (k >= H) continue;
+      xs[s] = src[k * a.ncols];
+      ys[s] = src[k * a.ncols + 1];
+    }
+  };
+  load(in);
   stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int code = a.d.code[o];
+    if (o > 0) {
+      // read the columns again (from cache) rather than hold them in
+      // registers through the previous output's transform
+      uint32_t z = 0;
+      asm volatile("" : "+s"(z));
+      load(in + z);
+    }
     __syncthreads();  // twiddles staged / the previous output's reads are done
     // Z[k] = X[k] + i Y[k], Z[P-k] = conj X[k] + i conj Y[k]; the imaginary
     // parts of X, Y at k = 0 and k = N are dropped (real by symmetry)
