@@ -209,6 +209,7 @@ def write_trace_profile(trace_csv, bench_json, command):
     """Per-kernel durations from a rocprofv3 --kernel-trace run, next to the
     per-pass means the same bench run measured live with HIP events."""
     rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     agg = {}
     for r in rows:
         name = _short_name(r["Kernel_Name"])
@@ -237,6 +238,30 @@ def write_trace_profile(trace_csv, bench_json, command):
         for k in line["passes"]["ms_f32"]:
             md.append("| %s | %.1f | %.1f |" % (k, 1e3 * line["passes"]["ms_f32"][k],
                                                1e3 * line["passes"]["ms_f64"][k]))
+        if "launches_ms_f32" in line["passes"]:
+            md += ["", "Per-launch mean durations of the same timed solves, with the kernel each launch "
+                   "runs under the tuned schedule (%s), in microseconds:" % json.dumps(line.get("schedule")), "",
+                   "live: HIP events of the bench; trace: the same kernel's last dispatches in this trace "
+                   "(the timed solves run last in each precision).", "",
+                   "| launch | pass | FP32 kernel | FP32 live | FP32 trace | FP64 kernel | FP64 live | FP64 trace |",
+                   "|---|---|---|---|---|---|---|---|"]
+            model = launch_model(tuple(line["config"]["grid"]), 4)
+            steps = int(line["steps"])
+
+            def timed_mean(kname):
+                per_solve = sum(1 for pn, pt, _ in model
+                                if launch_kernel_name(pt, "f32" if "float" in kname else "f64",
+                                                      line["schedule"]["f32" if "float" in kname else "f64"],
+                                                      pn) == kname)
+                d = agg.get(kname, {"d": []})["d"][-steps * per_solve:]
+                return sum(d) / len(d) if d else float("nan")
+
+            for i, ((pname, pat, _), a, b) in enumerate(zip(model, line["passes"]["launches_ms_f32"],
+                                                            line["passes"]["launches_ms_f64"])):
+                k32 = launch_kernel_name(pat, "f32", line["schedule"]["f32"], pname)
+                k64 = launch_kernel_name(pat, "f64", line["schedule"]["f64"], pname)
+                md.append("| %d | %s | %s | %.1f | %.1f | %s | %.1f | %.1f |" % (
+                    i, pname, k32, 1e3 * a[1], timed_mean(k32), k64, 1e3 * b[1], timed_mean(k64)))
     md.append("")
     with open(TRACE_MD, "w") as f:
         f.write("\n".join(md))
