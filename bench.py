@@ -39,8 +39,8 @@ same counter reads for a plain 256 MiB device-to-device copy in the same run
 (--copy-calibration). `--digest-counters FETCH_CSV FETCH_OUT WRITE_CSV WRITE_OUT` turns the two
 counter files (with the two profiled runs' outputs, which must carry the
 current source hash) into profiles/vgf_solve_beam_3d_256_traffic.{json,md},
-stamped with a hash of the library sources; a bench run reports the traffic
-only while the sources still hash the same, else null. `--digest-trace STATS_CSV` turns a
+stamped with a hash of the library code (comments and whitespace ignored); a
+bench run reports the traffic only while the code still hashes the same, else null. `--digest-trace STATS_CSV` turns a
 `rocprofv3 --kernel-trace --stats` summary into
 profiles/vgf_solve_beam_3d_256_kernel_trace.md.
 """
@@ -49,6 +49,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -64,15 +65,23 @@ PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_JSON = os.path.join(PROFILES, "vgf_solve_beam_3d_256_traffic.json")
 TRACE_MD = os.path.join(PROFILES, "vgf_solve_beam_3d_256_kernel_trace.md")
 CALIB_BYTES = 256 * 1024 * 1024
-def kernel_source_hash():
-    """sha256 over the library's sources and build flags: counter data taken
-    from other sources no longer describe the kernels that run."""
+def _code_only(text):
+    """C/C++ source without comments and with whitespace collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(root=None):
+    """sha256 over the library's code (comments and whitespace ignored) and
+    its build script: counter data taken from other code no longer describe
+    the kernels that run."""
     h = hashlib.sha256()
-    pkg = os.path.join(ROOT, "paper_2103_08531_amd")
+    pkg = os.path.join(root or ROOT, "paper_2103_08531_amd")
     csrc = os.path.join(pkg, "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(csrc, name)) as f:
+            h.update(name.encode() + b"\0" + _code_only(f.read()).encode())
     with open(os.path.join(pkg, "build.py"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()
@@ -198,7 +207,7 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
         for pname in tot:
             md.append("| %s | %s | %.1f | %.1f | %.3f |" % (pname, label, tot[pname] / 1e6, alg[pname] / 1e6,
                                                            tot[pname] / alg[pname]))
-    md += ["", "Source hash (sha256 of the library sources and build flags the counters describe): `%s`"
+    md += ["", "Source hash (sha256 of the library code, comments and whitespace ignored, and its build script, that the counters describe): `%s`"
            % d["source_hash"], ""]
     with open(TRAFFIC_JSON[:-5] + ".md", "w") as f:
         f.write("\n".join(md))

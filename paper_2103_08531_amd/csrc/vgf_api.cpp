@@ -8,14 +8,17 @@
 // even kernel spectrum on its non-negative octant, pre-divided by the inverse
 // FFT normalisation prod_a(2 N_a) and rounded once to the plan precision.
 //
-// Solve data flow (3D; axis 2 contiguous, P_a = 2 N_a, H = N_2 + 1):
-//   rho [N0][N1][N2]  --r2c axis 2-->  X1 [N0][N1][H]
-//   X1                --c2c axis 1-->  X2 [N0][P1][H]
-//   X2  --fused axis 0 (fwd, x kernel, x -i k_a kernel, inv)-->  Y_f [N0][P1][H]
-//   Y_f               --c2c^-1 axis 1--> Z_f [N0][N1][H]
-//   Z_f               --c2r axis 2-->  phi / E_a [N0][N1][N2]
-// 2D skips the middle-axis passes. All passes are asynchronous on the
-// caller's stream.
+// Solve data flow, default layout (3D; axis 2 contiguous, P_a = 2 N_a,
+// H0 = N_0 + 1):
+//   rho [N0][N1][N2]  --r2c axis 0-->  X1 [H0][N1][N2]
+//   X1                --c2c axis 1-->  X2 [H0][P1][N2]
+//   X2  --axis 2 (fwd, x kernel, inv of phi and -i k_2 phi)-->  Y [H0][P1][N2] x2
+//   Y                 --c2c^-1 axis 1--> Z: phi, E_1 (from phi), E_2 [H0][N1][N2]
+//   Z                 --c2r axis 0-->  phi / E_a [N0][N1][N2]
+// The axis-0 layout (gradient-kernel plans, VGF_LAYOUT_AXIS0) swaps the
+// roles of axes 0 and 2: r2c/c2r along axis 2 (H = N_2 + 1 padded to Hs),
+// the multiply pass along axis 0. 2D skips the middle-axis passes. All
+// passes are asynchronous on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
