@@ -169,7 +169,7 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
     for prec in ("f32", "f64"):
         for pname, pattern, nbytes in launch_model((256, 256, 256), 4 if prec == "f32" else 8):
             for v in (0, 1):
-                alg_of[launch_kernel_name(pattern, prec, [v] * 5, pname)] = nbytes
+                alg_of[launch_kernel_name(pattern, prec, [3 * v] * 5, pname)] = nbytes
     md = [ "# HBM traffic per launch: VGF solve kernels, beam_3d_256 (3D 256^3, phi+E), FP32 and FP64", "",
           "Counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch), one rocprofv3 run each, averaged over "
           "the dispatches of each kernel. Each is scaled by the factor that maps its reading for a plain "
@@ -198,8 +198,9 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
         if not sched:
             continue
         tot, alg = {}, {}
-        for pname, pattern, nbytes in launch_model((256, 256, 256), 4 if prec == "f32" else 8):
-            v = d["kernels"].get(launch_kernel_name(pattern, prec, sched, pname))
+        model = launch_model((256, 256, 256), 4 if prec == "f32" else 8)
+        for (pname, pattern, nbytes), idx in zip(model, launch_indices(model)):
+            v = d["kernels"].get(launch_kernel_name(pattern, prec, sched, pname, idx))
             if v is None:
                 continue
             tot[pname] = tot.get(pname, 0.0) + v["traffic_bytes"]
@@ -257,18 +258,19 @@ def write_trace_profile(trace_csv, bench_json, command):
             model = launch_model(tuple(line["config"]["grid"]), 4)
             steps = int(line["steps"])
 
+            idxs = launch_indices(model)
+
             def timed_mean(kname):
-                per_solve = sum(1 for pn, pt, _ in model
-                                if launch_kernel_name(pt, "f32" if "float" in kname else "f64",
-                                                      line["schedule"]["f32" if "float" in kname else "f64"],
-                                                      pn) == kname)
+                prec = "f32" if "float" in kname else "f64"
+                per_solve = sum(1 for (pn, pt, _), ix in zip(model, idxs)
+                                if launch_kernel_name(pt, prec, line["schedule"][prec], pn, ix) == kname)
                 d = agg.get(kname, {"d": []})["d"][-steps * per_solve:]
                 return sum(d) / len(d) if d else float("nan")
 
             for i, ((pname, pat, _), a, b) in enumerate(zip(model, line["passes"]["launches_ms_f32"],
                                                             line["passes"]["launches_ms_f64"])):
-                k32 = launch_kernel_name(pat, "f32", line["schedule"]["f32"], pname)
-                k64 = launch_kernel_name(pat, "f64", line["schedule"]["f64"], pname)
+                k32 = launch_kernel_name(pat, "f32", line["schedule"]["f32"], pname, idxs[i])
+                k64 = launch_kernel_name(pat, "f64", line["schedule"]["f64"], pname, idxs[i])
                 md.append("| %d | %s | %s | %.1f | %.1f | %s | %.1f | %.1f |" % (
                     i, pname, k32, 1e3 * a[1], timed_mean(k32), k64, 1e3 * b[1], timed_mean(k64)))
     md.append("")
@@ -326,9 +328,21 @@ def kernel_bytes(n, prec_bytes):
     return out
 
 
-def launch_kernel_name(name_pattern, prec, schedule, pass_name):
-    """Concrete kernel name of a launch under a tile schedule."""
-    return name_pattern.format(t="float" if prec == "f32" else "double", v=schedule[PASS_INDEX[pass_name]])
+def launch_indices(model):
+    """Index of each launch among the launches of its pass (0 = the first)."""
+    seen, out = {}, []
+    for pname, _, _ in model:
+        out.append(seen.get(pname, 0))
+        seen[pname] = out[-1] + 1
+    return out
+
+
+def launch_kernel_name(name_pattern, prec, schedule, pass_name, idx=0):
+    """Concrete kernel name of a pass's launch number idx under a tile
+    schedule (bit 0 of the pass's value: its first launch; bit 1: the later
+    ones)."""
+    v = (schedule[PASS_INDEX[pass_name]] >> (1 if idx > 0 else 0)) & 1
+    return name_pattern.format(t="float" if prec == "f32" else "double", v=v)
 
 
 def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
@@ -577,7 +591,7 @@ def main():
         pname, pattern, nbytes = model[k]
         assert res["launches"][k][0] == pname, (res["launches"], model)
         ms = res["launches"][k][1]
-        name = launch_kernel_name(pattern, prec, res["schedule"], pname)
+        name = launch_kernel_name(pattern, prec, res["schedule"], pname, launch_indices(model)[k])
         tr = None
         if traffic is not None and name in traffic["kernels"]:
             tr = traffic["kernels"][name]["traffic_bytes"]

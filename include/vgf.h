@@ -217,32 +217,40 @@ int vgf_batch_hip_error(vgf_batch batch);
 void vgf_batch_destroy(vgf_batch batch);
 
 /* ---- Tile schedules and their autotuner ----
- * The strided FFT passes (axis-1 forward and inverse in 3D, the fused axis-0
- * pass) come in tile-schedule variants: 0 = one 128-byte row segment of
- * columns per workgroup (the default), 1 = half of it (more and smaller
- * workgroups). A variant changes only the launch shape: every line is
+ * The strided FFT passes come in two tile variants: 0 = one 128-byte row
+ * segment of columns per workgroup (the default), 1 = half of it (more and
+ * smaller workgroups). Strided are, in the default layout, the axis-0 R2C
+ * and C2R passes and the axis-1 passes (3D); in the axis-0 layout
+ * (VGF_LAYOUT_AXIS0, gradient-kernel plans) the axis-1 passes and the axis-0
+ * multiply pass. A variant changes only the launch shape: every line is
  * transformed with the same arithmetic, so results are bit-identical across
- * schedules. A schedule is an int[5], one variant per pass in the order
+ * schedules. A schedule is an int[5], one value per pass in the order
  * VGF_PASS_R2C, VGF_PASS_C2C_FWD, VGF_PASS_FUSED, VGF_PASS_C2C_INV,
- * VGF_PASS_C2R; the contiguous-axis passes (and the 2D middle passes, which
- * do not exist) only take 0. */
+ * VGF_PASS_C2R. A value holds two bits: bit 0 is the variant of the pass's
+ * first launch, bit 1 that of its later launches (the inverse passes launch
+ * once per group of outputs, the two-output launch first; adjoints may
+ * launch a pass more than once). Passes that are not strided (and the 2D
+ * middle passes, which do not exist) only take 0. */
 enum { VGF_PASS_R2C = 0, VGF_PASS_C2C_FWD = 1, VGF_PASS_FUSED = 2, VGF_PASS_C2C_INV = 3,
        VGF_PASS_C2R = 4, VGF_NUM_PASSES = 5 };
 
 /* Chooses the plan's schedule by measurement: two warm-up solves per
  * variant, then `reps` rounds that each run one solve of (rho, phi, E)
- * (arguments as vgf_solve) per variant, interleaved, with HIP events at the
- * pass boundaries on `stream`. Each pass takes its fastest repetition per
- * variant and keeps the default variant unless another is more than 2%
- * faster. phi / E receive solve results. Synchronises `stream`.
+ * (arguments as vgf_solve) per variant, interleaved, with HIP events after
+ * every launch on `stream`. For each pass, its first launch and its later
+ * launches each take their fastest repetition per variant and keep the
+ * default variant unless another is more than 2% faster; a pass launched
+ * once gives both bits its first launch's choice. phi / E receive solve
+ * results. Synchronises `stream`.
  * The choice is cached in the process per (grid, precision, outputs), so an
  * identical plan tuned again takes the cached schedule without running.
  * Errors: as vgf_solve, INVALID_ARG for reps <= 0. */
 vgf_status vgf_plan_autotune(vgf_plan plan, const void* rho, void* phi, void* E, int reps,
                              hipStream_t stream);
 
-/* The plan's schedule (int[5], see above); set checks every variant and
- * rejects a non-zero variant for a pass that has none (INVALID_ARG). */
+/* The plan's schedule (int[5], see above); set checks every value (0..3)
+ * and rejects a non-zero value for a pass that has no variants
+ * (INVALID_ARG). */
 vgf_status vgf_plan_get_schedule(vgf_plan plan, int* schedule);
 vgf_status vgf_plan_set_schedule(vgf_plan plan, const int* schedule);
 

@@ -466,6 +466,13 @@ void c2r_out(vgf::C2RArgs<T>& ca, int o, const Entries<T>& en, int field, int64_
 // pass ids (also the order of plan->schedule)
 enum { kPassR2C = 0, kPassC2CF = 1, kPassFused = 2, kPassC2CI = 3, kPassC2R = 4, kPasses = 5 };
 
+// Tile variant of a pass's launch under a schedule value: bit 0 selects the
+// variant of the pass's first launch, bit 1 that of its later launches (the
+// passes that launch more than once start with the launch that forms two
+// outputs from phi's spectrum).
+inline int launch_variant(const int* sched, int pass, int idx) { return (sched[pass] >> (idx > 0 ? 1 : 0)) & 1; }
+constexpr int kScheduleValues = 4;
+
 template <typename T>
 vgf::GradSpec<T> grad_spec(vgf_plan p) {
   vgf::GradSpec<T> sp{};
@@ -506,7 +513,7 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
     const int64_t P1 = p->P[1];
     const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     fused_in = b.x2;
     g.out_fs = N0 * P1 * Hs;
   } else {
@@ -520,7 +527,7 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
     const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     for (int f = 0; f < g.nf; ++f) {
       vgf::C2CInvArgs<T> ia{b.y + f * g.out_fs, {b.z + f * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, f), ia, tw(1), s));
     }
     lastin = b.z;
     last_fs = zfs;
@@ -572,7 +579,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   ra.ncols = vol / N0;
   ra.nentry = en.count;
   ra.d = deriv1<T>(p, 0, 0);
-  VGF_LAUNCH(kPassR2C, vgf::launch_r2c_s<T>((int)p->P[0], sched[kPassR2C], ra, tw(0), s));
+  VGF_LAUNCH(kPassR2C, vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(sched, kPassR2C, 0), ra, tw(0), s));
   const cplx<T>* fin = b.x1;
   vgf::FusedCGeom<T> g{};
   g.dim = d;
@@ -591,7 +598,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     fg.nentry = en.count;
     fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     fin = b.x2;
   }
   VGF_LAUNCH(kPassFused, vgf::launch_fused_c<T>((int)p->P[d - 1], false, fin, b.y, g, (const T*)p->spec, tw(d - 1), s));
@@ -605,10 +612,10 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
     vgf::C2CInvArgs<T> ia{b.y, {b.z, b.z + zfs}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
     if (want_E) {
       vgf::C2CInvArgs<T> ia2{b.y + g.fs, {b.z + 2 * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia2, tw(1), s));
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 1), ia2, tw(1), s));
     }
     zphi = b.z;
     zf[0] = b.z + zfs;
@@ -618,6 +625,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     zf[0] = b.y + g.fs;
   }
   (void)zes;
+  int nc2r = 0;  // launches of the c2r pass so far
   auto c2r = [&](const cplx<T>* in, int f0, int code0, int f1, int code1) -> hipError_t {
     vgf::C2RSArgs<T> ca{};
     ca.in = in;
@@ -627,7 +635,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     ca.d = f1 == -2 ? deriv1<T>(p, 0, code0) : deriv2<T>(p, 0, code0, code1);
     c2r_s_out(ca, 0, en, f0, vol);
     if (f1 != -2) c2r_s_out(ca, 1, en, f1, vol);
-    return vgf::launch_c2r_s<T>((int)p->P[0], sched[kPassC2R], ca, tw(0), s);
+    return vgf::launch_c2r_s<T>((int)p->P[0], launch_variant(sched, kPassC2R, nc2r++), ca, tw(0), s);
   };
   if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(zphi, -1, 0, 0, -1));
   else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(zphi, -1, 0, -2, 0));
@@ -692,8 +700,8 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     fg.nentry = en.count;
     fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
-    VGF_LAUNCH(kPassFused, vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x2, b.y, g, spec, tw(0), s));
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
+    VGF_LAUNCH(kPassFused, vgf::launch_fused<T>((int)p->P[0], launch_variant(sched, kPassFused, 0), false, b.x2, b.y, g, spec, tw(0), s));
     // Yp -> Zp (phi, and E_2 later) and Z1 = -i k_1 Zp; Y0 -> Z0
     vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     ig.nentry = en.count;
@@ -702,10 +710,10 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     cplx<T>* z1 = b.z + zfs;
     cplx<T>* z0 = b.z + 2 * zfs;
     vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
     if (want_E) {
       vgf::C2CInvArgs<T> ia0{b.y + yfs, {z0, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia0, tw(1), s));
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 1), ia0, tw(1), s));
     }
     if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(zp, -1, 0, 2, -1));
     else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(zp, -1, 0, -2, 0));
@@ -718,7 +726,7 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     const int64_t yfs = N0 * Hs;
     g.out_fs = yfs;
     VGF_LAUNCH(kPassR2C, vgf::launch_r2c<T>((int)p->P[1], ra, tw(1), s));
-    VGF_LAUNCH(kPassFused, vgf::launch_fused<T>((int)p->P[0], sched[kPassFused], false, b.x1, b.y, g, spec, tw(0), s));
+    VGF_LAUNCH(kPassFused, vgf::launch_fused<T>((int)p->P[0], launch_variant(sched, kPassFused, 0), false, b.x1, b.y, g, spec, tw(0), s));
     if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(b.y, -1, 0, 1, -1));
     else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(b.y, -1, 0, -2, 0));
     else VGF_LAUNCH(kPassC2R, c2r(b.y, 1, -1, -2, 0));
@@ -773,9 +781,11 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
   std::vector<int> nmark((size_t)reps * NV, 0);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  // variant v on every launch of every tunable pass (both bits of the value)
+  static_assert(NV == 2, "schedule values hold one bit per launch class");
   int sched[NV][kPasses];
   for (int v = 0; v < NV; ++v)
-    for (int k = 0; k < kPasses; ++k) sched[v][k] = pass_tunable(p, k) ? v : 0;
+    for (int k = 0; k < kPasses; ++k) sched[v][k] = pass_tunable(p, k) ? v * 3 : 0;
   vgf_status st = VGF_OK;
   // warm-up of every variant, then the variants interleaved rep by rep so
   // that clock ramps and cache state bias none of them
@@ -786,21 +796,27 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
       const size_t o = ((size_t)r * NV + v) * kMaxMarks;
       st = run(sched[v], &ev[o], &tags[o]);
     }
-  // fastest repetition of each pass under each variant
-  double t[NV][kPasses];
+  // fastest repetition under each variant of each pass's first launch
+  // (class 0) and of its later launches together (class 1)
+  double t[NV][kPasses][2];
+  bool later[kPasses] = {};
   for (int v = 0; v < NV; ++v)
-    for (int k = 0; k < kPasses; ++k) t[v][k] = 1e30;
+    for (int k = 0; k < kPasses; ++k) t[v][k][0] = t[v][k][1] = 1e30;
   if (st == VGF_OK && e == hipSuccess) e = hipStreamSynchronize(s);
   for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
     for (int v = 0; v < NV && e == hipSuccess; ++v) {
       const size_t o = ((size_t)r * NV + v) * kMaxMarks;
-      double pass_ms[kPasses] = {};
+      double pass_ms[kPasses][2] = {};
+      int seen[kPasses] = {};
       for (int i = 0; i + 1 < kMaxMarks && tags[o + i] >= 0 && e == hipSuccess; ++i) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, ev[o + i], ev[o + i + 1]);
-        pass_ms[tags[o + i]] += ms;
+        const int k = tags[o + i], c = seen[k]++ > 0 ? 1 : 0;
+        pass_ms[k][c] += ms;
+        if (c) later[k] = true;
       }
-      for (int k = 0; k < kPasses; ++k) t[v][k] = std::min(t[v][k], pass_ms[k]);
+      for (int k = 0; k < kPasses; ++k)
+        for (int c = 0; c < 2; ++c) t[v][k][c] = std::min(t[v][k][c], pass_ms[k][c]);
     }
   for (hipEvent_t x : ev)
     if (x) (void)hipEventDestroy(x);
@@ -809,12 +825,18 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
     *herr = e;
     return VGF_ERR_HIP;
   }
-  // keep the default unless another variant is faster by more than 2%
+  // per launch class, keep the default unless another variant is faster by
+  // more than 2%; a pass without later launches gives them its first
+  // launch's variant (the adjoint may launch it more than once)
   for (int k = 0; k < kPasses; ++k) {
     best[k] = 0;
     if (!pass_tunable(p, k)) continue;
-    for (int v = 1; v < NV; ++v)
-      if (t[v][k] < 0.98 * t[best[k]][k]) best[k] = v;
+    int b[2] = {0, 0};
+    for (int c = 0; c < 2; ++c)
+      for (int v = 1; v < NV; ++v)
+        if (t[v][k][c] < 0.98 * t[b[c]][k][c]) b[c] = v;
+    if (!later[k]) b[1] = b[0];
+    best[k] = b[0] | (b[1] << 1);
   }
   return VGF_OK;
 }
@@ -914,13 +936,13 @@ vgf_status adjoint_grad_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hi
       ra.lpe = lpe;
       VGF_RUN(vgf::launch_r2c<T>((int)p->P[2], ra, tw(2), s));
       vgf::C2CFwdArgs<T> fa{{b.z + f * zfs, nullptr}, b.y + f * yfs, fg, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, p->schedule[kPassC2CF], fa, tw(1), s));
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(p->schedule, kPassC2CF, f), fa, tw(1), s));
     }
     g.in_fs = yfs;
     VGF_RUN(vgf::launch_fused_grad<T>((int)p->P[0], true, b.y, b.x2, g, grad_spec<T>(p), tw(0), s));
     const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, p->schedule[kPassC2CI], ia, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, launch_variant(p->schedule, kPassC2CI, 0), ia, tw(1), s));
   } else {
     const int64_t yfs = N0 * Hs;
     for (int f = 0; f < g.nf; ++f) {
@@ -951,6 +973,7 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
   const int64_t fs = lpe * NL;             // field stride of Y
   const int64_t zfs = H0 * N1 * (d == 3 ? NL : 1);  // field stride of Z (3D)
   // axis 0: A = R2C(g_phi) + i k_0 R2C(g_E0); the other fields plain
+  int nr2c = 0;  // launches of the r2c kernel so far
   auto r2c = [&](cplx<T>* out, const T* in0, int code0, const T* in1, int code1) -> hipError_t {
     vgf::R2CSArgs<T> ra{};
     ra.out = out;
@@ -960,7 +983,7 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
     ra.d.n = 0;
     if (in0) { ra.in[ra.d.n] = in0; ra.d.code[ra.d.n++] = code0; }
     if (in1) { ra.in[ra.d.n] = in1; ra.d.code[ra.d.n++] = code1; }
-    return vgf::launch_r2c_s<T>((int)p->P[0], sched[kPassR2C], ra, tw(0), s);
+    return vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(sched, kPassR2C, nr2c++), ra, tw(0), s);
   };
   vgf::FusedCGeom<T> g{};
   g.dim = d;
@@ -984,17 +1007,17 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
     }
     const vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
     vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], fa, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     g.fields[g.nf++] = 0;
     if (g_E) {
       vgf::C2CFwdArgs<T> f2{{zb2, nullptr}, b.y + fs, fg, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, sched[kPassC2CF], f2, tw(1), s));
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 1), f2, tw(1), s));
       g.fields[g.nf++] = 1;
     }
     VGF_RUN(vgf::launch_fused_c<T>((int)p->P[2], true, b.y, b.x2, g, (const T*)p->spec, tw(2), s));
     const vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, sched[kPassC2CI], ia, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
   } else {
     VGF_RUN(r2c(b.y, g_phi, 0, g_E, 1));
     g.fields[g.nf++] = 0;
@@ -1010,7 +1033,7 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
   ca.ncols = vol / N0;
   ca.nentry = 1;
   ca.d = deriv1<T>(p, 0, 0);
-  VGF_RUN(vgf::launch_c2r_s<T>((int)p->P[0], sched[kPassC2R], ca, tw(0), s));
+  VGF_RUN(vgf::launch_c2r_s<T>((int)p->P[0], launch_variant(sched, kPassC2R, 0), ca, tw(0), s));
   return VGF_OK;
 }
 
@@ -1053,16 +1076,16 @@ vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStre
     }
     const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
     vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, p->schedule[kPassC2CF], fa, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(p->schedule, kPassC2CF, 0), fa, tw(1), s));
     if (g_E) {
       vgf::C2CFwdArgs<T> f0{{zb0, nullptr}, b.y + yfs, fg, deriv1<T>(p, 1, 0)};
-      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, p->schedule[kPassC2CF], f0, tw(1), s));
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(p->schedule, kPassC2CF, 1), f0, tw(1), s));
     }
     g.in_fs = yfs;
     VGF_RUN(vgf::launch_fused<T>((int)p->P[0], 0, true, b.y, b.x2, g, spec, tw(0), s));
     const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
-    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, p->schedule[kPassC2CI], ia, tw(1), s));
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, launch_variant(p->schedule, kPassC2CI, 0), ia, tw(1), s));
     vgf::C2RArgs<T> ca{b.x1, {g_rho, nullptr}, N0 * N1, Hs, deriv1<T>(p, 2, 0)};
     VGF_RUN(vgf::launch_c2r<T>((int)p->P[2], ca, tw(2), s));
   } else {
@@ -1350,7 +1373,7 @@ vgf_status vgf_plan_get_schedule(vgf_plan p, int* schedule) {
 vgf_status vgf_plan_set_schedule(vgf_plan p, const int* schedule) {
   if (!p || !schedule) return VGF_ERR_INVALID_ARG;
   for (int k = 0; k < kPasses; ++k) {
-    if (schedule[k] < 0 || schedule[k] >= vgf_tile_variants()) return VGF_ERR_INVALID_ARG;
+    if (schedule[k] < 0 || schedule[k] >= kScheduleValues) return VGF_ERR_INVALID_ARG;
     if (schedule[k] != 0 && !pass_tunable(p, k)) return VGF_ERR_INVALID_ARG;
   }
   for (int k = 0; k < kPasses; ++k) p->schedule[k] = schedule[k];

@@ -70,6 +70,22 @@ constexpr int kTileVariants = kTileVariantsHost;
 template <typename T, int P, int V>
 struct TileV : Tile<T, P, (V == 0 ? 0 : (Tile<T, P>::NL > 1 ? Tile<T, P>::NL / 2 : 1))> {};
 
+// Block -> column tile of the strided passes. Half-width tiles (V = 1) split
+// each 128-byte row segment between two workgroups; workgroups are dealt to
+// the 8 XCDs round-robin, so the two halves go to blocks 8 apart (same XCD,
+// consecutive dispatch rounds) and the second half is read from that XCD's
+// L2. A bijection on [0, nb).
+template <int V> __device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t nb) {
+  if constexpr (V == 0) {
+    return b;
+  } else {
+    const int64_t full = nb & ~(int64_t)15;
+    if (b >= full) return b;
+    const int64_t x = b & 7, k = b >> 3;
+    return ((((k >> 1) << 3) + x) << 1) + (k & 1);
+  }
+}
+
 // signed frequency of index k on a length-2N axis, Nyquist index N -> 0
 __device__ __forceinline__ int signed_freq_zn(int k, int N) {
   return k < N ? k : (k == N ? 0 : k - 2 * N);
@@ -380,8 +396,8 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   stage_twiddles<C, P, NT, -1>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
-  const ColIO ci((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_in);
-  const ColIO co((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_out);
+  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_in);
+  const ColIO co(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_out);
   typename SL::Regs acc;
 
   const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
@@ -430,8 +446,8 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
   using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
   using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
-  const ColIO ci((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_in);
-  const ColIO co((int64_t)blockIdx.x * NL + l, a.g.ncols, a.g.ls_out);
+  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_in);
+  const ColIO co(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_out);
   const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
   const C* __restrict__ src = a.in + e * a.g.es_in + bb * a.g.bs_in;
   typename S0::Regs gin;
@@ -969,7 +985,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
   const int e = (int)blockIdx.y;
   const int64_t npairs = a.ncols / 2;
-  const ColIO ci((int64_t)blockIdx.x * NL + l, npairs, npairs);
+  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, npairs, npairs);
   stage_twiddles<C, P, NT, -1>(twl, tw, tid);
 
   C acc_a[NSLOT], acc_b[NSLOT];
@@ -1038,7 +1054,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
   const int e = (int)blockIdx.y;
   const int64_t npairs = a.ncols / 2;
-  const ColIO ci((int64_t)blockIdx.x * NL + l, npairs, npairs);
+  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, npairs, npairs);
   const C* __restrict__ in = a.in + e * a.in_es + 2 * (int64_t)ci.col;
   C xs[NSLOT], ys[NSLOT];
   auto load = [&](const C* __restrict__ src) {
@@ -1234,12 +1250,12 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
 }
 
 // adjoint: acc = sum_f conj(m_f) FFT(in_f) (m_f = 1 or -i k_last), times the
-// real kernel spectrum, inverted with pruned output
+// real kernel spectrum, inverted with pruned output; the same line walk as
+// the forward pass
 template <typename T, int P>
-__global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>* __restrict__ in,
-                                                                  cplx<T>* __restrict__ out, FusedCGeom<T> g,
-                                                                  const T* __restrict__ spec,
-                                                                  const cplx<T>* __restrict__ tw) {
+__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_c_adj(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, const T* __restrict__ spec,
+    const cplx<T>* __restrict__ tw, int gpw) {
   using C = cplx<T>;
   using TW = TileW<T, P>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
@@ -1254,71 +1270,80 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_fused_c_adj(const cplx<T>
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l = lane / NQ, q = lane % NQ;
   C* tile = tiles + w * LPW * LP;
-  const int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * LPW + l;
-  const bool valid = line < g.nlines;
-  const EntryLine el(valid ? line : 0, g.lpe, g.nlines);
-  const int64_t ll = el.line;
-  int64_t row;
-  if (g.dim == 3) {
-    const int P1 = 2 * g.n1;
-    const int k0 = (int)(ll / P1), k1 = (int)(ll - (int64_t)k0 * P1);
-    row = (int64_t)k0 * (g.n1 + 1) + (k1 <= g.n1 ? k1 : P1 - k1);
-  } else {
-    row = ll;
+  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw * LPW + l;
+  LineWalk wk;
+  wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
+  wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
+  {
+    const EntryLine el(line < g.nlines ? line : 0, g.lpe, g.nlines);
+    wk.e = (int)el.e;
+    wk.k0 = (int)el.line / wk.p1;
+    wk.k1 = (int)el.line - wk.k0 * wk.p1;
   }
-  const T* __restrict__ srow = spec + row * (N + 1);
   stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
   __syncthreads();
 
-  typename IS0::Regs acc;
+  bool valid = line < g.nlines;
+  for (int it = 0; it < gpw; ++it) {
+    const int64_t lofs = ((int64_t)wk.k0 * wk.p1 + wk.k1) * N;
+    const int row = !valid ? 0
+                           : g.dim == 3 ? wk.k0 * (g.n1 + 1) + (wk.k1 <= g.n1 ? wk.k1 : wk.p1 - wk.k1)
+                                        : wk.k1;
+    const T* __restrict__ srow = spec + (int64_t)row * (N + 1);
+    typename IS0::Regs acc;
 #pragma unroll
-  for (int t = 0; t < SL::NTASK; ++t)
+    for (int t = 0; t < SL::NTASK; ++t)
 #pragma unroll
-    for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
-  for (int fi = 0; fi < g.nf; ++fi) {
-    const C* __restrict__ src = in + el.e * g.in_es + fi * g.fs + ll * N;
-    typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
-    S0::template butterflies<true>(g0, q);
-    wave_sync();  // the previous field's reads of the tile are done
-    S0::lds_out(g0, tile, l, q);
-    wave_sync();
-    typename SL::Regs rh;
-    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
-    const bool d = g.fields[fi] != 0;
+      for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
+    for (int fi = 0; fi < g.nf; ++fi) {
+      const C* __restrict__ src = valid ? in + wk.e * g.in_es + fi * g.fs + lofs : in;
+      typename S0::Regs g0;
+      S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+      S0::template butterflies<true>(g0, q);
+      wave_sync();  // the previous transform's reads of the tile are done
+      S0::lds_out(g0, tile, l, q);
+      wave_sync();
+      typename SL::Regs rh;
+      middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+      const bool d = g.fields[fi] != 0;
+#pragma unroll
+      for (int t = 0; t < SL::NTASK; ++t) {
+        if (!SL::active(t, q)) continue;
+        int j = q + t * SL::NQ;
+        if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(j));
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r) {
+          const C m = d ? deriv(rh.v[t][r], 1, axis_k<T, SL::R, SL::NB>(g.ks, j, r)) : rh.v[t][r];
+          acc.v[t][r].x += m.x;
+          acc.v[t][r].y += m.y;
+        }
+      }
+    }
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
       if (!SL::active(t, q)) continue;
       const int j = q + t * SL::NQ;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
-        const C m = d ? deriv(rh.v[t][r], 1, axis_k<T, SL::R, SL::NB>(g.ks, j, r)) : rh.v[t][r];
-        acc.v[t][r].x += m.x;
-        acc.v[t][r].y += m.y;
+        const int p = j + r * SL::NB;
+        const T sv = srow[p <= N ? p : P - p];
+        acc.v[t][r].x *= sv;
+        acc.v[t][r].y *= sv;
       }
     }
-  }
-#pragma unroll
-  for (int t = 0; t < SL::NTASK; ++t) {
-    if (!SL::active(t, q)) continue;
-    const int j = q + t * SL::NQ;
-#pragma unroll
-    for (int r = 0; r < SL::R; ++r) {
-      const int p = j + r * SL::NB;
-      const T sv = srow[p <= N ? p : P - p];
-      acc.v[t][r].x *= sv;
-      acc.v[t][r].y *= sv;
+    IS0::butterflies(acc, q);
+    wave_sync();
+    IS0::lds_out(acc, tile, l, q);
+    wave_sync();
+    typename ISL::Regs o;
+    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+    if (valid) {
+      C* __restrict__ dst = out + wk.e * g.out_es + lofs;
+      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
     }
-  }
-  IS0::butterflies(acc, q);
-  wave_sync();
-  IS0::lds_out(acc, tile, l, q);
-  wave_sync();
-  typename ISL::Regs o;
-  middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
-  if (valid) {
-    C* __restrict__ dst = out + el.e * g.out_es + ll * N;
-    ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
+    line += LPW;
+    wk.advance(LPW);
+    valid = line < g.nlines;
   }
 }
 
@@ -1504,19 +1529,16 @@ hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const
   using TW = TileW<T, P>;
   if (g.nf == 0 || g.nlines == 0) return hipSuccess;
   if (g.nf > 2 || (g.lpe > 0 && g.nlines % g.lpe != 0)) return hipErrorInvalidValue;
-  if (adjoint) {
-    const int64_t per_block = (int64_t)TW::WPB * TW::LPW;
-    const int64_t blocks = (g.nlines + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_fused_c_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw);
-  } else {
-    // line groups per wavefront: up to VGF_FC_GPW, fewer where the grid
-    // would drop below kFusedCMinBlocks workgroups
-    const int64_t groups = (g.nlines + TW::LPW - 1) / TW::LPW;
-    int gpw = VGF_FC_GPW;
-    while (gpw > 1 && (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw) < kFusedCMinBlocks) gpw /= 2;
-    const int64_t blocks = (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw);
+  // line groups per wavefront: up to VGF_FC_GPW, fewer where the grid would
+  // drop below kFusedCMinBlocks workgroups
+  const int64_t groups = (g.nlines + TW::LPW - 1) / TW::LPW;
+  int gpw = VGF_FC_GPW;
+  while (gpw > 1 && (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw) < kFusedCMinBlocks) gpw /= 2;
+  const int64_t blocks = (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw);
+  if (adjoint)
+    hipLaunchKernelGGL((k_fused_c_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
+  else
     hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
-  }
   return hipGetLastError();
 }
 
