@@ -518,6 +518,73 @@ def cpu_baseline(ch, rho64, L, results):
     return base, acc
 
 
+def host_info():
+    """CPU model, logical CPUs and memory of the machine running the oracle."""
+    model, mem = "?", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count(), "mem_gib": round(mem / 2**30, 1)}
+
+
+def oracle_timing(seed):
+    """The oracle's 2N FFT path per workload on the host cores, with all of
+    the oracle's threads and with one (kernel precompute excluded, as in
+    the CPU baseline). The batch and the differentiable step are timed on one
+    grid of each size they hold and summed over their draws."""
+    import oracle as orc
+    from paper_2103_08531_amd import workloads as W
+
+    def solve_time(ch, want_phi=True, want_E=True, adjoint=False):
+        w = orc.vgf_kernel(ch.n, ch.h, orc.default_L(ch.n, ch.h))
+        rho = ch.rho()
+        t0 = time.perf_counter()
+        orc.solve_fft2n(ch.n, ch.h, w, rho, want_phi=want_phi, want_E=want_E)
+        if adjoint:
+            orc.adjoint_fft2n(ch.n, ch.h, w, None, np.stack([rho] * len(ch.n)))
+        return time.perf_counter() - t0
+
+    batch = W.batch_3d_mixed(seed)
+    rhs, _ = W.diff_3d_128(seed)
+    full = orc.num_threads()
+    rows = []
+    for threads in (full, 1):
+        orc.set_num_threads(threads)
+        r = {"threads": threads}
+        r["gaussian_3d_32"] = solve_time(W.gaussian_3d_32(seed))
+        print("[oracle %d threads] gaussian_3d_32 %.2f s" % (threads, r["gaussian_3d_32"]), file=sys.stderr, flush=True)
+        r["mixture_2d_512"] = solve_time(W.mixture_2d_512(seed))
+        print("[oracle %d threads] mixture_2d_512 %.2f s" % (threads, r["mixture_2d_512"]), file=sys.stderr, flush=True)
+        per_size = {}
+        for ch in batch:
+            N = ch.n[0]
+            if N not in per_size:
+                per_size[N] = solve_time(ch)
+                print("[oracle %d threads] batch grid %d^3 %.2f s" % (threads, N, per_size[N]),
+                      file=sys.stderr, flush=True)
+        r["batch_3d_mixed"] = sum(per_size[ch.n[0]] for ch in batch)
+        r["diff_3d_128"] = len(rhs) * solve_time(rhs[0], want_phi=False, want_E=True, adjoint=True)
+        print("[oracle %d threads] diff_3d_128 %.2f s" % (threads, r["diff_3d_128"]), file=sys.stderr, flush=True)
+        if threads == full:
+            r["beam_3d_256"] = solve_time(W.beam_3d_256(seed))
+            print("[oracle %d threads] beam_3d_256 %.2f s" % (threads, r["beam_3d_256"]), file=sys.stderr,
+                  flush=True)
+        rows.append(r)
+    orc.set_num_threads(full)
+    return {"host": host_info(), "seconds": rows,
+            "note": "seconds per solve (gaussian_3d_32, mixture_2d_512, beam_3d_256: phi + E), per batch of "
+                    "64 grids (batch_3d_mixed, phi + E), per step of 8 E-only solves and 8 adjoints "
+                    "(diff_3d_128); the 256^3 solve runs with all threads only"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,7 +603,13 @@ def main():
     ap.add_argument("--digest-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
                     help="write the kernel-trace profile from a rocprofv3 kernel_trace.csv file")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the profile")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the oracle's 2N FFT path on every workload (all threads and one), "
+                         "print one JSON line and exit (no GPU)")
     args = ap.parse_args()
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing(args.seed)), flush=True)
+        return
     if args.digest_counters:
         write_traffic_profile(*args.digest_counters, command=args.command)
         return
