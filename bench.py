@@ -29,7 +29,8 @@ Printed JSON line (one, rank 0):
                replayed hipGraph, before and after autotuning the groups' tile
                schedules, in ms per batch and solves/s
   other_workloads  gaussian_3d_32 and mixture_2d_512 (FP64, VGF and HE)
-               solves/s, diff_3d_128 (8 FP32 forward solves + 8 adjoints) ms
+               solves/s, launched pass by pass and replayed as one graph,
+               diff_3d_128 (8 FP32 forward solves + 8 adjoints) ms
 The 256^3 plans are autotuned (tile schedule per pass, bit-identical results)
 before the warm-up; the chosen schedules are reported.
 
@@ -471,6 +472,11 @@ def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
             plan.autotune(rho, phi, E, reps=3)
             ms = time_fn(torch, lambda: plan.solve(rho, phi, E), max(steps, 50), warmup)
             res[method] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms}
+            # the same solve replayed as one captured graph (a one-entry batch)
+            batch = vgf.Batch([plan], graph=True)
+            ms_g = time_fn(torch, lambda: batch.solve([rho], [phi], [E]), max(steps, 50), warmup)
+            res[method + "_graph"] = {"ms_per_solve": ms_g, "solves_per_s": 1e3 / ms_g}
+            batch.close()
             plan.close()
         out[name] = res
     rhs, _ = workloads.diff_3d_128(seed=seed)
