@@ -348,7 +348,10 @@ def launch_kernel_name(name_pattern, prec, schedule, pass_name, idx=0):
 
 def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
     dt = torch.float32 if precision == "f32" else torch.float64
-    plan = vgf.Plan(ch.n, ch.h, method="vgf", precision=precision)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter()
+    plan = vgf.Plan(ch.n, ch.h, method="vgf", precision=precision)  # FP64 precompute, synchronous
+    plan_ms = 1e3 * (time.perf_counter() - t_plan)
     rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
     phi = torch.empty(ch.n, dtype=dt, device="cuda")
     E = torch.empty((3,) + ch.n, dtype=dt, device="cuda")
@@ -377,7 +380,7 @@ def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
     del rho, phi, E
     torch.cuda.empty_cache()
     return {"wall_ms": wall_ms, "event_ms": ev_ms, "passes": passes, "launches": launches,
-            "nsolves": nsolves, "out": out, "L": L, "schedule": list(schedule)}
+            "nsolves": nsolves, "out": out, "L": L, "schedule": list(schedule), "plan_ms": plan_ms}
 
 
 def run_batch(vgf, torch, workloads, steps, warmup, seed):
@@ -700,6 +703,7 @@ def main():
         "fp64": {"value": 1e3 / f64["wall_ms"], "unit": "solves/s", "ms_per_step": f64["wall_ms"],
                  "dtype": "f64"},
         "schedule": {"f32": f32["schedule"], "f64": f64["schedule"]},
+        "plan_ms": {"f32": f32["plan_ms"], "f64": f64["plan_ms"]},
         "roofline": {"bound": "hbm", "kernel": d32["kernel"],
                      "achieved": d32["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d32["achieved"] / HBM_PEAK_GBS, "traffic": d32["traffic"],

@@ -100,6 +100,22 @@ void cis(int64_t t, int64_t n, long double* c, long double* s) {
   *s = sinl(ang);
 }
 
+// cis(t, n) for every residue t mod n, evaluated once (the cosine tables of
+// the precompute index it with products m * j)
+struct CisTable {
+  std::vector<long double> c, s;
+  int64_t n;
+  explicit CisTable(int64_t n_) : c((size_t)n_), s((size_t)n_), n(n_) {
+    for (int64_t t = 0; t < n; ++t) cis(t, n, &c[(size_t)t], &s[(size_t)t]);
+  }
+  void at(int64_t t, long double* cc, long double* ss) const {
+    t %= n;
+    if (t < 0) t += n;
+    *cc = c[(size_t)t];
+    *ss = s[(size_t)t];
+  }
+};
+
 template <typename T> std::vector<cplx<T>> make_twiddles(int64_t P) {
   std::vector<cplx<T>> v((size_t)P);
   for (int64_t e = 0; e < P; ++e) {
@@ -191,10 +207,11 @@ vgf_status precompute(vgf_plan p, hipStream_t s) {
       for (int a = 0; a < d && e == hipSuccess; ++a) {
         const int64_t N = p->n[a], M4 = 4 * p->n[a], Mi = ext[a];
         host_mat.assign((size_t)(Mi * N), 0.0);
+        const CisTable ct(M4);
         for (int64_t m = 0; m < Mi; ++m)
           for (int64_t j = 0; j < N; ++j) {
             long double c, sn;
-            cis(m * j, M4, &c, &sn);
+            ct.at(m * j, &c, &sn);
             if (a == odd_axis) {
               const long double km = 2.0L * kPiL * (long double)m / ((long double)M4 * (long double)p->h[a]);
               host_mat[(size_t)(m * N + j)] =
@@ -225,10 +242,11 @@ vgf_status precompute(vgf_plan p, hipStream_t s) {
       for (int a = 0; a < d && e == hipSuccess; ++a) {
         const int64_t N = p->n[a], P2 = 2 * p->n[a];
         host_mat.assign((size_t)(N * (N + 1)), 0.0);
+        const CisTable ct(P2);
         for (int64_t m = 0; m < N; ++m)
           for (int64_t k = 0; k <= N; ++k) {
             long double c, sn;
-            cis(m * k, P2, &c, &sn);
+            ct.at(m * k, &c, &sn);
             host_mat[(size_t)(m * (N + 1) + k)] =
                 a == odd_axis ? (m == 0 ? 0.0 : (double)(2.0L * sn)) : (double)((m == 0 ? 1.0L : 2.0L) * c);
           }

@@ -6,7 +6,7 @@
 // restricted to offsets |n_a| < N_a is the numerical Green's function. Both
 // that restricted inverse DFT and the 2N DFT of the resulting even kernel are
 // separable cosine transforms of real even data, applied one axis at a time
-// (k_axis_apply) with FP64 cosine tables built on the host.
+// as FP64 matrix-core GEMMs (k_gemm_f64) with cosine tables built on the host.
 //
 // HE (Eq. 3 and the text after it): the kernel h^d G(|n h|) with the
 // singular factor at the origin replaced by 1.
@@ -75,35 +75,83 @@ __global__ void k_he(double* __restrict__ out, int dim, int64_t n0, int64_t n1, 
   out[i] = vol * g;
 }
 
-// Each thread produces JT consecutive outputs j of one (o, i), so every input
-// value it streams is used JT times.
-constexpr int JT = 8;
-__global__ void k_axis_apply(const double* __restrict__ in, double* __restrict__ out,
-                             const double* __restrict__ mat, int64_t outer, int M, int J,
-                             int64_t inner, int64_t total) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int JB = (J + JT - 1) / JT;
-  const int64_t i = t % inner;
-  const int64_t rest = t / inner;
-  const int jb = (int)(rest % JB);
-  const int64_t o = rest / JB;
-  const int j0 = jb * JT;
-  double acc[JT];
+// The axis transforms are dense contractions, out[o][j][i] = sum_m
+// mat[m][j] in[o][m][i], so they run as FP64 GEMMs on the matrix cores:
+// C[b][r][c] = sum_k A[b][r][k] B[b][k][c] with arbitrary element strides.
+// A workgroup of four wavefronts owns a 64 x 64 tile of C (32 x 32 per
+// wavefront, four 16 x 16 MFMA blocks) and walks k in steps of 16 through
+// LDS. v_mfma_f64_16x16x4f64 lane layout: lane l holds A[l%16][l/16],
+// B[l/16][l%16] and D[4v + l/16][l%16] (v = 0..3).
+typedef double d4 __attribute__((ext_vector_type(4)));
+struct GemmF64 {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t a_b, a_r, a_k;
+  int64_t b_b, b_k, b_c;
+  int64_t c_b, c_r, c_c;
+  int64_t R, Cn;
+  int K;
+};
+constexpr int GT = 64;  // rows and columns of C per workgroup
+constexpr int GK = 16;  // k per LDS stage
+
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmF64 g) {
+  __shared__ double As[GK][GT + 1];  // [k][row]
+  __shared__ double Bs[GK][GT + 1];  // [k][column]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int64_t r0 = (int64_t)blockIdx.y * GT, c0 = (int64_t)blockIdx.x * GT;
+  const double* __restrict__ A = g.A + (int64_t)blockIdx.z * g.a_b;
+  const double* __restrict__ B = g.B + (int64_t)blockIdx.z * g.b_b;
+  const bool a_kfast = g.a_k == 1;  // A contiguous along k (else along rows)
+  d4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < JT; ++u) acc[u] = 0.0;
-  const double* src = in + o * (int64_t)M * inner + i;
-  for (int m = 0; m < M; ++m) {
-    const double x = src[(int64_t)m * inner];
-    const double* row = mat + (int64_t)m * J + j0;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int u = 0; u < JT; ++u)
-      if (j0 + u < J) acc[u] = fma(row[u], x, acc[u]);
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < g.K; k0 += GK) {
+#pragma unroll
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int rr = a_kfast ? e / GK : e % GT, kk = a_kfast ? e % GK : e / GT;
+      const int64_t r = r0 + rr;
+      const int k = k0 + kk;
+      As[kk][rr] = (r < g.R && k < g.K) ? A[r * g.a_r + (int64_t)k * g.a_k] : 0.0;
+    }
+#pragma unroll
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int cc = e % GT, kk = e / GT;
+      const int64_t c = c0 + cc;
+      const int k = k0 + kk;
+      Bs[kk][cc] = (c < g.Cn && k < g.K) ? B[(int64_t)k * g.b_k + c * g.b_c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 4) {
+      const int kk = ks + lane / 16;
+      double av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = As[kk][wr * 32 + i * 16 + lane % 16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk][wc * 32 + j * 16 + lane % 16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
   }
-  double* dst = out + o * (int64_t)J * inner + i;
+  double* __restrict__ C = g.C + (int64_t)blockIdx.z * g.c_b;
 #pragma unroll
-  for (int u = 0; u < JT; ++u)
-    if (j0 + u < J) dst[(int64_t)(j0 + u) * inner] = acc[u];
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + wr * 32 + i * 16 + 4 * v + lane / 16;
+        const int64_t c = c0 + wc * 32 + j * 16 + lane % 16;
+        if (r < g.R && c < g.Cn) C[r * g.c_r + c * g.c_c] = acc[i][j][v];
+      }
 }
 
 template <typename T>
@@ -135,11 +183,37 @@ hipError_t launch_he_kernel(double* out, int dim, const int64_t* n, const double
   return hipGetLastError();
 }
 
+// out[o][j][i] = sum_m mat[m][j] in[o][m][i]: per o a GEMM with rows j and
+// columns i when the axis has an inner extent, else one GEMM with rows o and
+// columns j.
 hipError_t launch_axis_apply(const double* in, double* out, const double* mat, int64_t outer,
                              int M, int J, int64_t inner, hipStream_t s) {
-  const int64_t total = outer * ((J + JT - 1) / JT) * inner;
-  hipLaunchKernelGGL(k_axis_apply, dim3(blocks_for(total, 256)), dim3(256), 0, s, in, out, mat,
-                     outer, M, J, inner, total);
+  GemmF64 g{};
+  g.K = M;
+  if (inner > 1) {
+    g.A = mat;  // A[j][m] = mat[m][j]
+    g.a_b = 0; g.a_r = 1; g.a_k = J;
+    g.B = in;   // B[m][i]
+    g.b_b = (int64_t)M * inner; g.b_k = inner; g.b_c = 1;
+    g.C = out;  // C[j][i]
+    g.c_b = (int64_t)J * inner; g.c_r = inner; g.c_c = 1;
+    g.R = J;
+    g.Cn = inner;
+  } else {
+    g.A = in;   // A[o][m]
+    g.a_b = 0; g.a_r = M; g.a_k = 1;
+    g.B = mat;  // B[m][j]
+    g.b_b = 0; g.b_k = J; g.b_c = 1;
+    g.C = out;  // C[o][j]
+    g.c_b = 0; g.c_r = J; g.c_c = 1;
+    g.R = outer;
+    g.Cn = J;
+    outer = 1;
+  }
+  const int64_t gx = (g.Cn + GT - 1) / GT, gy = (g.R + GT - 1) / GT;
+  if (gx > 0x7fffffff || gy > 65535 || outer > 65535) return hipErrorInvalidValue;
+  if (gx == 0 || gy == 0 || outer == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)gx, (unsigned)gy, (unsigned)outer), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
