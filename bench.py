@@ -594,6 +594,80 @@ def oracle_timing(seed):
                     "(diff_3d_128); the 256^3 solve runs with all threads only"}
 
 
+PLAN_TRACE_MD = os.path.join(PROFILES, "vgf_plan_precompute_kernel_trace.md")
+PLAN_GRIDS = ((256, 256, 256), (512, 512))
+
+
+def plan_gemm_model(n):
+    """The FP64 GEMM launches of one VGF plan's precompute, in order:
+    (label, rows x k x columns, flops). Restricted inverse DFT: axis a maps
+    2N_a + 1 samples to N_a; spectrum: N_a to N_a + 1."""
+    d = len(n)
+    out = []
+    for stage, (m_of, j_of) in (("restricted", (lambda N: 2 * N + 1, lambda N: N)),
+                                ("spectrum", (lambda N: N, lambda N: N + 1))):
+        cur = [m_of(N) for N in n]
+        for a in range(d):
+            M, J = m_of(n[a]), j_of(n[a])
+            rest = 1
+            for b in range(d):
+                if b != a:
+                    rest *= cur[b]
+            out.append(("%s axis %d" % (stage, a), "%d x %d x %d" % (J, M, rest), 2 * M * J * rest))
+            cur[a] = J
+    return out
+
+
+def plan_only():
+    """Create each PLAN_GRIDS plan twice (FP32 plans; the precompute is FP64
+    either way) and print the creation wall times."""
+    import torch
+    from paper_2103_08531_amd import vgf
+    torch.cuda.synchronize()
+    out = {}
+    for n in PLAN_GRIDS:
+        h = tuple(2.0 / (x - 1) for x in n)
+        ts = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            p = vgf.Plan(n, h, precision="f32")
+            ts.append(1e3 * (time.perf_counter() - t0))
+            p.close()
+        out["x".join(map(str, n))] = ts
+    print(json.dumps({"plan_ms": out}), flush=True)
+
+
+def write_plan_trace_profile(trace_csv, command):
+    """Durations of the precompute GEMMs from a kernel trace of --plan-only,
+    with each launch's FP64 rate against the 78.6 TFLOP/s MFMA peak."""
+    rows = [r for r in csv.DictReader(open(trace_csv)) if "k_gemm_f64" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    model, keep = [], []
+    for n in PLAN_GRIDS:
+        for rep in range(2):
+            for m in plan_gemm_model(n):
+                model.append(("x".join(map(str, n)),) + m)
+                keep.append(rep == 1)
+    if len(rows) != len(model):
+        raise SystemExit("expected %d GEMM launches, found %d" % (len(model), len(rows)))
+    md = ["# Plan precompute on the matrix cores: FP64 GEMMs of the separable transforms", "",
+          "Kernel trace of plan creation (each grid twice; the second creation of each grid is listed). "
+          "Each launch is one axis of the restricted inverse DFT or of the kernel spectrum as a batched "
+          "FP64 GEMM (k_gemm_f64, v_mfma_f64_16x16x4f64). Flops = 2 x rows x k x columns.", "",
+          "Command:", "", "```", command, "```", "",
+          "| grid | transform | rows x k x columns | GFLOP | us | TFLOP/s | frac of 78.6 |",
+          "|---|---|---|---|---|---|---|"]
+    for (grid, label, shape, flops), r, k in zip(model, rows, keep):
+        if k:
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            md.append("| %s | %s | %s | %.2f | %.1f | %.1f | %.2f |" % (
+                grid, label, shape, flops / 1e9, us, flops / us / 1e6, flops / us / 1e6 / 78.6))
+    md.append("")
+    with open(PLAN_TRACE_MD, "w") as f:
+        f.write("\n".join(md))
+    print(PLAN_TRACE_MD)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -612,10 +686,20 @@ def main():
     ap.add_argument("--digest-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
                     help="write the kernel-trace profile from a rocprofv3 kernel_trace.csv file")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the profile")
+    ap.add_argument("--plan-only", action="store_true",
+                    help="create the 256^3 and 512^2 plans twice each, print their creation times, exit")
+    ap.add_argument("--digest-plan-trace", metavar="TRACE_CSV",
+                    help="write the precompute GEMM profile from a kernel trace of --plan-only")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the oracle's 2N FFT path on every workload (all threads and one), "
                          "print one JSON line and exit (no GPU)")
     args = ap.parse_args()
+    if args.digest_plan_trace:
+        write_plan_trace_profile(args.digest_plan_trace, args.command)
+        return
+    if args.plan_only:
+        plan_only()
+        return
     if args.oracle_timing:
         print(json.dumps(oracle_timing(args.seed)), flush=True)
         return
