@@ -329,6 +329,22 @@ def kernel_bytes(n, prec_bytes):
     return out
 
 
+# vector FMA rate without packed FP32 instructions (which this library does
+# not use): 256 CUs x 64 lanes x 2 flops x 2.4 GHz, in FP32 and in FP64
+VECTOR_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+
+
+def multiply_pass_flops(n):
+    """Conventional flop count of one multiply-pass launch (3D phi + E): per
+    line of the last axis, a forward and two inverse P-point complex
+    transforms at 5 P log2 P each, plus 2 P for the kernel multiply and 2 P
+    for -i k_last."""
+    N0, N1, N2 = n
+    P = 2 * N2
+    lines = (N0 + 1) * 2 * N1
+    return lines * (3 * 5 * P * np.log2(P) + 4 * P)
+
+
 def launch_indices(model):
     """Index of each launch among the launches of its pass (0 = the first)."""
     seen, out = {}, []
@@ -764,8 +780,16 @@ def main():
         tr = None
         if traffic is not None and name in traffic["kernels"]:
             tr = traffic["kernels"][name]["traffic_bytes"]
-        return {"kernel": name, "pass": pname, "launch": k, "achieved": nbytes / (ms * 1e-3) / 1e9,
-                "mean_launch_ms": ms, "algorithmic_bytes_per_launch": nbytes, "traffic": tr}
+        out = {"kernel": name, "pass": pname, "launch": k, "achieved": nbytes / (ms * 1e-3) / 1e9,
+               "mean_launch_ms": ms, "algorithmic_bytes_per_launch": nbytes, "traffic": tr}
+        if pname == "fused":
+            fl = multiply_pass_flops(ch.n)
+            peak = VECTOR_PEAK_TFLOPS[prec]
+            out["alu"] = {"achieved": fl / (ms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                          "frac": fl / (ms * 1e-3) / 1e12 / peak, "flops_per_launch": fl,
+                          "count": "5 P log2 P per P-point complex transform (three per line) + 4 P "
+                                   "for the kernel multiply and -i k; peak: non-packed vector FMA rate"}
+        return out
 
     d32 = dominant(f32, "f32")
     d64 = dominant(f64, "f64")
