@@ -106,7 +106,7 @@ enum {
  *   dim      : 2 or 3.
  *   n[dim]   : points per axis (host array).
  *   h[dim]   : grid spacing per axis, > 0 (host array).
- *   method   : VGF_METHOD_VGF or VGF_METHOD_HE.
+ *   method   : a vgf_method (VGF, or one of the HE variants).
  *   prec     : arithmetic and buffer type of every solve. The kernel spectrum
  *              is always computed in FP64 and, for VGF_F32, rounded to FP32
  *              once; FFT twiddles are FP64 values rounded to the plan type.
@@ -117,7 +117,8 @@ enum {
  *              it the 4N-periodic images reach the box. Ignored for HE.
  *   outputs  : VGF_OUT_PHI | VGF_OUT_E, the fields later solves may return,
  *              optionally | VGF_FIELD_CENTERED or | VGF_FIELD_GRADIENT_KERNEL
- *              (either requires VGF_OUT_E; the latter the VGF method).
+ *              (either requires VGF_OUT_E; the latter the VGF method), and
+ *              optionally | VGF_LAYOUT_AXIS0.
  *   stream   : stream on which the FP64 precompute runs; the call
  *              synchronises it before returning.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, L_WINDOW, OUT_OF_MEMORY, HIP. On
