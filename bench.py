@@ -299,8 +299,8 @@ def launch_model(n, prec_bytes):
     """The launches of one 3D solve (phi + E) in the default layout, in order:
     (pass, kernel name pattern at P = 2N, algorithmic HBM bytes). The
     multiply pass runs along the last axis and writes the spectra of phi and
-    E_2; the axis-1 inverse writes phi and E_1 (from phi), then E_2; the
-    axis-0 complex-to-real pass writes phi and E_0 (from phi), then E_1, then
+    E_2; the axis-1 inverse writes phi and E_1 (from phi) and E_2 in one
+    launch; the axis-0 complex-to-real pass writes phi and E_0 (from phi), then E_1, then
     E_2. Arrays: X1 = [N0+1][N1][N2], X2 = [N0+1][2 N1][N2] complex."""
     N0, N1, N2 = n
     P = 2 * N2
@@ -313,8 +313,7 @@ def launch_model(n, prec_bytes):
         ("r2c", "k_r2c_s<{t}, %d, 1, {v}>" % P, real + x1),
         ("c2c_fwd", "k_c2c_fwd<{t}, %d, 1, {v}>" % P, x1 + x2),
         ("fused", "k_fused_c<{t}, %d>" % P, x2 + spec + 2 * x2),
-        ("c2c_inv", "k_c2c_inv<{t}, %d, 2, {v}>" % P, x2 + 2 * x1),
-        ("c2c_inv", "k_c2c_inv<{t}, %d, 1, {v}>" % P, x2 + x1),
+        ("c2c_inv", "k_c2c_inv<{t}, %d, 3, {v}>" % P, 2 * x2 + 3 * x1),
         ("c2r", "k_c2r_s<{t}, %d, 2, {v}>" % P, x1 + 2 * real),
         ("c2r", "k_c2r_s<{t}, %d, 1, {v}>" % P, x1 + real),
         ("c2r", "k_c2r_s<{t}, %d, 1, {v}>" % P, x1 + real),

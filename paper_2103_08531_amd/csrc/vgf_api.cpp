@@ -629,12 +629,13 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
+    // one launch: phi and E_1 from phi's spectrum, E_2 from its own
     vgf::C2CInvArgs<T> ia{b.y, {b.z, b.z + zfs}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
     if (want_E) {
-      vgf::C2CInvArgs<T> ia2{b.y + g.fs, {b.z + 2 * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 1), ia2, tw(1), s));
+      ia.in2 = b.y + g.fs;
+      ia.out2 = b.z + 2 * zfs;
     }
+    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
     zphi = b.z;
     zf[0] = b.z + zfs;
     zf[1] = b.z + 2 * zfs;
@@ -727,12 +728,13 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
     cplx<T>* zp = b.z;
     cplx<T>* z1 = b.z + zfs;
     cplx<T>* z0 = b.z + 2 * zfs;
+    // one launch: phi and E_1 from phi's spectrum, E_0 from its own
     vgf::C2CInvArgs<T> ia{b.y, {zp, z1}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
-    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
     if (want_E) {
-      vgf::C2CInvArgs<T> ia0{b.y + yfs, {z0, nullptr}, ig, deriv1<T>(p, 1, 0)};
-      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 1), ia0, tw(1), s));
+      ia.in2 = b.y + yfs;
+      ia.out2 = z0;
     }
+    VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
     if (want_phi && want_E) VGF_LAUNCH(kPassC2R, c2r(zp, -1, 0, 2, -1));
     else if (want_phi) VGF_LAUNCH(kPassC2R, c2r(zp, -1, 0, -2, 0));
     else VGF_LAUNCH(kPassC2R, c2r(zp, 2, -1, -2, 0));

@@ -90,6 +90,10 @@ template <typename T> struct C2CInvArgs {
   cplx<T>* out[2];
   StridedGeom g;
   Deriv<T> d;
+  // optional (with d.n == 2): a second input of the same layout, transformed
+  // without a factor into out2 by the same launch
+  const cplx<T>* in2 = nullptr;
+  cplx<T>* out2 = nullptr;
 };
 
 // Geometry of the axis-0 (outermost) fused pass. Forward: one input, outputs

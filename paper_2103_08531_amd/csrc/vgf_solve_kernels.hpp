@@ -450,13 +450,16 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const ColIO co(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_out);
   const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
   const C* __restrict__ src = a.in + e * a.g.es_in + bb * a.g.bs_in;
+  // NOUT = 3: outputs 0 and 1 from `in` (factors d), output 2 from in2
+  // without a factor, in the same launch
+  const C* __restrict__ src2 = NOUT == 3 ? a.in2 + e * a.g.es_in + bb * a.g.bs_in : src;
   typename S0::Regs gin;
   S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
   stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
-    const int code = a.d.code[o];
+    const int code = o < 2 ? a.d.code[o] : 0;
     if (o > 0) {
       __syncthreads();
       // read the column again (from cache) rather than hold it in registers
@@ -464,7 +467,8 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
       // the occupancy its LDS tile allows
       uint32_t z = 0;
       asm volatile("" : "+s"(z));
-      S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r) + z]; });
+      const C* __restrict__ so = o < 2 ? src : src2;
+      S0::template load_first<false>(gin, q, [&](int j, int r) { return so[ci.off<S0::NB>(j, r) + z]; });
     }
     typename S0::Regs g0;
     if (code == 0) {
@@ -486,7 +490,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
     typename SL::Regs gl;
     middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
     if (co.valid) {
-      C* __restrict__ dst = a.out[o] + e * a.g.es_out + bb * a.g.bs_out;
+      C* __restrict__ dst = (o < 2 ? a.out[o] : a.out2) + e * a.g.es_out + bb * a.g.bs_out;
       SL::template store_last<true>(gl, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
     }
   }
@@ -1402,7 +1406,10 @@ hipError_t launch_c2c_inv_v(const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream
   if (bx == 0 || by == 0 || a.d.n == 0) return hipSuccess;
   if (by > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)bx, (unsigned)by);
-  if (a.d.n == 2)
+  if (a.in2 != nullptr && (a.d.n != 2 || a.out2 == nullptr)) return hipErrorInvalidValue;
+  if (a.in2 != nullptr)
+    hipLaunchKernelGGL((k_c2c_inv<T, P, 3, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  else if (a.d.n == 2)
     hipLaunchKernelGGL((k_c2c_inv<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw);
   else
     hipLaunchKernelGGL((k_c2c_inv<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw);
