@@ -300,8 +300,9 @@ def launch_model(n, prec_bytes):
     (pass, kernel name pattern at P = 2N, algorithmic HBM bytes). The
     multiply pass runs along the last axis and writes the spectra of phi and
     E_2; the axis-1 inverse writes phi and E_1 (from phi) and E_2 in one
-    launch; the axis-0 complex-to-real pass writes phi and E_0 (from phi), then E_1, then
-    E_2. Arrays: X1 = [N0+1][N1][N2], X2 = [N0+1][2 N1][N2] complex."""
+    launch; the axis-0 complex-to-real pass writes phi and E_0 (from phi),
+    E_1 and E_2 in one launch. Arrays: X1 = [N0+1][N1][N2],
+    X2 = [N0+1][2 N1][N2] complex."""
     N0, N1, N2 = n
     P = 2 * N2
     rb, cb = prec_bytes, 2 * prec_bytes
@@ -314,9 +315,7 @@ def launch_model(n, prec_bytes):
         ("c2c_fwd", "k_c2c_fwd<{t}, %d, 1, {v}>" % P, x1 + x2),
         ("fused", "k_fused_c<{t}, %d>" % P, x2 + spec + 2 * x2),
         ("c2c_inv", "k_c2c_inv<{t}, %d, 3, {v}>" % P, 2 * x2 + 3 * x1),
-        ("c2r", "k_c2r_s<{t}, %d, 2, {v}>" % P, x1 + 2 * real),
-        ("c2r", "k_c2r_s<{t}, %d, 1, {v}>" % P, x1 + real),
-        ("c2r", "k_c2r_s<{t}, %d, 1, {v}>" % P, x1 + real),
+        ("c2r", "k_c2r_s<{t}, %d, 4, {v}>" % P, 3 * x1 + 4 * real),
     ]
 
 

@@ -236,13 +236,15 @@ enum { VGF_PASS_R2C = 0, VGF_PASS_C2C_FWD = 1, VGF_PASS_FUSED = 2, VGF_PASS_C2C_
        VGF_PASS_C2R = 4, VGF_NUM_PASSES = 5 };
 
 /* Chooses the plan's schedule by measurement: two warm-up solves per
- * variant, then `reps` rounds that each run one solve of (rho, phi, E)
- * (arguments as vgf_solve) per variant, interleaved, with HIP events after
- * every launch on `stream`. For each pass, its first launch and its later
+ * variant, then `reps` rounds that each run, per variant, two solves of
+ * (rho, phi, E) (arguments as vgf_solve), the second timed with HIP events
+ * after every launch on `stream`. For each pass, its first launch and its later
  * launches each take their fastest repetition per variant and keep the
  * default variant unless another is more than 2% faster; a pass launched
- * once gives both bits its first launch's choice. phi / E receive solve
- * results. Synchronises `stream`.
+ * once gives both bits its first launch's choice. A schedule so assembled
+ * is kept only if it also beats the default on the whole solve by 1% (two
+ * more solves per round and candidate). phi / E receive solve results.
+ * Synchronises `stream`.
  * The choice is cached in the process per (grid, precision, outputs), so an
  * identical plan tuned again takes the cached schedule without running.
  * Errors: as vgf_solve, INVALID_ARG for reps <= 0. */

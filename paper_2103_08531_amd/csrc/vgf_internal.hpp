@@ -150,12 +150,16 @@ template <typename T> struct R2CSArgs {
 template <typename T> struct C2RSArgs {
   const cplx<T>* in;
   int64_t in_es;
-  T* out[2];
-  T* const* out_tab[2];
-  int64_t out_off[2];
+  T* out[4];
+  T* const* out_tab[4];
+  int64_t out_off[4];
   int64_t ncols;
   int nentry;
-  Deriv<T> d;     // per output: factor applied before its transform
+  Deriv<T> d;     // outputs 0 .. d.n-1 from `in`, each with its factor
+  // outputs d.n .. d.n+nx-1 from in_x[0 .. nx), without a factor, in the
+  // same launch (inputs laid out like `in`)
+  const cplx<T>* in_x[2];
+  int nx;
 };
 // Lines along the contiguous last axis (length n_last in, 2 n_last transformed)
 // of the arrays [H0][P1][n_last] (3D) or [H0][n_last] (2D), H0 = n0 + 1; line

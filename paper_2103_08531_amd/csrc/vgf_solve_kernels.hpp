@@ -1076,13 +1076,14 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
-    const int code = a.d.code[o];
+    const bool own = o < a.d.n;  // from `in` with its factor, else from in_x
+    const int code = own ? a.d.code[o] : 0;
     if (o > 0) {
       // read the columns again (from cache) rather than hold them in
       // registers through the previous output's transform
       uint32_t z = 0;
       asm volatile("" : "+s"(z));
-      load(in + z);
+      load((own ? in : a.in_x[o - a.d.n] + e * a.in_es + 2 * (int64_t)ci.col) + z);
     }
     __syncthreads();  // twiddles staged / the previous output's reads are done
     // Z[k] = X[k] + i Y[k], Z[P-k] = conj X[k] + i conj Y[k]; the imaginary
@@ -1513,10 +1514,13 @@ hipError_t launch_c2r_s_v(const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s
   if (bx == 0 || a.nentry == 0 || a.d.n == 0) return hipSuccess;
   if (a.nentry > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)bx, (unsigned)a.nentry);
-  if (a.d.n == 2)
-    hipLaunchKernelGGL((k_c2r_s<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw);
-  else
-    hipLaunchKernelGGL((k_c2r_s<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw);
+  if (a.d.n < 1 || a.d.n > 2 || a.nx < 0 || a.nx > 2) return hipErrorInvalidValue;
+  switch (a.d.n + a.nx) {
+    case 1: hipLaunchKernelGGL((k_c2r_s<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw); break;
+    case 2: hipLaunchKernelGGL((k_c2r_s<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw); break;
+    case 3: hipLaunchKernelGGL((k_c2r_s<T, P, 3, V>), grid, dim3(TL::NT), 0, s, a, tw); break;
+    default: hipLaunchKernelGGL((k_c2r_s<T, P, 4, V>), grid, dim3(TL::NT), 0, s, a, tw); break;
+  }
   return hipGetLastError();
 }
 
