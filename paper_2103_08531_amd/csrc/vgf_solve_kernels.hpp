@@ -443,32 +443,36 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   constexpr int NSTG = n_stages(P);
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
-  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  const int tid = threadIdx.x, l0 = tid % NL, q0 = tid / NL;
   using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
   using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
-  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_in);
-  const ColIO co(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, a.g.ncols, a.g.ls_out);
+  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l0, a.g.ncols, a.g.ls_in);
+  const ColIO co(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l0, a.g.ncols, a.g.ls_out);
   const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
   const C* __restrict__ src = a.in + e * a.g.es_in + bb * a.g.bs_in;
   // NOUT = 3: outputs 0 and 1 from `in` (factors d), output 2 from in2
   // without a factor, in the same launch
   const C* __restrict__ src2 = NOUT == 3 ? a.in2 + e * a.g.es_in + bb * a.g.bs_in : src;
   typename S0::Regs gin;
-  S0::template load_first<false>(gin, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
+  S0::template load_first<false>(gin, q0, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
   stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int code = o < 2 ? a.d.code[o] : 0;
-    if (o > 0) {
-      __syncthreads();
-      // read the column again (from cache) rather than hold it in registers
-      // through the previous output's transform: that keeps the kernel at
-      // the occupancy its LDS tile allows
+    // this output's copies of the thread's line and position: addresses are
+    // recomputed per output instead of held through every transform
+    int l = l0, q = q0;
+    if (o > 0) asm volatile("" : "+v"(l), "+v"(q));
+    if (o > 0) __syncthreads();  // the previous output's LDS reads are done
+    if (o == 2) {
+      // output 2 reads its own input here, not at the start (the laundered
+      // offset keeps the compiler from hoisting the loads): output 1 reuses
+      // the column held in registers, which the per-output copies of l and q
+      // leave room for
       uint32_t z = 0;
       asm volatile("" : "+s"(z));
-      const C* __restrict__ so = o < 2 ? src : src2;
-      S0::template load_first<false>(gin, q, [&](int j, int r) { return so[ci.off<S0::NB>(j, r) + z]; });
+      S0::template load_first<false>(gin, q, [&](int j, int r) { return src2[ci.off<S0::NB>(j, r) + z]; });
     }
     typename S0::Regs g0;
     if (code == 0) {
@@ -1055,16 +1059,20 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
   __shared__ C lds[P * LP];
   __shared__ C twl[P];
-  const int tid = threadIdx.x, l = tid % NL, q = tid / NL;
+  const int tid = threadIdx.x, l0 = tid % NL, q0 = tid / NL;
   const int e = (int)blockIdx.y;
   const int64_t npairs = a.ncols / 2;
-  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l, npairs, npairs);
+  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l0, npairs, npairs);
   const C* __restrict__ in = a.in + e * a.in_es + 2 * (int64_t)ci.col;
+  // FP64 holds the columns of `in` through the outputs taken from it
+  // (measured faster); in FP32 holding them takes more registers than two
+  // workgroups per CU allow, and reading them again from cache is faster
+  constexpr bool HOLD = sizeof(T) == 8;
   C xs[NSLOT], ys[NSLOT];
   auto load = [&](const C* __restrict__ src) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
-      const int k = q + NQ * s;
+      const int k = q0 + NQ * s;
       xs[s] = ys[s] = C{T(0), T(0)};
       if (k >= H) continue;
       xs[s] = src[k * a.ncols];
@@ -1078,14 +1086,20 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   for (int o = 0; o < NOUT; ++o) {
     const bool own = o < a.d.n;  // from `in` with its factor, else from in_x
     const int code = own ? a.d.code[o] : 0;
-    if (o > 0) {
-      // read the columns again (from cache) rather than hold them in
-      // registers through the previous output's transform
+    if (o > 0 && !(HOLD && own)) {
+      // read the columns (again, from cache, for an output of `in`) here
+      // rather than hold them in registers through the previous output's
+      // transform
       uint32_t z = 0;
       asm volatile("" : "+s"(z));
       load((own ? in : a.in_x[o - a.d.n] + e * a.in_es + 2 * (int64_t)ci.col) + z);
     }
     __syncthreads();  // twiddles staged / the previous output's reads are done
+    // this output's copies of the thread's line and position: the compiler
+    // then recomputes the LDS addresses per output instead of holding one
+    // set in registers through every transform
+    int l = l0, q = q0;
+    if (o > 0) asm volatile("" : "+v"(l), "+v"(q));
     // Z[k] = X[k] + i Y[k], Z[P-k] = conj X[k] + i conj Y[k]; the imaginary
     // parts of X, Y at k = 0 and k = N are dropped (real by symmetry)
 #pragma unroll
