@@ -79,14 +79,14 @@ typedef enum { VGF_F64 = 0, VGF_F32 = 1 } vgf_precision;
  *     one-sided (-3, 4, -1)/(2h) on the first and (3, -4, 1)/(2h) on the last
  *     plane of each axis -- instead of Fourier differentiation. This is the
  *     "Finite Diff" field of the comparison figures (Sec. III.A); Fourier
- *     differentiation is the default. Not accepted by vgf_batch_create. */
+ *     differentiation is the default. */
 /*   VGF_FIELD_GRADIENT_KERNEL : (VGF method, with VGF_OUT_E) E_a = w_a * rho
  *     with w_a the gradient kernel: the inverse DFT on the 4N-oversampled grid
  *     of -i k_a times the windowed spectrum, restricted like the potential's
  *     kernel (Sec. II, applied to the field; the other reading of Sec. III.A's
  *     "multiplying by the wavevector"). The plan stores dim more kernel
  *     spectra; the axis-0 pass multiplies every field by its own spectrum and
- *     inverts each field separately. Not accepted by vgf_batch_create. */
+ *     inverts each field separately. */
 /*   VGF_LAYOUT_AXIS0 : run the spectral multiply inside the axis-0 pass
  *     (real-to-complex along the last axis, strided axis-0 multiply pass)
  *     instead of the default (real-to-complex along axis 0, multiply pass
@@ -174,9 +174,13 @@ vgf_status vgf_solve_batched(const vgf_plan* plans, int count, const void* const
 typedef struct vgf_batch_s* vgf_batch;
 enum { VGF_BATCH_GRAPH = 1u };
 
-/* plans[0..count): the plan of each entry (non-NULL, count >= 1, not created
- * with VGF_FIELD_CENTERED or VGF_FIELD_GRADIENT_KERNEL). flags: 0 or VGF_BATCH_GRAPH. Allocates the group workspaces (VGF_ERR_OUT_OF_MEMORY
- * beyond VGF_MAX_WORKSPACE). Enqueues nothing. */
+/* plans[0..count): the plan of each entry (non-NULL, count >= 1; any method,
+ * precision, layout and field mode). A group of a VGF_FIELD_CENTERED plan
+ * runs its passes for phi over all entries, then the difference field over
+ * all entries in one more launch (phi goes to the entry's workspace when
+ * only E is asked for). flags: 0 or VGF_BATCH_GRAPH. Allocates the group
+ * workspaces (VGF_ERR_OUT_OF_MEMORY beyond VGF_MAX_WORKSPACE). Enqueues
+ * nothing. */
 vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, unsigned flags);
 
 /* Solves every entry i: rho[i] -> phi[i], E[i], with the layout, dtype and

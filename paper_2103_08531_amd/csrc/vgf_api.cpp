@@ -501,9 +501,9 @@ vgf::GradSpec<T> grad_spec(vgf_plan p) {
   return sp;
 }
 
-// Forward solve with gradient kernels (one entry): no derivative factors
-// after the axis-0 pass, which multiplies each requested field by its own
-// spectrum; every field is then inverted on its own.
+// Forward solve with gradient kernels: no derivative factors after the
+// axis-0 pass, which multiplies each requested field by its own spectrum;
+// every field is then inverted on its own. Each launch covers all entries.
 template <typename T>
 vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks, const int* sched,
                               hipEvent_t* mark_events, int* mark_tags) {
@@ -519,17 +519,26 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
   if (en.want_phi) g.fields[g.nf++] = 0;
   if (en.want_E)
     for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
-  T* outs[4];
-  for (int f = 0; f < g.nf; ++f) outs[f] = g.fields[f] == 0 ? en.phi : en.E + (g.fields[f] - 1) * vol;
+  g.nentry = en.count;
+  g.in_es = g.out_es = en.es;
   Marks mk(p, s, marks, mark_events, mark_tags);
-  const int64_t lpe = d == 3 ? N0 * N1 : N0;
-  vgf::R2CArgs<T> ra{{en.rho, nullptr}, b.x1, lpe, Hs, deriv1<T>(p, d - 1, 0)};
+  const int64_t lpe = d == 3 ? N0 * N1 : N0;  // contiguous lines per entry
+  vgf::R2CArgs<T> ra{};
+  ra.nlines = lpe * en.count;
   ra.lpe = lpe;
+  ra.hs = Hs;
+  ra.out = b.x1;
+  ra.out_es = en.es;
+  ra.d = deriv1<T>(p, d - 1, 0);
+  if (en.rho_tab) ra.in_tab[0] = en.rho_tab;
+  else ra.in[0] = en.rho;
   VGF_LAUNCH(kPassR2C, vgf::launch_r2c<T>((int)p->P[d - 1], ra, tw(d - 1), s));
   const cplx<T>* fused_in = b.x1;
   if (d == 3) {
     const int64_t P1 = p->P[1];
-    const vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
+    vgf::StridedGeom fg{H, Hs, Hs, N1 * Hs, P1 * Hs, (int)N0};
+    fg.nentry = en.count;
+    fg.es_in = fg.es_out = en.es;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
     VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     fused_in = b.x2;
@@ -542,7 +551,9 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
   int64_t last_fs = g.out_fs;
   if (d == 3) {
     const int64_t P1 = p->P[1], zfs = N0 * N1 * Hs;
-    const vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
+    vgf::StridedGeom ig{H, Hs, Hs, P1 * Hs, N1 * Hs, (int)N0};
+    ig.nentry = en.count;
+    ig.es_in = ig.es_out = en.es;
     for (int f = 0; f < g.nf; ++f) {
       vgf::C2CInvArgs<T> ia{b.y + f * g.out_fs, {b.z + f * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
       VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, f), ia, tw(1), s));
@@ -551,8 +562,14 @@ vgf_status enqueue_solve_grad(vgf_plan p, const Entries<T>& en, hipStream_t s, b
     last_fs = zfs;
   }
   for (int f = 0; f < g.nf; ++f) {
-    vgf::C2RArgs<T> ca{lastin + f * last_fs, {outs[f], nullptr}, lpe, Hs, deriv1<T>(p, d - 1, 0)};
+    vgf::C2RArgs<T> ca{};
+    ca.in = lastin + f * last_fs;
+    ca.in_es = en.es;
+    ca.nlines = lpe * en.count;
     ca.lpe = lpe;
+    ca.hs = Hs;
+    ca.d = deriv1<T>(p, d - 1, 0);
+    c2r_out(ca, 0, en, g.fields[f] - 1, vol);
     VGF_LAUNCH(kPassC2R, vgf::launch_c2r<T>((int)p->P[d - 1], ca, tw(d - 1), s));
   }
   return VGF_OK;
@@ -1612,7 +1629,17 @@ vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool 
   en.E_tab = want_E ? (T* const*)(g.tab + 2 * c) : nullptr;
   en.want_phi = want_phi;
   en.want_E = want_E;
-  return enqueue_solve<T>(p, en, s, false, sched ? sched : g.schedule, marks, tags);
+  if (!(p->fd && want_E)) return enqueue_solve<T>(p, en, s, false, sched ? sched : g.schedule, marks, tags);
+  // finite-difference field: phi of every entry (the tables hold the
+  // workspace arrays when phi is not wanted), then E = -D phi over all entries
+  en.phi_tab = (T* const*)(g.tab + c);
+  en.want_phi = true;
+  en.E_tab = nullptr;
+  en.want_E = false;
+  vgf_status st = enqueue_solve<T>(p, en, s, false, sched ? sched : g.schedule, marks, tags);
+  if (st != VGF_OK) return st;
+  return hip_status(p, vgf::launch_fd_field_entries<T>((const T* const*)(g.tab + c), (T* const*)(g.tab + 2 * c),
+                                                       c, fd_geom(p), s));
 }
 
 vgf_status batch_enqueue_groups(vgf_batch b, bool want_phi, bool want_E, bool branches, hipStream_t s) {
@@ -1680,7 +1707,11 @@ vgf_status batch_set_tables(vgf_batch b, const void* const* rho, void* const* ph
       if (st != VGF_OK) return st;
       if (want_phi != (phi && phi[i]) || want_E != (E && E[i])) return VGF_ERR_INVALID_ARG;
       ptrs[k + j] = const_cast<void*>(rho[i]);
-      ptrs[k + c + j] = want_phi ? phi[i] : nullptr;
+      // a finite-difference group always has a phi per entry: the field is
+      // taken from it (the entry's workspace array when phi is not wanted)
+      ptrs[k + c + j] = want_phi ? phi[i]
+                        : g.plan->fd ? (char*)g.ws + j * g.plan->ws_bytes + g.plan->off_phi
+                                     : nullptr;
       ptrs[k + 2 * c + j] = want_E ? E[i] : nullptr;
     }
     k += 3 * c;
@@ -1715,7 +1746,7 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
   *out = nullptr;
   if (count <= 0 || !plans || (flags & ~(unsigned)VGF_BATCH_GRAPH)) return VGF_ERR_INVALID_ARG;
   for (int i = 0; i < count; ++i)
-    if (!plans[i] || plans[i]->fd || plans[i]->gradk) return VGF_ERR_INVALID_ARG;
+    if (!plans[i]) return VGF_ERR_INVALID_ARG;
   vgf_batch b = new (std::nothrow) vgf_batch_s();
   if (!b) return VGF_ERR_OUT_OF_MEMORY;
   b->count = count;
@@ -1780,9 +1811,11 @@ vgf_status vgf_batch_autotune(vgf_batch b, const void* const* rho, void* const* 
   if (!b || reps <= 0) return VGF_ERR_INVALID_ARG;
   vgf_status st = batch_set_tables(b, rho, phi, E, stream);
   if (st != VGF_OK) return st;
-  const bool want_phi = phi != nullptr, want_E = E != nullptr;
   for (auto& g : b->groups) {
     const int count = (int)g.idx.size();
+    // a finite-difference group tunes the passes of phi (the field is a
+    // separate kernel; the tables hold a phi for every entry)
+    const bool want_phi = phi != nullptr || g.plan->fd, want_E = E != nullptr && !g.plan->fd;
     auto run = [&](const int* sched, hipEvent_t* ev, int* tg) -> vgf_status {
       vgf_status r = g.plan->prec == VGF_F32
                          ? batch_group_enqueue<float>(g, want_phi, want_E, stream, sched, ev, tg)

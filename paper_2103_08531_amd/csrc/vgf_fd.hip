@@ -35,9 +35,8 @@ __device__ __forceinline__ T dt_col(const T* __restrict__ y, int64_t base, int64
 }
 
 template <typename T>
-__global__ void k_fd_field(const T* __restrict__ phi, T* __restrict__ E, FdGeom g) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.total) return;
+__device__ __forceinline__ void fd_field_at(const T* __restrict__ phi, T* __restrict__ E, const FdGeom& g,
+                                            int64_t i) {
   int64_t rem = i;
   int idx[3];
   for (int a = g.dim - 1; a >= 0; --a) {
@@ -46,6 +45,21 @@ __global__ void k_fd_field(const T* __restrict__ phi, T* __restrict__ E, FdGeom 
   }
   for (int a = 0; a < g.dim; ++a)
     E[a * g.total + i] = -d_row(phi, i, g.stride[a], idx[a], g.n[a]) * (T)g.inv2h[a];
+}
+
+template <typename T>
+__global__ void k_fd_field(const T* __restrict__ phi, T* __restrict__ E, FdGeom g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.total) return;
+  fd_field_at(phi, E, g, i);
+}
+
+// entry blockIdx.y of a batch group
+template <typename T>
+__global__ void k_fd_field_entries(const T* const* __restrict__ phi_tab, T* const* __restrict__ E_tab, FdGeom g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.total) return;
+  fd_field_at(phi_tab[blockIdx.y], E_tab[blockIdx.y], g, i);
 }
 
 template <typename T>
@@ -76,6 +90,16 @@ hipError_t launch_fd_field(const T* phi, T* E, const FdGeom& g, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_fd_field_entries(const T* const* phi_tab, T* const* E_tab, int nentry, const FdGeom& g,
+                                   hipStream_t s) {
+  if (g.total == 0 || nentry == 0) return hipSuccess;
+  if (nentry < 0 || nentry > 65535) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)((g.total + 255) / 256);
+  hipLaunchKernelGGL(k_fd_field_entries<T>, dim3(blocks, (unsigned)nentry), dim3(256), 0, s, phi_tab, E_tab, g);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_fd_adjoint(const T* g_phi, const T* g_E, T* out, const FdGeom& g, hipStream_t s) {
   if (g.total == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((g.total + 255) / 256);
@@ -85,6 +109,10 @@ hipError_t launch_fd_adjoint(const T* g_phi, const T* g_E, T* out, const FdGeom&
 
 template hipError_t launch_fd_field<float>(const float*, float*, const FdGeom&, hipStream_t);
 template hipError_t launch_fd_field<double>(const double*, double*, const FdGeom&, hipStream_t);
+template hipError_t launch_fd_field_entries<float>(const float* const*, float* const*, int, const FdGeom&,
+                                                   hipStream_t);
+template hipError_t launch_fd_field_entries<double>(const double* const*, double* const*, int, const FdGeom&,
+                                                    hipStream_t);
 template hipError_t launch_fd_adjoint<float>(const float*, const float*, float*, const FdGeom&, hipStream_t);
 template hipError_t launch_fd_adjoint<double>(const double*, const double*, double*, const FdGeom&,
                                               hipStream_t);

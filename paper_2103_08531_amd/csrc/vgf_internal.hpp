@@ -207,6 +207,11 @@ struct FdGeom {
 // E[a] = -(D_a phi), E planar [dim][total]
 template <typename T>
 hipError_t launch_fd_field(const T* phi, T* E, const FdGeom& g, hipStream_t s);
+// the same for the nentry entries of a batch group (blockIdx.y): phi of
+// entry e is phi_tab[e], its field E_tab[e] (device pointer tables)
+template <typename T>
+hipError_t launch_fd_field_entries(const T* const* phi_tab, T* const* E_tab, int nentry, const FdGeom& g,
+                                   hipStream_t s);
 // out = g_phi - sum_a D_a^T g_E[a]  (g_phi may be null: zero)
 template <typename T>
 hipError_t launch_fd_adjoint(const T* g_phi, const T* g_E, T* out, const FdGeom& g, hipStream_t s);

@@ -824,7 +824,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
 // the octants hold T_a for frequency indices in [0, N]. Field 0 multiplies
 // by the kernel spectrum, field 1 + a by -i s_a T_a, s_a = -1 where the
 // axis-a index exceeds N_a (axis 0: the row of the line; axis 1 in 3D: the
-// column's k1; the last axis is a half spectrum). One tile per workgroup.
+// column's k1; the last axis is a half spectrum). One tile per workgroup;
+// the forward launch covers the entries of a batch group along blockIdx.y.
 // ---------------------------------------------------------------------------
 template <typename T, int R, int NB>
 __device__ __forceinline__ bool row_above_nyquist(int j, int r) {
@@ -874,6 +875,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   const FusedCol<T> fc(g, (int64_t)blockIdx.x * NL + l);
   const ColIO& cio = fc.io;
   const bool neg1 = g.dim == 3 && (int)(cio.col / (uint32_t)g.hs) > g.n1;
+  const int e = (int)blockIdx.y;  // entry
+  const C* __restrict__ src = in + e * g.in_es;
   stage_twiddles_both<C, P, NT>(twl, tw, tid);
   using S0 = Stage<T, P, NT, NL, LP, -1, 0>;
   using SL = Stage<T, P, NT, NL, LP, -1, NSTG - 1>;
@@ -882,7 +885,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
 
   typename S0::Regs g0;
-  S0::template load_first<true>(g0, q, [&](int j, int r) { return in[cio.off<S0::NB>(j, r)]; });
+  S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
   S0::template butterflies<true>(g0, q);
   S0::lds_out(g0, lds, l, q);
   __syncthreads();
@@ -898,7 +901,7 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
     typename ISL::Regs o;
     middle_and_last<T, P, NT, NL, LP, 1>(o, lds, tw_inverse<P>(twl), l, q);
     if (cio.valid) {
-      C* __restrict__ dst = out + fi * g.out_fs;
+      C* __restrict__ dst = out + e * g.out_es + fi * g.out_fs;
       ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
     }
   }
@@ -1494,14 +1497,16 @@ template <typename T, int P>
 hipError_t launch_fused_grad_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
                                const GradSpec<T>& sp, const cplx<T>* tw, hipStream_t s) {
   using TL = Tile<T, P>;
-  if (g.nf == 0) return hipSuccess;
-  if (g.nentry != 1 || g.nf > 4) return hipErrorInvalidValue;
+  if (g.nf == 0 || g.nentry == 0) return hipSuccess;
+  if (g.nf > 4 || g.nentry < 0 || g.nentry > 65535) return hipErrorInvalidValue;
+  if (adjoint && g.nentry != 1) return hipErrorInvalidValue;  // the adjoint runs one entry per launch
   const int64_t bx = (g.ncols + TL::NL - 1) / TL::NL;
   if (bx == 0) return hipSuccess;
   if (adjoint)
     hipLaunchKernelGGL((k_fused_grad_adj<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, sp, tw);
   else
-    hipLaunchKernelGGL((k_fused_grad<T, P>), dim3((unsigned)bx), dim3(TL::NT), 0, s, in, out, g, sp, tw);
+    hipLaunchKernelGGL((k_fused_grad<T, P>), dim3((unsigned)bx, (unsigned)g.nentry), dim3(TL::NT), 0, s, in,
+                       out, g, sp, tw);
   return hipGetLastError();
 }
 

@@ -168,6 +168,7 @@ class Plan:
             flags |= FIELD_GRADIENT_KERNEL
         if layout not in ("contiguous", "axis0"):
             raise ValueError("layout must be 'contiguous' or 'axis0'")
+        self.layout = layout
         if layout == "axis0":
             flags |= LAYOUT_AXIS0
         n_arr = (C.c_int64 * self.dim)(*self.n)

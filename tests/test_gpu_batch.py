@@ -89,6 +89,65 @@ def test_batch_equals_single_solves(graph):
         p.close()
 
 
+# plans of every field mode and layout in one batch: centred differences,
+# gradient kernels (axis-0 layout), the axis-0 layout with Fourier fields, and
+# the default; 3D and 2D, both precisions, groups of 1 and 2 entries
+MODE_SPECS = [((24, 32, 16), "f64", "centered", "contiguous"), ((48, 64), "f32", "centered", "contiguous"),
+              ((32, 32, 32), "f32", "gradient_kernel", "axis0"), ((64, 48), "f64", "gradient_kernel", "axis0"),
+              ((24, 24, 24), "f64", "fourier", "axis0"), ((32, 32, 32), "f32", "fourier", "contiguous")]
+MODE_ENTRIES = [0, 1, 2, 3, 4, 5, 2, 0, 3]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_field_modes_equal_single_solves(graph):
+    """Batches of finite-difference and gradient-kernel plans (mixed with
+    the other layouts) give every entry exactly what vgf_solve gives, for
+    phi + E, E only and phi only, across new pointers and after autotuning."""
+    torch, vgf = need_gpu()
+    plans = []
+    for n, prec, field, layout in MODE_SPECS:
+        h = tuple(2.0 / (x - 1) for x in n)
+        plans.append(vgf.Plan(n, h, precision=prec, field=field, layout=layout))
+    ents = [plans[i] for i in MODE_ENTRIES]
+    batch = vgf.Batch(ents, graph=graph)
+    assert batch.groups == len(MODE_SPECS)
+
+    def run(seed, want_phi, want_E, tune=False):
+        rhos = [torch.from_numpy(W.random_field(seed + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
+        phis = [torch.full(p.n, float("nan"), dtype=p.dtype, device="cuda") for p in ents]
+        Es = [torch.full((p.dim,) + p.n, float("nan"), dtype=p.dtype, device="cuda") for p in ents]
+        args = (rhos, phis if want_phi else None, Es if want_E else None)
+        if tune:
+            say("  schedules after autotune: %s" % (batch.autotune(*args, reps=2),))
+        batch.solve(*args)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between solves
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i, p in enumerate(ents):
+            p1, E1 = p.solve(rhos[i], want_phi=want_phi, want_E=want_E)
+            torch.cuda.synchronize()
+            tag = (seed, want_phi, want_E, i, p.n, p.field, p.layout)
+            if want_phi:
+                assert torch.equal(phis[i], p1), tag
+            else:
+                assert torch.isnan(phis[i]).all(), tag
+            if want_E:
+                assert torch.equal(Es[i], E1), tag
+            else:
+                assert torch.isnan(Es[i]).all(), tag
+        say("  seed %d phi=%s E=%s: all %d entries bit-identical to vgf_solve" % (seed, want_phi, want_E, len(ents)))
+
+    say("field-mode batch: %d entries, %d groups, graph=%s" % (len(ents), batch.groups, graph))
+    run(0, True, True)
+    run(10, True, True)
+    run(20, False, True)
+    run(30, True, False)
+    run(40, True, True, tune=True)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_partial_outputs():
     torch, vgf = need_gpu()
     keys = KEYS[:3]
