@@ -121,6 +121,10 @@ enum {
  *              optionally | VGF_LAYOUT_AXIS0.
  *   stream   : stream on which the FP64 precompute runs; the call
  *              synchronises it before returning.
+ * Environment, read here: VGF_STREAM_MIN_BYTES (default 33554432): forward
+ * solves in the default layout whose input (rho of all entries of a launch)
+ * has at least this many bytes use non-temporal loads and stores in their
+ * middle passes; results are identical either way, only speed differs.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, L_WINDOW, OUT_OF_MEMORY, HIP. On
  * error *out is set to NULL and nothing is leaked. */
 vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const double* h,

@@ -66,6 +66,7 @@ struct vgf_plan_s {
   double* specg64 = nullptr;     // [dim][prod(n+1)] their spectra T_a, FP64, unscaled
   void* specg = nullptr;         // [dim][prod(n+1)] plan type, scaled by 1/prod(P)
   size_t off_phi = 0;            // real phi array in the workspace (fd only)
+  int64_t stream_min = 0;        // input bytes per launch from which solves stream (stream_min_env)
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
 
@@ -125,6 +126,17 @@ template <typename T> std::vector<cplx<T>> make_twiddles(int64_t P) {
     v[(size_t)e].y = (T)(double)(-s);
   }
   return v;
+}
+
+// Input bytes (rho of all entries of a launch) from which the forward solve
+// uses non-temporal loads and stores in its middle passes: the arrays are
+// then several times the caches. Read once per plan.
+int64_t stream_min_env() {
+  const char* e = std::getenv("VGF_STREAM_MIN_BYTES");
+  if (!e || !*e) return (int64_t)32 << 20;
+  char* end = nullptr;
+  const long long v = std::strtoll(e, &end, 10);
+  return v < 0 ? 0 : (int64_t)v;
 }
 
 size_t max_workspace_env() {
@@ -606,6 +618,11 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
             (cplx<T>*)(base + p->off_z)};
   auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
   Marks mk(p, s, marks, mark_events, mark_tags);
+  // large arrays: non-temporal input loads of the axis-0 R2C, stores of the
+  // axis-1 forward, loads and stores of the multiply pass and of the axis-1
+  // inverse (the combination measured fastest; the axis-0 C2R, whose FP32
+  // form reads phi's spectrum twice, stays plain)
+  const bool nt = vol * en.count * (int64_t)sizeof(T) >= p->stream_min;
   vgf::R2CSArgs<T> ra{};
   if (en.rho_tab) ra.in_tab[0] = en.rho_tab;
   else ra.in[0] = en.rho;
@@ -614,6 +631,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   ra.ncols = vol / N0;
   ra.nentry = en.count;
   ra.d = deriv1<T>(p, 0, 0);
+  ra.nt_load = nt;
   VGF_LAUNCH(kPassR2C, vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(sched, kPassR2C, 0), ra, tw(0), s));
   const cplx<T>* fin = b.x1;
   vgf::FusedCGeom<T> g{};
@@ -627,11 +645,13 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   g.fs = g.lpe * NL;
   g.ks = (T)wavenumber_step(p, d - 1);
   g.nf = want_E ? 2 : 1;
+  g.nt = nt;
   if (d == 3) {
     const int64_t P1 = p->P[1], N2 = NL;
     vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
     fg.nentry = en.count;
     fg.es_in = fg.es_out = en.es;
+    fg.nt_store = nt;
     vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
     VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     fin = b.x2;
@@ -646,6 +666,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
+    ig.nt_load = ig.nt_store = nt;
     // one launch: phi and E_1 from phi's spectrum, E_2 from its own
     vgf::C2CInvArgs<T> ia{b.y, {b.z, b.z + zfs}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
     if (want_E) {
@@ -1258,6 +1279,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->nf_max = ((outputs & VGF_OUT_PHI) ? 1 : 0) + ((outputs & VGF_OUT_E) ? dim : 0);
   p->fd = (outputs & VGF_FIELD_CENTERED) != 0;
   p->gradk = (outputs & VGF_FIELD_GRADIENT_KERNEL) != 0;
+  p->stream_min = stream_min_env();
   // the multiply pass runs along the contiguous axis unless asked otherwise;
   // gradient-kernel plans use the axis-0 layout
   p->contig = !p->gradk && !(outputs & VGF_LAYOUT_AXIS0);

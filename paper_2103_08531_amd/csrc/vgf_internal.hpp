@@ -35,6 +35,8 @@ struct StridedGeom {
   int nbatch;
   int nentry = 1;
   int64_t es_in = 0, es_out = 0;
+  // non-temporal loads of the input / stores of the outputs (large arrays)
+  bool nt_load = false, nt_store = false;
 };
 
 // Spectral derivative factors along the transformed axis. A forward pass
@@ -146,6 +148,7 @@ template <typename T> struct R2CSArgs {
   int64_t ncols;  // real columns per row
   int nentry;
   Deriv<T> d;     // per input term: factor applied after its transform
+  bool nt_load = false;  // non-temporal loads of the inputs (large arrays)
 };
 template <typename T> struct C2RSArgs {
   const cplx<T>* in;
@@ -174,6 +177,7 @@ template <typename T> struct FusedCGeom {
   T ks;               // 2 pi / (P_last h_last)
   int nf;             // forward: 1 (phi) or 2 (phi, E_last); adjoint: inputs
   int fields[2];      // adjoint: per input 0 or 1 (+i k_last)
+  bool nt = false;    // forward: non-temporal loads and stores (large arrays)
 };
 template <typename T>
 hipError_t launch_r2c_s(int P, int variant, const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s);

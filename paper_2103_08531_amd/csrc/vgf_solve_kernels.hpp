@@ -39,6 +39,33 @@
 
 namespace vgf {
 
+// Loads and stores with the non-temporal hint. The solve passes read and
+// write each array once; when the arrays are much larger than the caches
+// (the plan decides per solve from the input bytes), the hint keeps those
+// lines from displacing cached data that is still reused (measured faster at
+// 256^3; small grids, whose arrays stay cached between passes, are faster
+// with plain accesses).
+__device__ __forceinline__ float2 load_nt(const float2* p) {
+  typedef float V __attribute__((ext_vector_type(2)));
+  const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return make_float2(w.x, w.y);
+}
+__device__ __forceinline__ double2 load_nt(const double2* p) {
+  typedef double V __attribute__((ext_vector_type(2)));
+  const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return make_double2(w.x, w.y);
+}
+__device__ __forceinline__ void store_nt(float2* p, float2 v) {
+  typedef float V __attribute__((ext_vector_type(2)));
+  const V w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
+}
+__device__ __forceinline__ void store_nt(double2* p, double2 v) {
+  typedef double V __attribute__((ext_vector_type(2)));
+  const V w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
+}
+
 // Tile shape for length P: NL lines (contiguous columns) per workgroup, 16
 // complex values per thread, LDS tile <= 64 KiB.
 template <typename T, int P, int NL_FORCE = 0> struct Tile {
@@ -428,7 +455,10 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   }
   if (!co.valid) return;
   C* __restrict__ dst = a.out + e * a.g.es_out + bb * a.g.bs_out;
-  SL::template store_last<false>(acc, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
+  if (a.g.nt_store)
+    SL::template store_last<false>(acc, q, [&](int j, int r, C v) { store_nt(&dst[co.off<SL::NB>(j, r)], v); });
+  else
+    SL::template store_last<false>(acc, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
 }
 
 // ---------------------------------------------------------------------------
@@ -454,7 +484,10 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   // without a factor, in the same launch
   const C* __restrict__ src2 = NOUT == 3 ? a.in2 + e * a.g.es_in + bb * a.g.bs_in : src;
   typename S0::Regs gin;
-  S0::template load_first<false>(gin, q0, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
+  if (a.g.nt_load)
+    S0::template load_first<false>(gin, q0, [&](int j, int r) { return load_nt(&src[ci.off<S0::NB>(j, r)]); });
+  else
+    S0::template load_first<false>(gin, q0, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
   stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
@@ -472,7 +505,10 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
       // leave room for
       uint32_t z = 0;
       asm volatile("" : "+s"(z));
-      S0::template load_first<false>(gin, q, [&](int j, int r) { return src2[ci.off<S0::NB>(j, r) + z]; });
+      if (a.g.nt_load)
+        S0::template load_first<false>(gin, q, [&](int j, int r) { return load_nt(&src2[ci.off<S0::NB>(j, r) + z]); });
+      else
+        S0::template load_first<false>(gin, q, [&](int j, int r) { return src2[ci.off<S0::NB>(j, r) + z]; });
     }
     typename S0::Regs g0;
     if (code == 0) {
@@ -495,7 +531,10 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
     middle_and_last<T, P, NT, NL, LP, 1>(gl, lds, twl, l, q);
     if (co.valid) {
       C* __restrict__ dst = (o < 2 ? a.out[o] : a.out2) + e * a.g.es_out + bb * a.g.bs_out;
-      SL::template store_last<true>(gl, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
+      if (a.g.nt_store)
+        SL::template store_last<true>(gl, q, [&](int j, int r, C v) { store_nt(&dst[co.off<SL::NB>(j, r)], v); });
+      else
+        SL::template store_last<true>(gl, q, [&](int j, int r, C v) { dst[co.off<SL::NB>(j, r)] = v; });
     }
   }
 }
@@ -1007,7 +1046,10 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
     const int code = a.d.code[term];
     if (term > 0) __syncthreads();  // the previous term's reads of the tile are done
     typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
+    if (a.nt_load)
+      S0::template load_first<true>(g0, q, [&](int j, int r) { return load_nt(&src[ci.off<S0::NB>(j, r)]); });
+    else
+      S0::template load_first<true>(g0, q, [&](int j, int r) { return src[ci.off<S0::NB>(j, r)]; });
     S0::template butterflies<true>(g0, q);
     S0::lds_out(g0, lds, l, q);
     __syncthreads();
@@ -1218,7 +1260,10 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   typename S0::Regs x;
   auto load_input = [&](bool ok) {
     const C* __restrict__ src = ok ? in + wk.e * g.in_es + ((int64_t)wk.k0 * wk.p1 + wk.k1) * N : in;
-    S0::template load_first<true>(x, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+    if (g.nt)
+      S0::template load_first<true>(x, q, [&](int j, int r) { return load_nt(&src[S0::in_pos(j, r)]); });
+    else
+      S0::template load_first<true>(x, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
   };
   bool valid = line < g.nlines;
   for (int it = 0; it < gpw; ++it) {
@@ -1265,7 +1310,10 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
       if (store) {
         C* __restrict__ d = dst + fi * g.fs;
-        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
+        if (g.nt)
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
+        else
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
       }
     }
   }

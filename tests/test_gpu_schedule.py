@@ -72,6 +72,62 @@ def test_every_schedule_is_bit_identical(n, prec, layout):
     plan.close()
 
 
+def _plan_env(vgf, n, prec, stream_min):
+    """A plan created with VGF_STREAM_MIN_BYTES = stream_min (read at creation)."""
+    import os
+    old = os.environ.get("VGF_STREAM_MIN_BYTES")
+    os.environ["VGF_STREAM_MIN_BYTES"] = str(stream_min)
+    try:
+        return vgf.Plan(n, tuple(2.0 / (x - 1) for x in n), precision=prec)
+    finally:
+        if old is None:
+            del os.environ["VGF_STREAM_MIN_BYTES"]
+        else:
+            os.environ["VGF_STREAM_MIN_BYTES"] = old
+
+
+STREAM_CASES = [((32, 32, 32), "f32"), ((24, 16, 32), "f64"), ((64, 48), "f64"), ((128, 128), "f32"),
+                ((48, 64, 24), "f32")]
+
+
+@pytest.mark.parametrize("n,prec", STREAM_CASES)
+def test_streaming_accesses_are_bit_identical(n, prec):
+    """Non-temporal loads and stores (forced on for a small grid) change no
+    bit of any output, with either tile schedule and every output set, for
+    single solves and for a batch of the plan."""
+    torch, vgf = need_gpu()
+    on = _plan_env(vgf, n, prec, 0)
+    off = _plan_env(vgf, n, prec, 1 << 62)
+    rho = torch.from_numpy(W.random_field(8, n)).to("cuda", on.dtype)
+    half = tuple(3 if i in _tunable(len(n), "contiguous") else 0 for i in range(5))
+    for sched in ((0,) * 5, half):
+        on.schedule = sched
+        off.schedule = sched
+        for wp, wE in ((True, True), (False, True), (True, False)):
+            a = on.solve(rho, want_phi=wp, want_E=wE)
+            b = off.solve(rho, want_phi=wp, want_E=wE)
+            torch.cuda.synchronize()
+            for x, y in zip(a, b):
+                assert (x is None) == (y is None)
+                if x is not None:
+                    assert torch.equal(x, y), (n, prec, sched, wp, wE)
+    rhos = [torch.from_numpy(W.random_field(20 + i, n)).to("cuda", on.dtype) for i in range(3)]
+    outs = {}
+    for name, plan in (("on", on), ("off", off)):
+        batch = vgf.Batch([plan] * 3, graph=False)
+        phis = [torch.empty(n, dtype=plan.dtype, device="cuda") for _ in range(3)]
+        Es = [torch.empty((len(n),) + n, dtype=plan.dtype, device="cuda") for _ in range(3)]
+        batch.solve(rhos, phis, Es)
+        torch.cuda.synchronize()
+        outs[name] = (phis, Es)
+        batch.close()
+    for i in range(3):
+        assert torch.equal(outs["on"][0][i], outs["off"][0][i]) and torch.equal(outs["on"][1][i], outs["off"][1][i])
+    say("%s %s: streaming and plain accesses bit-identical (solve, 2 schedules, 3 output sets, batch)" % (n, prec))
+    on.close()
+    off.close()
+
+
 def test_plan_autotune_is_cached_and_exact():
     torch, vgf = need_gpu()
     n = (128, 128, 128)
