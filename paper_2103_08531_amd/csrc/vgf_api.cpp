@@ -132,10 +132,12 @@ template <typename T> std::vector<cplx<T>> make_twiddles(int64_t P) {
 // uses non-temporal loads and stores in its middle passes: the arrays are
 // then several times the caches. Read once per plan.
 int64_t stream_min_env() {
+  constexpr int64_t kDefault = (int64_t)32 << 20;
   const char* e = std::getenv("VGF_STREAM_MIN_BYTES");
-  if (!e || !*e) return (int64_t)32 << 20;
+  if (!e || !*e) return kDefault;
   char* end = nullptr;
   const long long v = std::strtoll(e, &end, 10);
+  if (end == e) return kDefault;  // not a number
   return v < 0 ? 0 : (int64_t)v;
 }
 
@@ -937,8 +939,10 @@ template <class Run>
 vgf_status tune_cached(vgf_plan p, bool want_phi, bool want_E, int count, int reps, hipStream_t s, Run run,
                        int* sched_out, hipError_t* herr) {
   // the pass structure depends on the outputs and on the field mode
+  // and on whether the solve streams (non-temporal accesses)
+  const int64_t in_bytes = prod(p->n, p->dim) * count * (p->prec == VGF_F32 ? 4 : 8);
   const int outs = (want_phi ? 1 : 0) | (want_E ? 2 : 0) | (p->fd ? 4 : 0) | (p->gradk ? 8 : 0) |
-                   (p->contig ? 16 : 0);
+                   (p->contig ? 16 : 0) | (in_bytes >= p->stream_min ? 32 : 0);
   TuneKey key{(int)p->prec, p->dim, outs, count, {p->n[0], p->n[1], p->dim == 3 ? p->n[2] : 0}};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

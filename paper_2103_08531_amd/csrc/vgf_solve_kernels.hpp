@@ -5,28 +5,29 @@
 //
 // The factor -i k_a of E_a only involves axis a, so it commutes with the
 // transforms along the other axes. Each pass therefore applies the
-// derivative of its own axis: the axis-0 pass produces the spectra of phi and
-// of E_0 only, the axis-1 inverse produces E_1 from phi's spectrum, and the
-// final complex-to-real pass produces E_2 (3D) from phi's spectrum. Forward
-// passes of the adjoint do the mirror image: they sum their inputs after
+// derivative of its own axis, and the number of arrays grows only as the
+// passes that derive a field from phi's spectrum are reached. Forward passes
+// of the adjoint do the mirror image: they sum their inputs after
 // multiplying by +i k of their own axis.
 //
-//   k_r2c      pruned real-to-complex transforms along the last (contiguous)
-//              axis: N reals per line -> N+1 complex (the zero half of the
-//              padded line is never read); sums up to two inputs.
-//   k_c2c_fwd  strided forward transform along a middle axis (3D axis 1),
-//              pruned input; sums up to two inputs.
-//   k_fused    along axis 0: pruned forward transform, multiplication by the
-//              real kernel spectrum (phi) and by -i k_0 times it (E_0), and a
-//              pruned inverse per output; the forward spectrum never leaves
-//              registers.
-//   k_fused_adj  the adjoint of k_fused.
-//   k_c2c_inv  strided inverse transform along a middle axis, pruned output;
-//              up to two outputs from one input.
-//   k_c2r      inverse complex-to-real transform along the last axis keeping
-//              the first N outputs of the 2N line; up to two outputs.
-// Pairs of real lines travel as one complex line (re, im) through r2c/c2r.
-// FFT twiddles are staged in LDS once per workgroup.
+// Default layout (multiply pass along the contiguous last axis):
+//   k_r2c_s    pruned real-to-complex transforms along axis 0 (strided), two
+//              adjacent real columns as one complex column.
+//   k_c2c_fwd  strided forward transform along axis 1 (3D), pruned input;
+//              sums up to two inputs.
+//   k_fused_c  one wavefront per last-axis line: pruned forward transform,
+//              multiplication by the real kernel spectrum (phi) and by -i k
+//              of the last axis (E_last), a pruned inverse per output.
+//   k_c2c_inv  strided inverse along axis 1, pruned output: phi and E_1 from
+//              phi's spectrum (held in registers between the two), E_last
+//              from its own spectrum, in one launch.
+//   k_c2r_s    complex-to-real along axis 0 keeping the first N outputs: phi
+//              and E_0 from phi's spectrum, the other fields from theirs.
+// Axis-0 layout (and gradient-kernel fields): k_r2c / k_c2r along the last
+// axis (a wavefront per pair of real lines), k_fused / k_fused_grad along
+// axis 0 (strided), and the same axis-1 kernels.
+// FFT twiddles are staged in LDS once per workgroup. Large solves use
+// non-temporal loads and stores in the middle passes (load_nt / store_nt).
 #pragma once
 #include "vgf_fft.hpp"
 #include "vgf_internal.hpp"
