@@ -67,6 +67,26 @@ __device__ __forceinline__ void store_nt(double2* p, double2 v) {
   __builtin_nontemporal_store(w, reinterpret_cast<V*>(p));
 }
 
+// The two complex values of a pair of adjacent real columns, adjacent in
+// memory (16-byte aligned in FP32): one 16-byte access per lane in FP32, so
+// every load or store instruction of a wavefront covers whole cache lines.
+__device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void load_pair(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
+}
+__device__ __forceinline__ void store_pair(float2* p, float2 a, float2 b) {
+  *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void store_pair(double2* p, double2 a, double2 b) {
+  p[0] = a;
+  p[1] = b;
+}
+
 // Tile shape for length P: NL lines (contiguous columns) per workgroup, 16
 // complex values per thread, LDS tile <= 64 KiB.
 template <typename T, int P, int NL_FORCE = 0> struct Tile {
@@ -1087,8 +1107,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   for (int s = 0; s < NSLOT; ++s) {
     const int k = q + NQ * s;
     if (k >= H) continue;
-    out[k * a.ncols] = acc_a[s];
-    out[k * a.ncols + 1] = acc_b[s];
+    store_pair(out + k * a.ncols, acc_a[s], acc_b[s]);
   }
 }
 
@@ -1121,8 +1140,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
       const int k = q0 + NQ * s;
       xs[s] = ys[s] = C{T(0), T(0)};
       if (k >= H) continue;
-      xs[s] = src[k * a.ncols];
-      ys[s] = src[k * a.ncols + 1];
+      load_pair(src + k * a.ncols, xs[s], ys[s]);
     }
   };
   load(in);
