@@ -30,7 +30,9 @@ Printed JSON line (one, rank 0):
                schedules, in ms per batch and solves/s
   other_workloads  gaussian_3d_32 and mixture_2d_512 (FP64, VGF and HE)
                solves/s, launched pass by pass and replayed as one graph,
-               diff_3d_128 (8 FP32 forward solves + 8 adjoints) ms
+               diff_3d_128 (8 FP32 forward solves + 8 adjoints) ms, and
+               variants_256: the beam_3d_256 input through every method,
+               field mode and layout, and a rectangular grid, FP32, phi + E
 The 256^3 plans are autotuned (tile schedule per pass, bit-identical results)
 before the warm-up; the chosen schedules are reported.
 
@@ -520,6 +522,41 @@ def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
     return out
 
 
+def run_variants(vgf, torch, ch, rho64, steps, warmup):
+    """The comparison variants at the headline size, FP32, phi + E, each on
+    its own autotuned plan: the HE methods (same passes, another kernel
+    spectrum), the finite-difference and gradient-kernel fields, the axis-0
+    layout, and a rectangular grid (256 x 128 x 192 points, spacing 2/255 on
+    every axis, the beam's leading block of points)."""
+    rho = torch.from_numpy(rho64).to("cuda", torch.float32)
+    cases = [("vgf", {}), ("vgf_axis0_layout", {"layout": "axis0"}), ("he", {"method": "he"}),
+             ("he_nearby", {"method": "he_nearby"}), ("he_cellavg", {"method": "he_cellavg"}),
+             ("vgf_fd_field", {"field": "centered"}), ("vgf_gradient_kernel", {"field": "gradient_kernel"})]
+    out = {"grid": list(ch.n), "precision": "f32", "outputs": "phi+E"}
+
+    def timed(plan, r):
+        phi = torch.empty(plan.n, dtype=torch.float32, device="cuda")
+        E = torch.empty((plan.dim,) + plan.n, dtype=torch.float32, device="cuda")
+        plan.autotune(r, phi, E, reps=3)
+        ms = time_fn(torch, lambda: plan.solve(r, phi, E), steps, warmup)
+        return {"ms_per_solve": ms, "solves_per_s": 1e3 / ms}
+
+    for name, kw in cases:
+        args = {"method": "vgf", "precision": "f32"}
+        args.update(kw)
+        plan = vgf.Plan(ch.n, ch.h, **args)
+        out[name] = timed(plan, rho)
+        plan.close()
+    n_r = (256, 128, 192)
+    rho_r = rho[:n_r[0], :n_r[1], :n_r[2]].contiguous()
+    plan = vgf.Plan(n_r, ch.h, method="vgf", precision="f32")
+    out["vgf_rectangular"] = dict(timed(plan, rho_r), grid=list(n_r))
+    plan.close()
+    del rho, rho_r
+    torch.cuda.empty_cache()
+    return out
+
+
 def rel_l2(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
 
@@ -759,6 +796,7 @@ def main():
     others = None
     if not args.no_batch:
         others = run_small_configs(vgf, torch, workloads, args.steps, args.warmup, args.seed)
+        others["variants_256"] = run_variants(vgf, torch, ch, rho64, args.steps, args.warmup)
         print("[bench] other workloads: %s" % json.dumps(others), file=sys.stderr, flush=True)
     batch = None
     if not args.no_batch:
