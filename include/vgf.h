@@ -199,6 +199,21 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
 vgf_status vgf_batch_solve(vgf_batch batch, const void* const* rho, void* const* phi, void* const* E,
                            hipStream_t stream);
 
+/* Adjoint of every entry i: g_rho[i] = K^T g_phi[i] + sum_a K_a^T g_E[i][a],
+ * with the arguments and rules of vgf_solve_adjoint for the entry's plan.
+ * g_rho holds a non-NULL buffer for every entry; g_phi (or g_E) is NULL
+ * (that cotangent is zero for every entry) or holds a non-NULL buffer for
+ * every entry; at least one of them is non-NULL (VGF_ERR_INVALID_ARG
+ * otherwise; VGF_ERR_NOT_REQUESTED for a cotangent of an output the entry's
+ * plan was not created for). Groups of default-layout plans with Fourier
+ * fields run each pass as one launch over all of their entries; the other
+ * groups run one vgf_solve_adjoint per entry (on the plan's own workspace).
+ * Always direct launches on `stream` (a captured graph replays solves only);
+ * stream-ordered and asynchronous; nothing is enqueued when an argument is
+ * invalid. Results equal vgf_solve_adjoint's bit for bit. */
+vgf_status vgf_batch_adjoint(vgf_batch batch, const void* const* g_phi, const void* const* g_E,
+                             void* const* g_rho, hipStream_t stream);
+
 /* Tunes every group's schedule as vgf_plan_autotune does, with the group's
  * entry count per launch (a schedule that suits one grid alone may not suit
  * many at once), on the caller's buffers (arguments as vgf_batch_solve;

@@ -1057,28 +1057,57 @@ vgf_status adjoint_grad_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hi
 
 // Adjoint in the contiguous-multiply layout: the mirror image of
 // enqueue_solve_c (forward passes sum their inputs with +i k of their axis).
+// The cotangents of the entries one adjoint launch covers: direct pointers
+// (one entry, the plan workspace) or device tables of per-entry pointers
+// with workspaces es elements apart (a batch group).
+template <typename T> struct AdjEntries {
+  int count = 1;
+  char* ws = nullptr;
+  int64_t es = 0;
+  const T* g_phi = nullptr;
+  const T* g_E = nullptr;
+  T* g_rho = nullptr;
+  const T* const* g_phi_tab = nullptr;
+  const T* const* g_E_tab = nullptr;
+  T* const* g_rho_tab = nullptr;
+  bool has_phi = false, has_E = false;
+};
+
 template <typename T>
-vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+vgf_status adjoint_c_entries(vgf_plan p, const AdjEntries<T>& en, const int* sched, hipStream_t s) {
   const int d = p->dim;
   const int64_t N0 = p->n[0], N1 = p->n[1], H0 = N0 + 1, NL = p->n[d - 1];
   const int64_t vol = prod(p->n, d);
-  Bufs<T> b = bufs<T>(p);
+  char* base = en.ws;
+  Bufs<T> b{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2), (cplx<T>*)(base + p->off_y),
+            (cplx<T>*)(base + p->off_z)};
   auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
-  const int* sched = p->schedule;
   const int64_t lpe = d == 3 ? H0 * p->P[1] : H0;
   const int64_t fs = lpe * NL;             // field stride of Y
   const int64_t zfs = H0 * N1 * (d == 3 ? NL : 1);  // field stride of Z (3D)
-  // axis 0: A = R2C(g_phi) + i k_0 R2C(g_E0); the other fields plain
+  // axis 0: A = R2C(g_phi) + i k_0 R2C(g_E0); the other fields plain.
+  // Input term: g_phi (field < 0) or field `field` of g_E.
   int nr2c = 0;  // launches of the r2c kernel so far
-  auto r2c = [&](cplx<T>* out, const T* in0, int code0, const T* in1, int code1) -> hipError_t {
+  auto r2c = [&](cplx<T>* out, int f0, int code0, int f1, int code1, bool t0, bool t1) -> hipError_t {
     vgf::R2CSArgs<T> ra{};
     ra.out = out;
+    ra.out_es = en.es;
     ra.ncols = vol / N0;
-    ra.nentry = 1;
+    ra.nentry = en.count;
     ra.d.ks = (T)wavenumber_step(p, 0);
     ra.d.n = 0;
-    if (in0) { ra.in[ra.d.n] = in0; ra.d.code[ra.d.n++] = code0; }
-    if (in1) { ra.in[ra.d.n] = in1; ra.d.code[ra.d.n++] = code1; }
+    auto term = [&](int f, int code) {
+      const int t = ra.d.n++;
+      ra.d.code[t] = code;
+      if (en.count == 1 && !en.g_phi_tab && !en.g_E_tab) {
+        ra.in[t] = f < 0 ? en.g_phi : en.g_E + f * vol;
+      } else {
+        ra.in_tab[t] = f < 0 ? en.g_phi_tab : en.g_E_tab;
+        ra.in_off[t] = f < 0 ? 0 : f * vol;
+      }
+    };
+    if (t0) term(f0, code0);
+    if (t1) term(f1, code1);
     return vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(sched, kPassR2C, nr2c++), ra, tw(0), s);
   };
   vgf::FusedCGeom<T> g{};
@@ -1087,7 +1116,8 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
   g.n1 = (int)N1;
   g.n_last = (int)NL;
   g.lpe = lpe;
-  g.nlines = lpe;
+  g.nlines = lpe * en.count;
+  g.in_es = g.out_es = en.es;
   g.fs = fs;
   g.ks = (T)wavenumber_step(p, d - 1);
   g.nf = 0;
@@ -1096,41 +1126,59 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
     cplx<T>* za = b.z;
     cplx<T>* zb1 = b.z + zfs;
     cplx<T>* zb2 = b.z + 2 * zfs;
-    VGF_RUN(r2c(za, g_phi, 0, g_E, 1));
-    if (g_E) {
-      VGF_RUN(r2c(zb1, g_E + vol, 0, nullptr, 0));
-      VGF_RUN(r2c(zb2, g_E + 2 * vol, 0, nullptr, 0));
+    VGF_RUN(r2c(za, -1, 0, 0, 1, en.has_phi, en.has_E));
+    if (en.has_E) {
+      VGF_RUN(r2c(zb1, 1, 0, 0, 0, true, false));
+      VGF_RUN(r2c(zb2, 2, 0, 0, 0, true, false));
     }
-    const vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
-    vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, g_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
+    vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
+    fg.nentry = en.count;
+    fg.es_in = fg.es_out = en.es;
+    vgf::C2CFwdArgs<T> fa{{za, zb1}, b.y, fg, en.has_E ? deriv2<T>(p, 1, 0, 1) : deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     g.fields[g.nf++] = 0;
-    if (g_E) {
+    if (en.has_E) {
       vgf::C2CFwdArgs<T> f2{{zb2, nullptr}, b.y + fs, fg, deriv1<T>(p, 1, 0)};
       VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 1), f2, tw(1), s));
       g.fields[g.nf++] = 1;
     }
     VGF_RUN(vgf::launch_fused_c<T>((int)p->P[2], true, b.y, b.x2, g, (const T*)p->spec, tw(2), s));
-    const vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
+    vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
+    ig.nentry = en.count;
+    ig.es_in = ig.es_out = en.es;
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
   } else {
-    VGF_RUN(r2c(b.y, g_phi, 0, g_E, 1));
+    VGF_RUN(r2c(b.y, -1, 0, 0, 1, en.has_phi, en.has_E));
     g.fields[g.nf++] = 0;
-    if (g_E) {
-      VGF_RUN(r2c(b.y + fs, g_E + vol, 0, nullptr, 0));
+    if (en.has_E) {
+      VGF_RUN(r2c(b.y + fs, 1, 0, 0, 0, true, false));
       g.fields[g.nf++] = 1;
     }
     VGF_RUN(vgf::launch_fused_c<T>((int)p->P[1], true, b.y, b.x1, g, (const T*)p->spec, tw(1), s));
   }
   vgf::C2RSArgs<T> ca{};
   ca.in = b.x1;
-  ca.out[0] = g_rho;
+  ca.in_es = en.es;
+  if (en.g_rho_tab) ca.out_tab[0] = en.g_rho_tab;
+  else ca.out[0] = en.g_rho;
   ca.ncols = vol / N0;
-  ca.nentry = 1;
+  ca.nentry = en.count;
   ca.d = deriv1<T>(p, 0, 0);
   VGF_RUN(vgf::launch_c2r_s<T>((int)p->P[0], launch_variant(sched, kPassC2R, 0), ca, tw(0), s));
   return VGF_OK;
+}
+
+template <typename T>
+vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  AdjEntries<T> en;
+  en.ws = (char*)p->ws;
+  en.g_phi = g_phi;
+  en.g_E = g_E;
+  en.g_rho = g_rho;
+  en.has_phi = g_phi != nullptr;
+  en.has_E = g_E != nullptr;
+  return adjoint_c_entries<T>(p, en, p->schedule, s);
 }
 
 template <typename T>
@@ -1668,6 +1716,24 @@ vgf_status batch_group_enqueue(const vgf_batch_s::Group& g, bool want_phi, bool 
                                                        c, fd_geom(p), s));
 }
 
+// Adjoint of every entry of a default-layout group with Fourier fields in
+// one launch per pass (tables: [g_rho | g_phi | g_E]).
+template <typename T>
+vgf_status batch_group_adjoint(const vgf_batch_s::Group& g, bool has_phi, bool has_E, hipStream_t s) {
+  const vgf_plan p = g.plan;
+  const int c = (int)g.idx.size();
+  AdjEntries<T> en;
+  en.count = c;
+  en.ws = (char*)g.ws;
+  en.es = (int64_t)(p->ws_bytes / sizeof(cplx<T>));
+  en.g_rho_tab = (T* const*)g.tab;
+  en.g_phi_tab = has_phi ? (const T* const*)(g.tab + c) : nullptr;
+  en.g_E_tab = has_E ? (const T* const*)(g.tab + 2 * c) : nullptr;
+  en.has_phi = has_phi;
+  en.has_E = has_E;
+  return adjoint_c_entries<T>(p, en, g.schedule, s);
+}
+
 vgf_status batch_enqueue_groups(vgf_batch b, bool want_phi, bool want_E, bool branches, hipStream_t s) {
   for (auto& g : b->groups) {
     hipStream_t gs = branches ? g.st : s;
@@ -1716,6 +1782,8 @@ vgf_status batch_capture(vgf_batch b, bool want_phi, bool want_E) {
   return VGF_OK;
 }
 
+vgf_status batch_write_tables(vgf_batch b, const std::vector<void*>& ptrs, hipStream_t stream);
+
 // Validates one call's pointers and refreshes the device pointer tables on
 // `stream` when they differ from the last ones written.
 vgf_status batch_set_tables(vgf_batch b, const void* const* rho, void* const* phi, void* const* E,
@@ -1742,8 +1810,14 @@ vgf_status batch_set_tables(vgf_batch b, const void* const* rho, void* const* ph
     }
     k += 3 * c;
   }
+  return batch_write_tables(b, ptrs, stream);
+}
+
+// Writes the per-group pointer tables ([3][count] per group, group order)
+// on `stream` unless they already hold `ptrs`.
+vgf_status batch_write_tables(vgf_batch b, const std::vector<void*>& ptrs, hipStream_t stream) {
   if (b->tab_valid && ptrs == b->cur) return VGF_OK;
-  k = 0;
+  size_t k = 0;
   for (auto& g : b->groups) {
     const size_t c3 = 3 * g.idx.size();
     for (size_t o = 0; o < c3; o += vgf::PtrChunk::kMax) {
@@ -1830,6 +1904,49 @@ vgf_status vgf_batch_solve(vgf_batch b, const void* const* rho, void* const* phi
     if (st != VGF_OK) return st;
   }
   return batch_hip(b, hipGraphLaunch(b->exec, stream));
+}
+
+vgf_status vgf_batch_adjoint(vgf_batch b, const void* const* g_phi, const void* const* g_E, void* const* g_rho,
+                             hipStream_t stream) {
+  if (!b || !g_rho || (!g_phi && !g_E)) return VGF_ERR_INVALID_ARG;
+  // validate every entry before anything is enqueued
+  for (auto& g : b->groups)
+    for (int i : g.idx) {
+      if (!g_rho[i] || (g_phi && !g_phi[i]) || (g_E && !g_E[i])) return VGF_ERR_INVALID_ARG;
+      if (g_phi && !(g.plan->outputs & VGF_OUT_PHI)) return VGF_ERR_NOT_REQUESTED;
+      if (g_E && !(g.plan->outputs & VGF_OUT_E)) return VGF_ERR_NOT_REQUESTED;
+    }
+  std::vector<void*> ptrs((size_t)3 * b->count, nullptr);
+  size_t k = 0;
+  for (auto& g : b->groups) {
+    const size_t c = g.idx.size();
+    for (size_t j = 0; j < c; ++j) {
+      const int i = g.idx[j];
+      ptrs[k + j] = g_rho[i];
+      ptrs[k + c + j] = g_phi ? const_cast<void*>(g_phi[i]) : nullptr;
+      ptrs[k + 2 * c + j] = g_E ? const_cast<void*>(g_E[i]) : nullptr;
+    }
+    k += 3 * c;
+  }
+  vgf_status st = batch_write_tables(b, ptrs, stream);
+  if (st != VGF_OK) return st;
+  for (auto& g : b->groups) {
+    const vgf_plan p = g.plan;
+    if (p->contig && !p->fd && !p->gradk) {
+      st = p->prec == VGF_F32 ? batch_group_adjoint<float>(g, g_phi != nullptr, g_E != nullptr, stream)
+                              : batch_group_adjoint<double>(g, g_phi != nullptr, g_E != nullptr, stream);
+      if (st == VGF_ERR_HIP) b->last_err = p->last_err;
+      if (st != VGF_OK) return st;
+      continue;
+    }
+    // other plans: one adjoint per entry on the plan's own workspace
+    for (int i : g.idx) {
+      st = vgf_solve_adjoint(p, g_phi ? g_phi[i] : nullptr, g_E ? g_E[i] : nullptr, g_rho[i], stream);
+      if (st == VGF_ERR_HIP) b->last_err = p->last_err;
+      if (st != VGF_OK) return st;
+    }
+  }
+  return VGF_OK;
 }
 
 vgf_status vgf_batch_autotune(vgf_batch b, const void* const* rho, void* const* phi, void* const* E,

@@ -28,7 +28,7 @@ EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batch
            "vgf_batch_create", "vgf_batch_solve", "vgf_batch_workspace_bytes", "vgf_batch_groups",
            "vgf_batch_hip_error", "vgf_batch_destroy", "vgf_plan_autotune", "vgf_plan_get_schedule",
            "vgf_plan_set_schedule", "vgf_batch_autotune", "vgf_batch_get_schedule",
-           "vgf_plan_get_gradient_kernel", "vgf_plan_get_gradient_spectrum"]
+           "vgf_plan_get_gradient_kernel", "vgf_plan_get_gradient_spectrum", "vgf_batch_adjoint"]
 BATCH_GRAPH = 1
 PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused", "c2c_inv", "c2r"],
               2: ["r2c", "fused", "c2r"]}
@@ -86,6 +86,8 @@ def lib():
         L.vgf_batch_create.argtypes = [C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_uint]
         L.vgf_batch_solve.restype = C.c_int
         L.vgf_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
+        L.vgf_batch_adjoint.restype = C.c_int
+        L.vgf_batch_adjoint.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
         L.vgf_batch_workspace_bytes.restype = C.c_int
         L.vgf_batch_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.vgf_batch_groups.restype = C.c_int
@@ -394,6 +396,33 @@ class Batch:
         ph = (VP * count)(*[x.data_ptr() for x in phis]) if phis is not None else None
         ee = (VP * count)(*[x.data_ptr() for x in Es]) if Es is not None else None
         return rh, ph, ee
+
+    def adjoint(self, g_phis=None, g_Es=None, g_rhos=None, stream=None):
+        """Adjoint of every entry (vgf_batch_adjoint): g_phis / g_Es are lists
+        of cotangents (None: zero for every entry); returns g_rhos (allocated
+        when not given)."""
+        torch = _torch()
+        count = len(self.plans)
+        if g_phis is None and g_Es is None:
+            raise ValueError("adjoint needs g_phis or g_Es")
+        if g_rhos is None:
+            ref = g_phis if g_phis is not None else g_Es
+            g_rhos = [torch.empty(p.n, dtype=p.dtype, device=ref[i].device) for i, p in enumerate(self.plans)]
+        if len(g_rhos) != count or (g_phis is not None and len(g_phis) != count) or (
+                g_Es is not None and len(g_Es) != count):
+            raise ValueError("one g_rho (and g_phi / g_E) per entry")
+        for i, p in enumerate(self.plans):
+            p._check_tensor(g_rhos[i], p.n, "g_rho[%d]" % i)
+            if g_phis is not None:
+                p._check_tensor(g_phis[i], p.n, "g_phi[%d]" % i)
+            if g_Es is not None:
+                p._check_tensor(g_Es[i], (p.dim,) + p.n, "g_E[%d]" % i)
+        VP = C.c_void_p
+        gr = (VP * count)(*[x.data_ptr() for x in g_rhos])
+        gp = (VP * count)(*[x.data_ptr() for x in g_phis]) if g_phis is not None else None
+        ge = (VP * count)(*[x.data_ptr() for x in g_Es]) if g_Es is not None else None
+        _check(lib().vgf_batch_adjoint(self.handle, gp, ge, gr, _stream(stream)), "vgf_batch_adjoint")
+        return g_rhos
 
     def autotune(self, rhos, phis=None, Es=None, reps=3, stream=None):
         """Tune every group's tile schedule on these buffers; returns the schedules."""

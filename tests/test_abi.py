@@ -115,6 +115,7 @@ def test_null_batch_calls_fail_cleanly(V):
     assert L.vgf_batch_create(C.byref(handle), plans, 2, 4) == -1  # unknown flag
     ptrs = (VP * 1)(None)
     assert L.vgf_batch_solve(None, ptrs, ptrs, None, None) == -1
+    assert L.vgf_batch_adjoint(None, ptrs, None, ptrs, None) == -1
     s = C.c_size_t()
     assert L.vgf_batch_workspace_bytes(None, C.byref(s)) == -1
     assert L.vgf_batch_groups(None) == 0

@@ -148,6 +148,49 @@ def test_batch_field_modes_equal_single_solves(graph):
         p.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_adjoint_equals_single_adjoints(graph):
+    """vgf_batch_adjoint gives every entry exactly what vgf_solve_adjoint
+    gives (batched groups and per-entry groups alike), for both cotangents
+    and each alone; a solve of the same batch afterwards (its graph replayed
+    with the solve's pointers restored) still equals vgf_solve."""
+    torch, vgf = need_gpu()
+    plans = []
+    for n, prec, field, layout in MODE_SPECS:
+        h = tuple(2.0 / (x - 1) for x in n)
+        plans.append(vgf.Plan(n, h, precision=prec, field=field, layout=layout))
+    ents = [plans[i] for i in MODE_ENTRIES] + [plans[5], plans[5]]  # a group of three
+    batch = vgf.Batch(ents, graph=graph)
+    rhos = [torch.from_numpy(W.random_field(60 + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
+    phis = [torch.empty(p.n, dtype=p.dtype, device="cuda") for p in ents]
+    Es = [torch.empty((p.dim,) + p.n, dtype=p.dtype, device="cuda") for p in ents]
+    batch.solve(rhos, phis, Es)  # captures the graph with the solve's pointers
+    for seed, wp, wE in ((70, True, True), (80, False, True), (90, True, False)):
+        gps = [torch.from_numpy(W.random_field(seed + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
+        gEs = [torch.from_numpy(W.random_field(seed + 50 + i, (p.dim,) + p.n)).to("cuda", p.dtype)
+               for i, p in enumerate(ents)]
+        grs = [torch.full(p.n, float("nan"), dtype=p.dtype, device="cuda") for p in ents]
+        batch.adjoint(gps if wp else None, gEs if wE else None, grs)
+        torch.cuda.synchronize()
+        for i, p in enumerate(ents):
+            ref = p.adjoint(gps[i] if wp else None, gEs[i] if wE else None)
+            torch.cuda.synchronize()
+            assert torch.equal(grs[i], ref), (seed, wp, wE, i, p.n, p.field, p.layout)
+        say("  adjoint g_phi=%s g_E=%s: all %d entries bit-identical to vgf_solve_adjoint"
+            % (wp, wE, len(ents)))
+    rhos = [torch.from_numpy(W.random_field(95 + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
+    batch.solve(rhos, phis, Es)
+    torch.cuda.synchronize()
+    for i, p in enumerate(ents):
+        p1, E1 = p.solve(rhos[i])
+        torch.cuda.synchronize()
+        assert torch.equal(phis[i], p1) and torch.equal(Es[i], E1), ("solve after adjoint", i)
+    say("  solve after the adjoint: bit-identical (graph=%s)" % graph)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_partial_outputs():
     torch, vgf = need_gpu()
     keys = KEYS[:3]
