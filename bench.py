@@ -30,7 +30,8 @@ Printed JSON line (one, rank 0):
                schedules, in ms per batch and solves/s
   other_workloads  gaussian_3d_32 and mixture_2d_512 (FP64, VGF and HE)
                solves/s, launched pass by pass and replayed as one graph,
-               diff_3d_128 (8 FP32 forward solves + 8 adjoints) ms, and
+               diff_3d_128 (8 FP32 forward solves + 8 adjoints, one by one
+               and batched) ms, and
                variants_256: the beam_3d_256 input through every method,
                field mode and layout, and a rectangular grid, FP32, phi + E
 The 256^3 plans are autotuned (tile schedule per pass, bit-identical results)
@@ -514,9 +515,20 @@ def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
             plan.adjoint(None, gE, gr)
 
     ms = time_fn(torch, step, steps, warmup)
+    # the same step through one batch: each pass one launch over the 8 entries
+    batch = vgf.Batch([plan] * len(rhs), graph=True)
+
+    def step_batched():
+        batch.solve(rhos, None, Es)
+        batch.adjoint(None, gEs, grs)
+
+    ms_b = time_fn(torch, step_batched, steps, warmup)
     out["diff_3d_128"] = {"grid": list(n), "batch": len(rhs), "precision": "f32", "outputs": "E",
                           "ms_per_step": ms, "rhs_per_s": len(rhs) * 1e3 / ms,
-                          "step": "8 forward solves (E only) + 8 adjoints"}
+                          "ms_per_step_batched": ms_b, "rhs_per_s_batched": len(rhs) * 1e3 / ms_b,
+                          "step": "8 forward solves (E only) + 8 adjoints; batched: one vgf_batch_solve "
+                                  "(graph) + one vgf_batch_adjoint"}
+    batch.close()
     plan.close()
     torch.cuda.empty_cache()
     return out
