@@ -494,3 +494,66 @@ def VGFSolve():
 def solve(rho, plan):
     """Differentiable solve: returns (phi, E) with autograd through the adjoint."""
     return VGFSolve().apply(rho, plan)
+
+
+def _batch_autograd_function():
+    torch = _torch()
+
+    class VGFBatchSolve(torch.autograd.Function):
+        """The solves of every entry of a Batch; backward applies the batched
+        hand-written adjoint (vgf_batch_adjoint)."""
+
+        @staticmethod
+        def forward(ctx, batch, want_phi, want_E, *rhos):
+            ctx.batch = batch
+            ctx.want = (want_phi, want_E)
+            plans = batch.plans
+            phis = [torch.empty(p.n, dtype=p.dtype, device=rhos[i].device)
+                    for i, p in enumerate(plans)] if want_phi else None
+            Es = [torch.empty((p.dim,) + p.n, dtype=p.dtype, device=rhos[i].device)
+                  for i, p in enumerate(plans)] if want_E else None
+            batch.solve([r.contiguous() for r in rhos], phis, Es)
+            return tuple((phis or []) + (Es or []))
+
+        @staticmethod
+        def backward(ctx, *grads):
+            batch = ctx.batch
+            want_phi, want_E = ctx.want
+            plans = batch.plans
+            count = len(plans)
+
+            def cotangents(gs, shape_of):
+                if all(g is None for g in gs):
+                    return None
+                return [g.contiguous() if g is not None else
+                        torch.zeros(shape_of(p), dtype=p.dtype, device=next(x for x in gs if x is not None).device)
+                        for g, p in zip(gs, plans)]
+
+            gp = cotangents(grads[:count], lambda p: p.n) if want_phi else None
+            ge = cotangents(grads[count if want_phi else 0:], lambda p: (p.dim,) + p.n) if want_E else None
+            if gp is None and ge is None:
+                return (None, None, None) + (None,) * count
+            return (None, None, None) + tuple(batch.adjoint(gp, ge))
+
+    return VGFBatchSolve
+
+
+_VGFBatchSolve = None
+
+
+def solve_batch(batch, rhos, want_phi=True, want_E=True):
+    """Differentiable solves of a Batch's entries: returns (phis, Es), lists
+    (None for an output not wanted), with autograd through the batched
+    adjoint."""
+    global _VGFBatchSolve
+    if _VGFBatchSolve is None:
+        _VGFBatchSolve = _batch_autograd_function()
+    want_phi = want_phi and all("phi" in p.outputs for p in batch.plans)
+    want_E = want_E and all("E" in p.outputs for p in batch.plans)
+    if not (want_phi or want_E):
+        raise ValueError("no output wanted")
+    outs = _VGFBatchSolve.apply(batch, want_phi, want_E, *rhos)
+    count = len(batch.plans)
+    phis = list(outs[:count]) if want_phi else None
+    Es = list(outs[count if want_phi else 0:]) if want_E else None
+    return phis, Es

@@ -191,6 +191,47 @@ def test_batch_adjoint_equals_single_adjoints(graph):
         p.close()
 
 
+def test_batch_autograd_equals_per_entry_autograd():
+    """Gradients through vgf.solve_batch (batched solve and adjoint) equal
+    those through vgf.solve per entry, bit for bit, for phi + E plans of
+    several kinds and for an E-only group (the differentiable workload's
+    shape), including entries whose phi does not enter the loss."""
+    torch, vgf = need_gpu()
+    specs = [((32, 32, 32), "f32", "fourier", ("phi", "E")), ((64, 48), "f64", "fourier", ("phi", "E")),
+             ((24, 32, 16), "f64", "centered", ("phi", "E")), ((32, 32, 32), "f32", "fourier", ("E",))]
+    plans = []
+    for n, prec, field, outs in specs:
+        h = tuple(2.0 / (x - 1) for x in n)
+        plans.append(vgf.Plan(n, h, precision=prec, field=field, outputs=outs))
+    for ents in ([plans[0], plans[1], plans[0], plans[2]], [plans[3]] * 3):
+        batch = vgf.Batch(ents, graph=True)
+        rhos = [torch.from_numpy(W.random_field(200 + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
+        tE = [torch.from_numpy(W.random_field(300 + i, (p.dim,) + p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
+
+        def loss_of(phis, Es):
+            total = 0.0
+            for i in range(len(ents)):
+                total = total + ((Es[i] - tE[i]) ** 2).sum().double()
+                if phis is not None and i % 2 == 0:  # phi of the odd entries stays out of the loss
+                    total = total + (phis[i] ** 2).sum().double()
+            return total
+
+        xs = [r.clone().requires_grad_(True) for r in rhos]
+        phis, Es = vgf.solve_batch(batch, xs)
+        loss_of(phis, Es).backward()
+        ys = [r.clone().requires_grad_(True) for r in rhos]
+        outs = [vgf.solve(y, p) for y, p in zip(ys, ents)]
+        has_phi = all("phi" in p.outputs for p in ents)
+        loss_of([o[0] for o in outs] if has_phi else None, [o[1] for o in outs]).backward()
+        torch.cuda.synchronize()
+        for i in range(len(ents)):
+            assert torch.equal(xs[i].grad, ys[i].grad), (i, ents[i].n, ents[i].field, ents[i].outputs)
+        say("  batched autograd over %d entries: gradients bit-identical to per-entry autograd" % len(ents))
+        batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_partial_outputs():
     torch, vgf = need_gpu()
     keys = KEYS[:3]
