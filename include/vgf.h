@@ -199,8 +199,10 @@ vgf_status vgf_batch_create(vgf_batch* out, const vgf_plan* plans, int count, un
 vgf_status vgf_batch_solve(vgf_batch batch, const void* const* rho, void* const* phi, void* const* E,
                            hipStream_t stream);
 
-/* Adjoint of every entry i: g_rho[i] = K^T g_phi[i] + sum_a K_a^T g_E[i][a],
- * with the arguments and rules of vgf_solve_adjoint for the entry's plan.
+/* Adjoint of every entry i (the transpose of the per-right-hand-side
+ * convolution of Sec. II / Eq. 3 and of its field, Sec. III.A):
+ * g_rho[i] = K^T g_phi[i] + sum_a K_a^T g_E[i][a], with the arguments and
+ * rules of vgf_solve_adjoint for the entry's plan.
  * g_rho holds a non-NULL buffer for every entry; g_phi (or g_E) is NULL
  * (that cotangent is zero for every entry) or holds a non-NULL buffer for
  * every entry; at least one of them is non-NULL (VGF_ERR_INVALID_ARG
