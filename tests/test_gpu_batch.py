@@ -232,6 +232,37 @@ def test_batch_autograd_equals_per_entry_autograd():
         p.close()
 
 
+def test_batch_adjoint_rejects_bad_arguments():
+    """Partial cotangent lists, a missing g_rho and cotangents of outputs a
+    plan was not created for are refused before anything is enqueued."""
+    torch, vgf = need_gpu()
+    n = (32, 32, 32)
+    h = tuple(2.0 / (x - 1) for x in n)
+    full = vgf.Plan(n, h, precision="f32")
+    e_only = vgf.Plan(n, h, precision="f32", outputs=("E",))
+    VP = C.c_void_p
+    for plans, expect_phi in (([full, full], 0), ([full, e_only], -6)):
+        batch = vgf.Batch(plans, graph=False)
+        gp = [torch.randn(n, device="cuda") for _ in plans]
+        gE = [torch.randn((3,) + n, device="cuda") for _ in plans]
+        gr = [torch.full(n, float("nan"), device="cuda") for _ in plans]
+        arr = lambda xs: (VP * len(xs))(*[x.data_ptr() if x is not None else None for x in xs])
+        L = vgf.lib()
+        assert L.vgf_batch_adjoint(batch.handle, None, None, arr(gr), None) == -1
+        assert L.vgf_batch_adjoint(batch.handle, arr([gp[0], None]), None, arr(gr), None) == -1
+        assert L.vgf_batch_adjoint(batch.handle, None, arr(gE), arr([gr[0], None]), None) == -1
+        assert L.vgf_batch_adjoint(batch.handle, None, arr(gE), None, None) == -1
+        st = L.vgf_batch_adjoint(batch.handle, arr(gp), None, arr(gr), None)
+        assert st == expect_phi
+        torch.cuda.synchronize()
+        if st != 0:
+            for x in gr:
+                assert torch.isnan(x).all()  # nothing was enqueued
+        batch.close()
+    full.close()
+    e_only.close()
+
+
 def test_batch_rejects_partial_outputs():
     torch, vgf = need_gpu()
     keys = KEYS[:3]
