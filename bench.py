@@ -219,6 +219,41 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
     print(TRAFFIC_JSON)
 
 
+WORKLOAD_TITLES = {
+    "batch_3d_mixed": "64 FP32 grids of N in {32, 48, 64, 96, 128}, phi + E: one solve per grid, grouped "
+                      "launches, one replayed graph, and the graph after autotuning",
+    "diff_3d_128": "8 FP32 right-hand sides at 128^3, E only: forward solves and adjoints one by one, then "
+                   "one batched solve (graph) and one batched adjoint",
+}
+
+
+def write_workload_trace_profile(trace_csv, name, bench_json, command):
+    """Per-kernel durations from a rocprofv3 --kernel-trace run of
+    `bench.py --only-workload NAME`, next to the times that run printed."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    agg = {}
+    for r in rows:
+        k = _short_name(r["Kernel_Name"])
+        if k.startswith("at::") or "elementwise" in k or "distribution" in k:
+            k = "torch " + k[:40]
+        agg.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(d) for d in agg.values())
+    md = ["# Kernel trace: %s" % name, "", WORKLOAD_TITLES.get(name, name) + ".", "",
+          "rocprofv3 kernel trace of the whole run (plans, autotuning, warm-up and timed repetitions of "
+          "every mode). Durations in microseconds.", "", "Command:", "", "```", command, "```", "",
+          "| kernel | calls | mean us | total ms | share |", "|---|---|---|---|---|"]
+    for k, d in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        md.append("| %s | %d | %.1f | %.3f | %.1f%% |" % (k, len(d), sum(d) / len(d), sum(d) / 1e3,
+                                                         100.0 * sum(d) / total))
+    if bench_json:
+        line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        md += ["", "Times the same (profiled) run measured:", "", "```", json.dumps(line, indent=1), "```"]
+    path = os.path.join(PROFILES, "%s_kernel_trace.md" % name)
+    with open(path, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(path)
+
+
 def write_trace_profile(trace_csv, bench_json, command):
     """Per-kernel durations from a rocprofv3 --kernel-trace run, next to the
     per-pass means the same bench run measured live with HIP events."""
@@ -499,6 +534,15 @@ def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
             batch.close()
             plan.close()
         out[name] = res
+    out["diff_3d_128"] = run_diff(vgf, torch, workloads, steps, warmup, seed)
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_diff(vgf, torch, workloads, steps, warmup, seed):
+    """diff_3d_128: 8 right-hand sides at 128^3, FP32, E only; one step is
+    the 8 forward solves plus the 8 adjoints of the loss gradient, one by one
+    and as one batched solve (graph) + one batched adjoint."""
     rhs, _ = workloads.diff_3d_128(seed=seed)
     n, h = rhs[0].n, rhs[0].h
     plan = vgf.Plan(n, h, method="vgf", precision="f32", outputs=("E",))
@@ -523,15 +567,14 @@ def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
         batch.adjoint(None, gEs, grs)
 
     ms_b = time_fn(torch, step_batched, steps, warmup)
-    out["diff_3d_128"] = {"grid": list(n), "batch": len(rhs), "precision": "f32", "outputs": "E",
-                          "ms_per_step": ms, "rhs_per_s": len(rhs) * 1e3 / ms,
-                          "ms_per_step_batched": ms_b, "rhs_per_s_batched": len(rhs) * 1e3 / ms_b,
-                          "step": "8 forward solves (E only) + 8 adjoints; batched: one vgf_batch_solve "
-                                  "(graph) + one vgf_batch_adjoint"}
+    res = {"grid": list(n), "batch": len(rhs), "precision": "f32", "outputs": "E",
+           "ms_per_step": ms, "rhs_per_s": len(rhs) * 1e3 / ms,
+           "ms_per_step_batched": ms_b, "rhs_per_s_batched": len(rhs) * 1e3 / ms_b,
+           "step": "8 forward solves (E only) + 8 adjoints; batched: one vgf_batch_solve "
+                   "(graph) + one vgf_batch_adjoint"}
     batch.close()
     plan.close()
-    torch.cuda.empty_cache()
-    return out
+    return res
 
 
 def run_variants(vgf, torch, ch, rho64, steps, warmup):
@@ -762,6 +805,10 @@ def main():
     ap.add_argument("--command", default="", help="the profiling command, recorded in the profile")
     ap.add_argument("--plan-only", action="store_true",
                     help="create the 256^3 and 512^2 plans twice each, print their creation times, exit")
+    ap.add_argument("--only-workload", choices=["batch_3d_mixed", "diff_3d_128"],
+                    help="time only this workload (for a kernel trace of it), print one JSON line, exit")
+    ap.add_argument("--digest-workload-trace", nargs=3, metavar=("TRACE_CSV", "WORKLOAD", "BENCH_JSON"),
+                    help="write profiles/WORKLOAD_kernel_trace.md from a kernel trace of --only-workload")
     ap.add_argument("--digest-plan-trace", metavar="TRACE_CSV",
                     help="write the precompute GEMM profile from a kernel trace of --plan-only")
     ap.add_argument("--oracle-timing", action="store_true",
@@ -770,6 +817,10 @@ def main():
     args = ap.parse_args()
     if args.digest_plan_trace:
         write_plan_trace_profile(args.digest_plan_trace, args.command)
+        return
+    if args.digest_workload_trace:
+        write_workload_trace_profile(args.digest_workload_trace[0], args.digest_workload_trace[1],
+                                     args.digest_workload_trace[2], args.command)
         return
     if args.plan_only:
         plan_only()
@@ -792,6 +843,13 @@ def main():
     import torch
     from paper_2103_08531_amd import vgf, workloads
     torch.cuda.set_device(0)
+    if args.only_workload:
+        if args.only_workload == "batch_3d_mixed":
+            res = run_batch(vgf, torch, workloads, args.steps, args.warmup, args.seed)
+        else:
+            res = run_diff(vgf, torch, workloads, args.steps, args.warmup, args.seed)
+        print(json.dumps({"workload": args.only_workload, "result": res}), flush=True)
+        return
     ch = workloads.beam_3d_256(seed=args.seed)
     rho64 = ch.rho()
     # one small plan first, so that the timed plan creations exclude the
