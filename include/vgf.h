@@ -111,7 +111,8 @@ enum {
  *              is always computed in FP64 and, for VGF_F32, rounded to FP32
  *              once; FFT twiddles are FP64 values rounded to the plan type.
  *   L        : truncation radius of the VGF kernel (Eq. 4). L <= 0 selects
- *              1.1 x the box diameter. Must lie strictly inside
+ *              1.1 x the box diameter; a NaN or infinite L is rejected with
+ *              L_WINDOW. Must lie strictly inside
  *              (diameter, min_a(4 n_a h_a - (n_a - 1) h_a)): below it the
  *              truncated kernel misses source-target pairs (Sec. II), above
  *              it the 4N-periodic images reach the box. Ignored for HE.

@@ -1307,6 +1307,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   const double diam = std::sqrt(diam2);
   double Lp = 0.0;
   if (method == VGF_METHOD_VGF) {
+    if (std::isnan(L)) return VGF_ERR_L_WINDOW;
     Lp = (L > 0.0) ? L : 1.1 * diam;
     if (!(Lp > diam) || !(Lp < upper) || !std::isfinite(Lp)) return VGF_ERR_L_WINDOW;
   }

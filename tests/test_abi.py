@@ -68,15 +68,28 @@ def test_plan_create_rejects_bad_arguments(V):
     assert _create(V, dim=2, n=(640, 64))[0] == -2
 
 
-def test_plan_create_rejects_L_outside_window(V):
-    n = (32, 32, 32)
-    h = tuple(2.0 / 31 for _ in n)
-    diam = 2.0 * 3 ** 0.5
-    assert _create(V, n=n, h=h, L=0.99 * diam)[0] == -3
-    upper = 4 * 32 * h[0] - 2.0
-    assert _create(V, n=n, h=h, L=1.01 * upper)[0] == -3
-    # 2D window
-    assert _create(V, dim=2, n=(64, 64), h=(2 / 63, 2 / 63), L=2.0)[0] == -3
+def test_plan_create_rejects_L_outside_window(V, orc):
+    """The library rejects L just outside the oracle's window, whose ends are
+    pinned by behaviour (tests/test_oracle_window.py), on cubic, 2D and
+    rectangular grids; NaN and infinite L are rejected too (HE ignores L)."""
+    cases = [(3, (32, 32, 32), (2.0 / 31,) * 3), (2, (64, 64), (2 / 63, 2 / 63)),
+             (3, (16, 48, 24), (0.13, 0.05, 0.09)), (2, (96, 128), (2.0 / 95, 2.6 / 127))]
+    for dim, n, h in cases:
+        lo, hi = orc.window(n, h)
+        for L in (0.99 * lo, lo, hi, 1.01 * hi, float("nan"), float("inf"), 1e300):
+            assert _create(V, dim=dim, n=n, h=h, L=L)[0] == -3, (n, h, L, lo, hi)
+        _not_window_error(V, _create(V, dim=dim, n=n, h=h, L=float("nan"), method=1))
+    # L <= 0 selects the default, inside the window
+    _not_window_error(V, _create(V, n=(32, 32, 32), h=(2.0 / 31,) * 3, L=-1.0))
+
+
+def _not_window_error(V, created):
+    """No L_WINDOW status; without a device the call fails later (HIP error),
+    with one it succeeds and the plan is released here."""
+    st, handle = created
+    assert st != -3
+    if st == 0:
+        V.lib().vgf_plan_destroy(handle)
 
 
 def test_null_plan_calls_fail_cleanly(V):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from gpu_common import FP32_TOL, FP64_TOL, check_fields, need_gpu, rounded_input, say
+from gpu_common import FP32_TOL, FP64_TOL, check_fields, need_gpu, rounded_input, gpu_plan, say
 from paper_2103_08531_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -21,7 +21,7 @@ def _plans(vgf, specs):
         key = (n, prec, method)
         if key not in plans:
             h = tuple(2.0 / (x - 1) for x in n)
-            plans[key] = vgf.Plan(n, h, method=method, precision=prec)
+            plans[key] = gpu_plan(vgf, n, h, method=method, precision=prec)
     return plans
 
 
@@ -107,7 +107,7 @@ def test_batch_field_modes_equal_single_solves(graph):
     plans = []
     for n, prec, field, layout in MODE_SPECS:
         h = tuple(2.0 / (x - 1) for x in n)
-        plans.append(vgf.Plan(n, h, precision=prec, field=field, layout=layout))
+        plans.append(gpu_plan(vgf, n, h, precision=prec, field=field, layout=layout))
     ents = [plans[i] for i in MODE_ENTRIES]
     batch = vgf.Batch(ents, graph=graph)
     assert batch.groups == len(MODE_SPECS)
@@ -158,7 +158,7 @@ def test_batch_adjoint_equals_single_adjoints(graph):
     plans = []
     for n, prec, field, layout in MODE_SPECS:
         h = tuple(2.0 / (x - 1) for x in n)
-        plans.append(vgf.Plan(n, h, precision=prec, field=field, layout=layout))
+        plans.append(gpu_plan(vgf, n, h, precision=prec, field=field, layout=layout))
     ents = [plans[i] for i in MODE_ENTRIES] + [plans[5], plans[5]]  # a group of three
     batch = vgf.Batch(ents, graph=graph)
     rhos = [torch.from_numpy(W.random_field(60 + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
@@ -202,7 +202,7 @@ def test_batch_autograd_equals_per_entry_autograd():
     plans = []
     for n, prec, field, outs in specs:
         h = tuple(2.0 / (x - 1) for x in n)
-        plans.append(vgf.Plan(n, h, precision=prec, field=field, outputs=outs))
+        plans.append(gpu_plan(vgf, n, h, precision=prec, field=field, outputs=outs))
     for ents in ([plans[0], plans[1], plans[0], plans[2]], [plans[3]] * 3):
         batch = vgf.Batch(ents, graph=True)
         rhos = [torch.from_numpy(W.random_field(200 + i, p.n)).to("cuda", p.dtype) for i, p in enumerate(ents)]
@@ -238,8 +238,8 @@ def test_batch_adjoint_rejects_bad_arguments():
     torch, vgf = need_gpu()
     n = (32, 32, 32)
     h = tuple(2.0 / (x - 1) for x in n)
-    full = vgf.Plan(n, h, precision="f32")
-    e_only = vgf.Plan(n, h, precision="f32", outputs=("E",))
+    full = gpu_plan(vgf, n, h, precision="f32")
+    e_only = gpu_plan(vgf, n, h, precision="f32", outputs=("E",))
     VP = C.c_void_p
     for plans, expect_phi in (([full, full], 0), ([full, e_only], -6)):
         batch = vgf.Batch(plans, graph=False)
@@ -293,7 +293,7 @@ def test_batch_3d_mixed_graph_vs_oracle():
     kernels = {}
     for ch in charges:
         if ch.n not in plans:
-            plans[ch.n] = vgf.Plan(ch.n, ch.h, method="vgf", precision="f32")
+            plans[ch.n] = gpu_plan(vgf, ch.n, ch.h, method="vgf", precision="f32")
             kernels[ch.n] = orc.vgf_kernel(ch.n, ch.h, plans[ch.n].L)
     pl = [plans[ch.n] for ch in charges]
     batch = vgf.Batch(pl, graph=True)
@@ -345,7 +345,7 @@ def test_batch_splits_groups_beyond_launch_limit():
     127 entries per group)."""
     torch, vgf = need_gpu()
     n = (512, 8)
-    plan = vgf.Plan(n, (2.0 / 511, 2.0 / 7), precision="f32")
+    plan = gpu_plan(vgf, n, (2.0 / 511, 2.0 / 7), precision="f32")
     count = 130
     batch = vgf.Batch([plan] * count, graph=True)
     assert batch.groups == 2

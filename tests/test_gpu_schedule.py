@@ -8,7 +8,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_common import need_gpu, say
+from gpu_common import need_gpu, gpu_plan, say
 from paper_2103_08531_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +46,7 @@ def _schedules(dim, layout):
 def test_every_schedule_is_bit_identical(n, prec, layout):
     torch, vgf = need_gpu()
     h = tuple(2.0 / (x - 1) for x in n)
-    plan = vgf.Plan(n, h, precision=prec, layout=layout)
+    plan = gpu_plan(vgf, n, h, precision=prec, layout=layout)
     assert plan.schedule == (0, 0, 0, 0, 0)
     rho = torch.from_numpy(W.random_field(3, n)).to("cuda", plan.dtype)
     g_phi = torch.from_numpy(W.random_field(4, n)).to("cuda", plan.dtype)
@@ -78,7 +78,7 @@ def _plan_env(vgf, n, prec, stream_min):
     old = os.environ.get("VGF_STREAM_MIN_BYTES")
     os.environ["VGF_STREAM_MIN_BYTES"] = str(stream_min)
     try:
-        return vgf.Plan(n, tuple(2.0 / (x - 1) for x in n), precision=prec)
+        return gpu_plan(vgf, n, tuple(2.0 / (x - 1) for x in n), precision=prec)
     finally:
         if old is None:
             del os.environ["VGF_STREAM_MIN_BYTES"]
@@ -132,7 +132,7 @@ def test_plan_autotune_is_cached_and_exact():
     torch, vgf = need_gpu()
     n = (128, 128, 128)
     h = tuple(2.0 / (x - 1) for x in n)
-    plan = vgf.Plan(n, h, precision="f32")
+    plan = gpu_plan(vgf, n, h, precision="f32")
     rho = torch.from_numpy(W.random_field(9, n)).to("cuda", torch.float32)
     phi0, E0 = plan.solve(rho)
     t0 = time.perf_counter()
@@ -144,7 +144,7 @@ def test_plan_autotune_is_cached_and_exact():
     torch.cuda.synchronize()
     assert torch.equal(phi, phi0) and torch.equal(E, E0)
     # an identical plan takes the cached choice without timing anything
-    plan2 = vgf.Plan(n, h, precision="f32")
+    plan2 = gpu_plan(vgf, n, h, precision="f32")
     t0 = time.perf_counter()
     assert plan2.autotune(rho, reps=3) == sched
     t_cached = time.perf_counter() - t0
@@ -160,7 +160,7 @@ def test_batch_autotune_keeps_results():
     plans = {}
     for n in keys:
         if n not in plans:
-            plans[n] = vgf.Plan(n, tuple(2.0 / (x - 1) for x in n), precision="f32")
+            plans[n] = gpu_plan(vgf, n, tuple(2.0 / (x - 1) for x in n), precision="f32")
     pl = [plans[n] for n in keys]
     rhos = [torch.from_numpy(W.random_field(20 + i, n)).to("cuda", torch.float32) for i, n in enumerate(keys)]
     phis = [torch.empty(n, dtype=torch.float32, device="cuda") for n in keys]

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from gpu_common import (FP32_TOL, FP64_TOL, check_fields, gpu_solve, need_gpu, rel_l2, rounded_input,
+from gpu_common import (FP32_TOL, FP64_TOL, check_fields, err, gpu_plan, gpu_solve, need_gpu, rel_l2, rounded_input,
                         say)
 from paper_2103_08531_amd import workloads as W
 
@@ -23,7 +23,7 @@ HE_MODES = {"he": 0, "he_nearby": 1, "he_cellavg": 2}
 @pytest.mark.parametrize("n,h", [((16, 24, 12), (0.1, 0.08, 0.13)), ((48, 32), (0.04, 0.05))])
 def test_he_variant_kernel_and_solve(method, n, h):
     torch, vgf = need_gpu()
-    plan = vgf.Plan(n, h, method=method, precision="f64")
+    plan = gpu_plan(vgf, n, h, method=method, precision="f64")
     w_o = orc.he_kernel(n, h, HE_MODES[method])
     w_g = plan.kernel()
     err = np.max(np.abs(w_g - w_o)) / np.max(np.abs(w_o))
@@ -42,7 +42,7 @@ def test_he_variant_kernel_and_solve(method, n, h):
 def test_fd_field_forward_and_adjoint(precision, n, method):
     torch, vgf = need_gpu()
     h = tuple((2.0 + 0.1 * a) / (x - 1) for a, x in enumerate(n))
-    plan = vgf.Plan(n, h, method=method, precision=precision, field="centered")
+    plan = gpu_plan(vgf, n, h, method=method, precision=precision, field="centered")
     tol = FP64_TOL if precision == "f64" else FP32_TOL
     w = orc.kernel(method, n, h, plan.L)
     rho = rounded_input(W.random_field(12, n), precision)
@@ -60,7 +60,7 @@ def test_fd_field_forward_and_adjoint(precision, n, method):
     ge = torch.from_numpy(g_E).to("cuda", plan.dtype)
     g_rho = plan.adjoint(gp, ge).double().cpu().numpy()
     ref = orc.adjoint_fft2n(n, h, w, g_phi + orc.fd_field_T(n, h, g_E))
-    e = rel_l2(g_rho, ref)
+    e = err(g_rho, ref)
     say("fd adjoint %s %s %s rel-L2 %.3e" % (method, n, precision, e))
     assert e <= tol
     # adjoint identity on the GPU path: <E(rho), g_E> = <rho, K_E^T g_E>
@@ -85,15 +85,15 @@ def test_paper_2d_sweep_all_methods():
         pa, Ea = orc.gauss_mixture_grid(n, x0, h, c, s, np.ones(1))
         row = {"N": N}
         for method in ("vgf", "he", "he_nearby", "he_cellavg"):
-            plan = vgf.Plan(n, h, method=method, precision="f64")
+            plan = gpu_plan(vgf, n, h, method=method, precision="f64")
             phi_g, E_g = gpu_solve(plan, rho)
             w = orc.kernel(method, n, h, plan.L)
             phi_o, E_o = orc.solve_fft2n(n, h, w, rho)
-            assert rel_l2(phi_g, phi_o) <= FP64_TOL and rel_l2(E_g, E_o) <= FP64_TOL, (N, method)
+            assert err(phi_g, phi_o) <= FP64_TOL and err(E_g, E_o) <= FP64_TOL, (N, method)
             row[method] = float(np.max(np.abs((phi_g - pa) / pa)))
             row[method + "_E"] = float(np.max(np.abs(E_g - Ea)))
             plan.close()
-        plan = vgf.Plan(n, h, method="he", precision="f64", field="centered")
+        plan = gpu_plan(vgf, n, h, method="he", precision="f64", field="centered")
         _, E_fd = gpu_solve(plan, rho)
         row["he_E_fd"] = float(np.max(np.abs(E_fd - Ea)))
         plan.close()
@@ -128,7 +128,7 @@ def _grid(n, h):
 def test_gradient_kernels_and_spectra(n, h):
     torch, vgf = need_gpu()
     h = _grid(n, h)
-    plan = vgf.Plan(n, h, method="vgf", precision="f64", field="gradient_kernel")
+    plan = gpu_plan(vgf, n, h, method="vgf", precision="f64", field="gradient_kernel")
     for a in range(len(n)):
         w_o = orc.vgf_grad_kernel(n, h, plan.L, a)
         w_g = plan.gradient_kernel(a)
@@ -149,7 +149,7 @@ def test_gradient_kernels_and_spectra(n, h):
 def test_gradient_kernel_solve_and_adjoint(precision, n, h):
     torch, vgf = need_gpu()
     h = _grid(n, h)
-    plan = vgf.Plan(n, h, method="vgf", precision=precision, field="gradient_kernel")
+    plan = gpu_plan(vgf, n, h, method="vgf", precision=precision, field="gradient_kernel")
     tol = FP64_TOL if precision == "f64" else FP32_TOL
     rho = rounded_input(W.random_field(21, n), precision)
     phi_g, E_g = gpu_solve(plan, rho)
@@ -167,7 +167,7 @@ def test_gradient_kernel_solve_and_adjoint(precision, n, h):
     for a in range(len(n)):
         V = orc.periodic_kernel_odd(n, orc.vgf_grad_kernel(n, h, plan.L, a), a)
         ref = ref - orc.conv_fft2n(n, V, g_E[a])  # K_a^T: the odd kernel reflected
-    e = rel_l2(g_rho, ref)
+    e = err(g_rho, ref)
     say("gradk adjoint %s %s rel-L2 %.3e" % (n, precision, e))
     assert e <= tol
     plan.close()
@@ -181,8 +181,8 @@ def test_gradient_kernel_beats_2n_field_when_unresolved():
     c, s = np.zeros((1, 3)), np.full((1, 3), 0.1)
     rho = W.gaussian_density(n, x0, h, c, s, np.ones(1))
     _, Ea = orc.gauss_mixture_grid(n, x0, h, c, s, np.ones(1))
-    pg = vgf.Plan(n, h, precision="f64", field="gradient_kernel")
-    pf = vgf.Plan(n, h, precision="f64")
+    pg = gpu_plan(vgf, n, h, precision="f64", field="gradient_kernel")
+    pf = gpu_plan(vgf, n, h, precision="f64")
     _, Eg = gpu_solve(pg, rho)
     _, Ef = gpu_solve(pf, rho)
     eg, ef = rel_l2(Eg, Ea), rel_l2(Ef, Ea)

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from gpu_common import (FP32_TOL, FP64_TOL, check_fields, gpu_solve, need_gpu, oracle_kernel,
+from gpu_common import (FP32_TOL, FP64_TOL, check_fields, err, gpu_plan, gpu_solve, need_gpu, oracle_kernel,
                         rel_l2, rounded_input, say)
 from paper_2103_08531_amd import workloads as W
 
@@ -42,7 +42,7 @@ def test_beam_3d_256(beam, beam_kernel, precision):
     ch, rho64 = beam
     L, w = beam_kernel
     say("beam_3d_256", precision)
-    plan = vgf.Plan(ch.n, ch.h, method="vgf", precision=precision)
+    plan = gpu_plan(vgf, ch.n, ch.h, method="vgf", precision=precision)
     assert abs(plan.L - L) < 1e-12 * L
     rho = rounded_input(rho64, precision)
     phi_g, E_g = gpu_solve(plan, rho)
@@ -80,7 +80,7 @@ def test_batch_3d_mixed():
     kernels = {}
     for ch in charges:
         if ch.n not in plans:
-            plans[ch.n] = vgf.Plan(ch.n, ch.h, method="vgf", precision="f32")
+            plans[ch.n] = gpu_plan(vgf, ch.n, ch.h, method="vgf", precision="f32")
             kernels[ch.n] = orc.vgf_kernel(ch.n, ch.h, plans[ch.n].L)
     rhos = [torch.from_numpy(ch.rho()).to("cuda", torch.float32) for ch in charges]
     pl = [plans[ch.n] for ch in charges]
@@ -108,7 +108,7 @@ def test_diff_3d_128():
     torch, vgf = need_gpu()
     rhs, target = W.diff_3d_128(seed=0)
     n, h = rhs[0].n, rhs[0].h
-    plan = vgf.Plan(n, h, method="vgf", precision="f32", outputs=("E",))
+    plan = gpu_plan(vgf, n, h, method="vgf", precision="f32", outputs=("E",))
     _, E_t = orc.gauss_mixture_grid(target.n, target.x0, target.h, target.centers, target.sigmas,
                                     target.weights, want_phi=False)
     w = orc.vgf_kernel(n, h, plan.L)
@@ -127,7 +127,7 @@ def test_diff_3d_128():
         # FP64 oracle gradient: 2 K_E^T (E(rho) - E_target)
         _, E_o = orc.solve_fft2n(n, h, w, rho_np, want_phi=False)
         g_o = orc.adjoint_fft2n(n, h, w, None, 2.0 * (E_o - E_t))
-        e = rel_l2(grad, g_o)
+        e = err(grad, g_o)
         say("diff[%d] grad vs oracle %.3e" % (b, e))
         assert e <= FP32_TOL
         # central finite differences along seeded directions (loss is quadratic)
