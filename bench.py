@@ -620,9 +620,12 @@ def cpu_baseline(ch, rho64, L, results):
     """FP64 oracle, 2N FFT path, one full solve (phi + E) on the host cores."""
     import oracle as orc
     w = orc.vgf_kernel(ch.n, ch.h, L)  # plan-time precompute: not timed
-    t0 = time.perf_counter()
-    phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, w, rho64)
-    t = time.perf_counter() - t0
+    times = []
+    for _ in range(2):  # two solves: about 25 s of host work on 16 threads
+        t0 = time.perf_counter()
+        phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, w, rho64)
+        times.append(time.perf_counter() - t0)
+    t = sum(times) / len(times)
     acc = {}
     for prec, r in results.items():
         acc[prec] = {"phi": rel_l2(r["out"]["phi"], phi_o),
@@ -639,8 +642,10 @@ def cpu_baseline(ch, rho64, L, results):
                      "E": rel_l2(r["out"]["E"][(slice(None),) + sub], Ea)}
     acc["vs_analytic"] = ana
     base = {"value": 1.0 / t, "unit": "solves/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": "one full 256^3 FP64 solve (phi + E) by the oracle's naive 2N FFT path, "
-                      "including its FFT of the kernel; kernel precompute excluded; %.1f s" % t}
+            "sample": "two full 256^3 FP64 solves (phi + E) by the oracle's naive 2N FFT path, "
+                      "each including its FFT of the kernel; kernel precompute excluded; %s s"
+                      % ", ".join("%.1f" % x for x in times),
+            "host": host_info()}
     return base, acc
 
 

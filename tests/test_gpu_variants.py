@@ -113,6 +113,61 @@ def test_paper_2d_sweep_all_methods():
         assert 1.5 < p < 2.7, (m, p)
 
 
+def test_paper_3d_sweep_all_methods():
+    """Sec. III.B, 3D test: sigma = 0.05 Gaussian (Eq. 14) on [-1/2, 1/2]^3,
+    N from the supported sizes in 10..100; potential error as the maximal
+    relative error against Eq. 15 (Eq. 12) and E_x error as the maximal
+    absolute error (Eq. 13): VGF and the three HE variants with Fourier
+    differentiation, and HE with centred differences. Every GPU result equals
+    the oracle's element-wise to 1e-12 first."""
+    torch, vgf = need_gpu()
+    sizes = (12, 16, 24, 32, 48, 64, 96)
+    rows = []
+    for N in sizes:
+        n, h, x0 = W.cube_grid(3, N, -0.5, 0.5)
+        c, s = np.zeros((1, 3)), np.full((1, 3), 0.05)
+        rho = W.gaussian_density(n, x0, h, c, s, np.ones(1))
+        pa, Ea = orc.gauss_mixture_grid(n, x0, h, c, s, np.ones(1))
+        row = {"N": N}
+        for method in ("vgf", "he", "he_nearby", "he_cellavg"):
+            say("3D sweep", N, method)
+            plan = gpu_plan(vgf, n, h, method=method, precision="f64")
+            phi_g, E_g = gpu_solve(plan, rho)
+            w = orc.kernel(method, n, h, plan.L)
+            phi_o, E_o = orc.solve_fft2n(n, h, w, rho)
+            check_fields(phi_g, E_g, phi_o, E_o, FP64_TOL, "3D sweep %d %s" % (N, method))
+            row[method] = float(np.max(np.abs((phi_g - pa) / pa)))
+            row[method + "_E"] = float(np.max(np.abs(E_g[0] - Ea[0])))
+            plan.close()
+        plan = gpu_plan(vgf, n, h, method="he", precision="f64", field="centered")
+        phi_g, E_fd = gpu_solve(plan, rho)
+        assert err(E_fd, orc.fd_field(n, h, phi_g)) <= FP64_TOL
+        row["he_E_fd"] = float(np.max(np.abs(E_fd[0] - Ea[0])))
+        plan.close()
+        rows.append(row)
+    say("N    vgf       he        nearby    cellavg   | E_x: vgf  he(F)     nearby(F) cellavg(F) he(FD)")
+    for r in rows:
+        say("%-4d %.2e  %.2e  %.2e  %.2e  |    %.2e  %.2e  %.2e  %.2e   %.2e" % (
+            r["N"], r["vgf"], r["he"], r["he_nearby"], r["he_cellavg"], r["vgf_E"], r["he_E"],
+            r["he_nearby_E"], r["he_cellavg_E"], r["he_E_fd"]))
+    # VGF reaches rounding by N = 48 (potential and field); faster than any power before
+    for r in rows:
+        if r["N"] >= 48:
+            assert r["vgf"] < 1e-13 and r["vgf_E"] < 1e-11, r
+            for m in ("he", "he_nearby", "he_cellavg"):
+                assert r["vgf"] < 1e-10 * r[m] and r["vgf_E"] < 1e-9 * r[m + "_E"], r
+    e = [r["vgf"] for r in rows]
+    assert e[2] / e[3] > 100 and e[1] / e[2] > 50, e
+    # every HE variant, and both of HE's fields, converge like h^2
+    for m in ("he", "he_nearby", "he_cellavg", "he_E", "he_nearby_E", "he_cellavg_E", "he_E_fd"):
+        p = -np.polyfit(np.log(sizes[3:]), np.log([r[m] for r in rows[3:]]), 1)[0]
+        say("  %s slope %.2f" % (m, p))
+        assert 1.7 < p < 2.3, (m, p)
+    # the cell average is the best HE variant at every N >= 24
+    for r in rows[2:]:
+        assert r["he_cellavg"] < r["he_nearby"] < r["he"], r
+
+
 # ---------------------------------------------------------------------------
 # Gradient-kernel field: E_a = w_a * rho with w_a the restricted inverse 4N
 # transform of -i k_a Ghat.
