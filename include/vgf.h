@@ -55,7 +55,8 @@ typedef enum {
   VGF_ERR_L_WINDOW = -3,         /* L outside (diameter, min_a(4 n_a h_a - extent_a)) */
   VGF_ERR_OUT_OF_MEMORY = -4,    /* device allocation failed or exceeds VGF_MAX_WORKSPACE */
   VGF_ERR_HIP = -5,              /* a HIP runtime call failed (see vgf_plan_hip_error) */
-  VGF_ERR_NOT_REQUESTED = -6     /* an output that the plan was not created for */
+  VGF_ERR_NOT_REQUESTED = -6,    /* an output that the plan was not created for */
+  VGF_ERR_SCRATCH_LIMIT = -7     /* vgf_solve_noalloc: the plan's workspace exceeds its scratch */
 } vgf_status;
 
 /* VGF: Vico-Greengard-Ferrando (Sec. II). HE: Hockney-Eastwood (Eq. 3) with
@@ -139,6 +140,26 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
  * Requesting a field the plan was not created for returns NOT_REQUESTED;
  * phi == E == NULL returns INVALID_ARG. Enqueued on `stream`. */
 vgf_status vgf_solve(vgf_plan plan, const void* rho, void* phi, void* E, hipStream_t stream);
+
+/* vgf_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same passes and the same results as vgf_solve, bit for bit, but the solve
+ * workspace is a static device array of VGF_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * that every device the library runs on holds until the process ends,
+ * instead of the plan's workspace. The call itself allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine); the plan's kernel
+ * spectra and twiddles come from vgf_plan_create as usual.
+ *   plan, rho, phi, E, stream : as for vgf_solve (device buffers owned by the
+ *   caller; the current device must be the plan's).
+ * The scratch is shared by every call on one device and keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that overlap
+ * on one device -- on different streams, or from different threads --
+ * race, and must be ordered by the caller.
+ * Errors: as vgf_solve, and SCRATCH_LIMIT when vgf_plan_workspace_bytes of
+ * the plan exceeds the scratch (e.g. 3D grids above about 64^3 in FP64 or
+ * 90^3 in FP32); nothing is enqueued then. */
+#define VGF_NOALLOC_SCRATCH_BYTES (64u << 20)
+vgf_status vgf_solve_noalloc(vgf_plan plan, const void* rho, void* phi, void* E, hipStream_t stream);
 
 /* Adjoint of vgf_solve (for reverse-mode differentiation):
  *   g_rho = K^T g_phi + sum_a K_a^T g_E[a],

@@ -77,9 +77,41 @@ struct vgf_plan_s {
   std::vector<int> prof_tags;           // pass of each launch, prof_cap x kMaxMarks
 };
 
+// Workspace of the allocation-free solve (vgf_solve_noalloc): a file-scope
+// device array, so every device the library runs on holds its own copy until
+// the process ends. In host code this name only stands for the symbol; the
+// device address comes from hipGetSymbolAddress, once per device
+// (scratch_address), and is what kernels and copies receive. Every pass of a
+// solve writes what the next one reads, so nothing in it has to start at
+// zero; it keeps the last call's contents.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device (plan creation does it, so a later solve only reads it).
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 bool size_supported(int64_t n) { return n >= 8 && vgf::supported_fft_len(2 * n); }
 
@@ -976,10 +1008,12 @@ vgf::FdGeom fd_geom(vgf_plan p) {
   return g;
 }
 
+// One solve on workspace ws (the plan's own, or the static scratch of
+// vgf_solve_noalloc), laid out as the plan's offsets describe.
 template <typename T>
-vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
+vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s, char* ws) {
   Entries<T> en;
-  en.ws = (char*)p->ws;
+  en.ws = ws;
   en.rho = rho;
   en.phi = phi;
   en.E = E;
@@ -987,7 +1021,7 @@ vgf_status solve_t(vgf_plan p, const T* rho, T* phi, T* E, hipStream_t s) {
   en.want_E = E != nullptr;
   if (!(p->fd && E)) return enqueue_solve<T>(p, en, s, true, p->schedule);
   // E = -D phi: phi (the caller's, or the workspace's), then the differences
-  T* ph = phi ? phi : (T*)((char*)p->ws + p->off_phi);
+  T* ph = phi ? phi : (T*)(ws + p->off_phi);
   en.phi = ph;
   en.E = nullptr;
   en.want_phi = true;
@@ -1269,6 +1303,8 @@ const char* vgf_status_string(vgf_status st) {
     case VGF_ERR_OUT_OF_MEMORY: return "out of device memory (or above VGF_MAX_WORKSPACE)";
     case VGF_ERR_HIP: return "HIP runtime error";
     case VGF_ERR_NOT_REQUESTED: return "output not requested at plan creation";
+    case VGF_ERR_SCRATCH_LIMIT:
+      return "solve workspace larger than the 64 MiB static scratch of vgf_solve_noalloc";
   }
   return "unknown status";
 }
@@ -1428,6 +1464,12 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
     (void)hipGetLastError();
     return st;
   }
+  {
+    // set-up of vgf_solve_noalloc on this device: its scratch address is
+    // looked up here, outside any solve (a failure is reported by that call)
+    void* scratch_dev = nullptr;
+    if (scratch_address(&scratch_dev) != hipSuccess) (void)hipGetLastError();
+  }
   *out = p;
   return VGF_OK;
 }
@@ -1436,8 +1478,20 @@ vgf_status vgf_solve(vgf_plan p, const void* rho, void* phi, void* E, hipStream_
   vgf_status st = check_solve_args(p, rho, phi, E);
   if (st != VGF_OK) return st;
   if (p->prec == VGF_F32)
-    return solve_t<float>(p, (const float*)rho, (float*)phi, (float*)E, stream);
-  return solve_t<double>(p, (const double*)rho, (double*)phi, (double*)E, stream);
+    return solve_t<float>(p, (const float*)rho, (float*)phi, (float*)E, stream, (char*)p->ws);
+  return solve_t<double>(p, (const double*)rho, (double*)phi, (double*)E, stream, (char*)p->ws);
+}
+
+vgf_status vgf_solve_noalloc(vgf_plan p, const void* rho, void* phi, void* E, hipStream_t stream) {
+  vgf_status st = check_solve_args(p, rho, phi, E);
+  if (st != VGF_OK) return st;
+  if (p->ws_bytes > kScratchBytes) return VGF_ERR_SCRATCH_LIMIT;
+  void* ws = nullptr;
+  hipError_t e = scratch_address(&ws);
+  if (e != hipSuccess) return hip_status(p, e);
+  if (p->prec == VGF_F32)
+    return solve_t<float>(p, (const float*)rho, (float*)phi, (float*)E, stream, (char*)ws);
+  return solve_t<double>(p, (const double*)rho, (double*)phi, (double*)E, stream, (char*)ws);
 }
 
 vgf_status vgf_solve_adjoint(vgf_plan p, const void* g_phi, const void* g_E, void* g_rho,

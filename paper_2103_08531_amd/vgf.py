@@ -17,7 +17,8 @@ LIB_PATH = os.environ.get("VGF_LIB") or os.path.join(HERE, "libvgf.so")
 OK = 0
 STATUS = {0: "VGF_OK", -1: "VGF_ERR_INVALID_ARG", -2: "VGF_ERR_UNSUPPORTED_SIZE",
           -3: "VGF_ERR_L_WINDOW", -4: "VGF_ERR_OUT_OF_MEMORY", -5: "VGF_ERR_HIP",
-          -6: "VGF_ERR_NOT_REQUESTED"}
+          -6: "VGF_ERR_NOT_REQUESTED", -7: "VGF_ERR_SCRATCH_LIMIT"}
+NOALLOC_SCRATCH_BYTES = 64 << 20
 METHODS = {"vgf": 0, "he": 1, "he_nearby": 2, "he_cellavg": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
 OUT_PHI, OUT_E, FIELD_CENTERED, FIELD_GRADIENT_KERNEL, LAYOUT_AXIS0 = 1, 2, 16, 32, 64
@@ -28,7 +29,8 @@ EXPORTS = ["vgf_plan_create", "vgf_solve", "vgf_solve_adjoint", "vgf_solve_batch
            "vgf_batch_create", "vgf_batch_solve", "vgf_batch_workspace_bytes", "vgf_batch_groups",
            "vgf_batch_hip_error", "vgf_batch_destroy", "vgf_plan_autotune", "vgf_plan_get_schedule",
            "vgf_plan_set_schedule", "vgf_batch_autotune", "vgf_batch_get_schedule",
-           "vgf_plan_get_gradient_kernel", "vgf_plan_get_gradient_spectrum", "vgf_batch_adjoint"]
+           "vgf_plan_get_gradient_kernel", "vgf_plan_get_gradient_spectrum", "vgf_batch_adjoint",
+           "vgf_solve_noalloc"]
 BATCH_GRAPH = 1
 PASS_NAMES = {3: ["r2c", "c2c_fwd", "fused", "c2c_inv", "c2r"],
               2: ["r2c", "fused", "c2r"]}
@@ -58,6 +60,8 @@ def lib():
                                       C.c_double, C.c_uint, vp]
         L.vgf_solve.restype = C.c_int
         L.vgf_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.vgf_solve_noalloc.restype = C.c_int
+        L.vgf_solve_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.vgf_solve_adjoint.restype = C.c_int
         L.vgf_solve_adjoint.argtypes = [vp, vp, vp, vp, vp]
         L.vgf_solve_batched.restype = C.c_int
@@ -252,6 +256,18 @@ class Plan:
             self._check_tensor(E, (self.dim,) + self.n, "E")
         st = lib().vgf_solve(self.handle, _ptr(rho), _ptr(phi), _ptr(E), _stream(stream))
         _check(st, "vgf_solve")
+        return phi, E
+
+    def solve_noalloc(self, rho, phi=None, E=None, stream=None):
+        """vgf_solve_noalloc: the solve on the library's static scratch; the
+        caller passes every output it wants (this call allocates nothing)."""
+        self._check_tensor(rho, self.n, "rho")
+        if phi is not None:
+            self._check_tensor(phi, self.n, "phi")
+        if E is not None:
+            self._check_tensor(E, (self.dim,) + self.n, "E")
+        st = lib().vgf_solve_noalloc(self.handle, _ptr(rho), _ptr(phi), _ptr(E), _stream(stream))
+        _check(st, "vgf_solve_noalloc")
         return phi, E
 
     def adjoint(self, g_phi=None, g_E=None, g_rho=None, stream=None):

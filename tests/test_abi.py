@@ -95,6 +95,7 @@ def _not_window_error(V, created):
 def test_null_plan_calls_fail_cleanly(V):
     L = V.lib()
     assert L.vgf_solve(None, None, None, None, None) == -1
+    assert L.vgf_solve_noalloc(None, None, None, None, None) == -1
     assert L.vgf_solve_adjoint(None, None, None, None, None) == -1
     assert L.vgf_solve_batched(None, -1, None, None, None, None) == -1
     assert L.vgf_solve_batched(None, 0, None, None, None, None) == 0
