@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "vgf.h"
+#include "vgf_fft.hpp"
 #include "vgf_internal.hpp"
 
 using vgf::cplx;
@@ -149,15 +150,60 @@ struct CisTable {
   }
 };
 
-template <typename T> std::vector<cplx<T>> make_twiddles(int64_t P) {
-  std::vector<cplx<T>> v((size_t)P);
-  for (int64_t e = 0; e < P; ++e) {
-    long double c, s;
-    cis(e, P, &c, &s);
-    v[(size_t)e].x = (T)(double)c;
-    v[(size_t)e].y = (T)(double)(-s);
+// Stage-major twiddle tables of one axis of length P, the forward radix
+// order at [0, P) and the inverse order at [P, 2P) (equal when the order is
+// a palindrome). Stage s (Ns > 1, radix R) keeps the R - 1 slots of
+// butterfly m < Ns at (Ns - R_0) + k Ns + m. A plain slot k holds
+// w_r = cos th_r - i sin th_r, th_r = 2 pi r m / (Ns R), r = k + 1 (the
+// forward sign; the inverse conjugates). Stages in scaled form
+// (vgf::stage_scaled: radix 8 and 4 with 3 not dividing Ns) hold tangents,
+// cosine ratios and cosines (slot layout at vgf::dft8_tw / vgf::dft4_tw).
+// Every value is evaluated in long double from exactly reduced angles and
+// rounded once. Returns false if a divisor would vanish (it cannot for the
+// stages that use the scaled form).
+template <typename T> bool make_stage_twiddles(int P, std::vector<cplx<T>>& out) {
+  out.assign((size_t)2 * P, cplx<T>{T(0), T(0)});
+  auto put = [&](size_t i, long double x, long double y) {
+    out[i].x = (T)x;
+    out[i].y = (T)y;
+  };
+  for (int dir = 0; dir < 2; ++dir) {
+    const int nst = vgf::n_stages(P);
+    auto radix = [&](int st) { return dir == 0 ? vgf::fwd_radix(P, st) : vgf::fwd_radix(P, nst - 1 - st); };
+    const int R0 = radix(0);
+    const size_t base = (size_t)dir * P;
+    int ns = R0;
+    for (int st = 1; st < nst; ++st) {
+      const int R = radix(st);
+      for (int m = 0; m < ns; ++m) {
+        auto at = [&](int k) { return base + (size_t)(ns - R0) + (size_t)k * ns + (size_t)m; };
+        long double c[8], sn[8];
+        for (int r = 0; r < R; ++r) cis((int64_t)r * m, (int64_t)ns * R, &c[r], &sn[r]);
+        if (vgf::stage_scaled(R, ns)) {
+          const int nz[] = {1, 2, 3, 5, 6, 7};
+          for (int r : nz)
+            if (r < R && r != R / 2 && c[r] == 0.0L) return false;
+          if (R == 8) {
+            put(at(0), sn[1] / c[1], sn[2] / c[2]);
+            put(at(1), sn[3] / c[3], sn[5] / c[5]);
+            put(at(2), sn[6] / c[6], sn[7] / c[7]);
+            put(at(3), c[4], -sn[4]);
+            put(at(4), c[6] / c[2], c[5] / c[1]);
+            put(at(5), c[7] / c[3], c[3] / c[1]);
+            put(at(6), c[2], c[1]);
+          } else {
+            put(at(0), sn[1] / c[1], sn[3] / c[3]);
+            put(at(1), c[2], -sn[2]);
+            put(at(2), c[3] / c[1], c[1]);
+          }
+        } else {
+          for (int r = 1; r < R; ++r) put(at(r - 1), c[r], -sn[r]);
+        }
+      }
+      ns *= R;
+    }
   }
-  return v;
+  return true;
 }
 
 // Input bytes (rho of all entries of a launch) from which the forward solve
@@ -1420,7 +1466,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   const size_t ws_bytes = p->off_phi + (p->fd ? align((size_t)vol * rb) : 0);
   p->ws_bytes = ws_bytes;
   size_t tw_bytes = 0;
-  for (int a = 0; a < dim; ++a) tw_bytes += (size_t)p->P[a] * cb;
+  for (int a = 0; a < dim; ++a) tw_bytes += (size_t)2 * p->P[a] * cb;
   p->bytes = ws_bytes + tw_bytes + (size_t)oct * (rb + 8) + (size_t)vol * 8;
   if (p->gradk) p->bytes += (size_t)dim * ((size_t)oct * (rb + 8) + (size_t)vol * 8);
   if (p->bytes > max_workspace_env()) {
@@ -1441,14 +1487,16 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
       if ((err = hipMalloc(&p->specg, (size_t)dim * oct * rb)) != hipSuccess) break;
     }
     for (int a = 0; a < dim && err == hipSuccess; ++a) {
-      err = hipMalloc(&p->tw[a], (size_t)p->P[a] * cb);
+      err = hipMalloc(&p->tw[a], (size_t)2 * p->P[a] * cb);
       if (err != hipSuccess) break;
       if (prec == VGF_F32) {
-        auto t = make_twiddles<float>(p->P[a]);
-        err = hipMemcpy(p->tw[a], t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
+        std::vector<float2> t;
+        if (!make_stage_twiddles<float>((int)p->P[a], t)) err = hipErrorInvalidValue;
+        else err = hipMemcpy(p->tw[a], t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
       } else {
-        auto t = make_twiddles<double>(p->P[a]);
-        err = hipMemcpy(p->tw[a], t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
+        std::vector<double2> t;
+        if (!make_stage_twiddles<double>((int)p->P[a], t)) err = hipErrorInvalidValue;
+        else err = hipMemcpy(p->tw[a], t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
       }
     }
   } while (false);

@@ -30,19 +30,38 @@
 
 namespace vgf {
 
-template <typename C> __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
-template <typename C> __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
-template <typename C> __device__ __forceinline__ C c_mul(C a, C b) {
-  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+// Every floating-point operation of the transforms is written out: products
+// that should be fused use fmaT, all others are plain operations, and the
+// solve kernels are compiled without contraction (-ffp-contract=off). The
+// rounding of each result is then fixed by the source, so every launch shape
+// (tile schedule, batch grouping) that runs the same per-line code gives the
+// same bits, whatever registers the compiler assigns in each instantiation.
+__host__ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename C> __host__ __device__ __forceinline__ C c_add(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __host__ __device__ __forceinline__ C c_sub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+// a * b: one product and one fused multiply-add per component
+template <typename C> __host__ __device__ __forceinline__ C c_mul(C a, C b) {
+  return C{fmaT(a.x, b.x, -(a.y * b.y)), fmaT(a.x, b.y, a.y * b.x)};
 }
 // a * conj(b)
-template <typename C> __device__ __forceinline__ C c_mulc(C a, C b) {
-  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+template <typename C> __host__ __device__ __forceinline__ C c_mulc(C a, C b) {
+  return C{fmaT(a.x, b.x, a.y * b.y), fmaT(a.y, b.x, -(a.x * b.y))};
+}
+// b + s * a for a real s (two fused multiply-adds)
+template <typename C, typename T> __host__ __device__ __forceinline__ C c_fma(T s, C a, C b) {
+  return C{fmaT(s, a.x, b.x), fmaT(s, a.y, b.y)};
 }
 // multiply by S*i  (S = -1: -i, S = +1: +i)
-template <int S, typename C> __device__ __forceinline__ C c_muli(C a) {
+template <int S, typename C> __host__ __device__ __forceinline__ C c_muli(C a) {
   if constexpr (S < 0) return C{a.y, -a.x};
   else return C{-a.y, a.x};
+}
+// b + S i s a for a real s: S i s a = (-S s a.y, S s a.x)
+template <int S, typename C, typename T> __host__ __device__ __forceinline__ C c_fmai(T s, C a, C b) {
+  if constexpr (S < 0) return C{fmaT(s, a.y, b.x), fmaT(-s, a.x, b.y)};
+  else return C{fmaT(-s, a.y, b.x), fmaT(s, a.x, b.y)};
 }
 
 // ---------------------------------------------------------------------------
@@ -93,7 +112,7 @@ template <typename T> struct K {
   static constexpr T s3 = T(0.86602540378443864676372317075293618347);   // sqrt(3)/2
 };
 
-template <int S, typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+template <int S, typename C> __host__ __device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
   C t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
   C t2 = c_add(a1, a3), t3 = c_muli<S>(c_sub(a1, a3));
   a0 = c_add(t0, t2);
@@ -104,7 +123,7 @@ template <int S, typename C> __device__ __forceinline__ void dft4(C& a0, C& a1, 
 
 // dft4 with a2 = a3 = 0 (the zero half of a padded input; adding a zero
 // explicitly would not be folded away, since x + 0 is not x for x = -0)
-template <int S, typename C> __device__ __forceinline__ void dft4_half(C& a0, C& a1, C& a2, C& a3) {
+template <int S, typename C> __host__ __device__ __forceinline__ void dft4_half(C& a0, C& a1, C& a2, C& a3) {
   const C b0 = a0, b1 = a1, t3 = c_muli<S>(a1);
   a0 = c_add(b0, b1);
   a2 = c_sub(b0, b1);
@@ -112,7 +131,27 @@ template <int S, typename C> __device__ __forceinline__ void dft4_half(C& a0, C&
   a3 = c_sub(b0, t3);
 }
 
-template <int S, bool HALF, typename C> __device__ __forceinline__ void dft8_impl(C* v) {
+// The last level of a radix-8 DIT butterfly: v_k = e_k + W^k o_k and
+// v_{k+4} = e_k - W^k o_k with W = exp(S 2 pi i / 8) = (1 + S i)/sqrt2 and
+// o_k = c o'_k. W o = c/sqrt2 (o.x - S o.y, o.y + S o.x) and
+// W^3 o = -c/sqrt2 (o.x + S o.y, o.y - S o.x): the sums are formed first and
+// the scale enters the fused multiply-adds.
+template <int S, typename C, typename T>
+__host__ __device__ __forceinline__ void dft8_combine(C* v, C e0, C e1, C e2, C e3, C o0, C o1, C o2, C o3, T c) {
+  const T q = c * K<T>::r12;
+  const C p1 = S < 0 ? C{o1.x + o1.y, o1.y - o1.x} : C{o1.x - o1.y, o1.y + o1.x};
+  const C p3 = S < 0 ? C{o3.x - o3.y, o3.y + o3.x} : C{o3.x + o3.y, o3.y - o3.x};
+  v[0] = c_fma(c, o0, e0);
+  v[4] = c_fma(-c, o0, e0);
+  v[2] = c_fmai<S>(c, o2, e2);
+  v[6] = c_fmai<S>(-c, o2, e2);
+  v[1] = c_fma(q, p1, e1);
+  v[5] = c_fma(-q, p1, e1);
+  v[3] = c_fma(-q, p3, e3);
+  v[7] = c_fma(q, p3, e3);
+}
+
+template <int S, bool HALF, typename C> __host__ __device__ __forceinline__ void dft8_impl(C* v) {
   using T = decltype(v[0].x);
   // even / odd 4-point DFTs
   C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
@@ -124,57 +163,112 @@ template <int S, bool HALF, typename C> __device__ __forceinline__ void dft8_imp
     dft4<S>(e0, e1, e2, e3);
     dft4<S>(o0, o1, o2, o3);
   }
-  // twiddles w8^k, w8 = exp(S 2 pi i / 8)
-  const T c = K<T>::r12;
-  C t1, t2, t3;
-  if constexpr (S < 0) {
-    t1 = C{(o1.x + o1.y) * c, (o1.y - o1.x) * c};   // (1 - i)/sqrt2
-    t3 = C{(o3.y - o3.x) * c, -(o3.x + o3.y) * c};  // (-1 - i)/sqrt2
-  } else {
-    t1 = C{(o1.x - o1.y) * c, (o1.x + o1.y) * c};   // (1 + i)/sqrt2
-    t3 = C{-(o3.x + o3.y) * c, (o3.x - o3.y) * c};  // (-1 + i)/sqrt2
-  }
-  t2 = c_muli<S>(o2);
+  // W^0 and W^2 need no product: o0 and S i o2 are added as they are
+  const T q = K<T>::r12;
+  const C p1 = S < 0 ? C{o1.x + o1.y, o1.y - o1.x} : C{o1.x - o1.y, o1.y + o1.x};
+  const C p3 = S < 0 ? C{o3.x - o3.y, o3.y + o3.x} : C{o3.x + o3.y, o3.y - o3.x};
+  const C t2 = c_muli<S>(o2);
   v[0] = c_add(e0, o0);
   v[4] = c_sub(e0, o0);
-  v[1] = c_add(e1, t1);
-  v[5] = c_sub(e1, t1);
   v[2] = c_add(e2, t2);
   v[6] = c_sub(e2, t2);
-  v[3] = c_add(e3, t3);
-  v[7] = c_sub(e3, t3);
+  v[1] = c_fma(q, p1, e1);
+  v[5] = c_fma(-q, p1, e1);
+  v[3] = c_fma(-q, p3, e3);
+  v[7] = c_fma(q, p3, e3);
 }
 
-template <int S, typename C> __device__ __forceinline__ void dft3_impl(C* v) {
+template <int S, typename C> __host__ __device__ __forceinline__ void dft3_impl(C* v) {
   using T = decltype(v[0].x);
-  C a0 = v[0], a1 = v[1], a2 = v[2];
-  C s = c_add(a1, a2), d = c_sub(a1, a2);
-  C m = C{a0.x - T(0.5) * s.x, a0.y - T(0.5) * s.y};
-  // S*i*(sqrt3/2)*d
-  C u = c_muli<S>(C{K<T>::s3 * d.x, K<T>::s3 * d.y});
+  const C a0 = v[0], a1 = v[1], a2 = v[2];
+  const C s = c_add(a1, a2), d = c_sub(a1, a2);
+  const C m = c_fma(T(-0.5), s, a0);  // a0 - s/2
   v[0] = c_add(a0, s);
-  v[1] = c_add(m, u);
-  v[2] = c_sub(m, u);
+  v[1] = c_fmai<S>(K<T>::s3, d, m);   // m + S i (sqrt3/2) d
+  v[2] = c_fmai<S>(-K<T>::s3, d, m);
 }
 
 // run: full R-point DFT; run_half: the same with inputs R/2 .. R-1 zero
 // (never read)
 template <int R, int S, typename C> struct Dft;
 template <int S, typename C> struct Dft<2, S, C> {
-  __device__ __forceinline__ static void run(C* v) { C a = v[0], b = v[1]; v[0] = c_add(a, b); v[1] = c_sub(a, b); }
-  __device__ __forceinline__ static void run_half(C* v) { v[1] = v[0]; }
+  __host__ __device__ __forceinline__ static void run(C* v) { C a = v[0], b = v[1]; v[0] = c_add(a, b); v[1] = c_sub(a, b); }
+  __host__ __device__ __forceinline__ static void run_half(C* v) { v[1] = v[0]; }
 };
 template <int S, typename C> struct Dft<3, S, C> {
-  __device__ __forceinline__ static void run(C* v) { dft3_impl<S>(v); }
+  __host__ __device__ __forceinline__ static void run(C* v) { dft3_impl<S>(v); }
 };
 template <int S, typename C> struct Dft<4, S, C> {
-  __device__ __forceinline__ static void run(C* v) { dft4<S>(v[0], v[1], v[2], v[3]); }
-  __device__ __forceinline__ static void run_half(C* v) { dft4_half<S>(v[0], v[1], v[2], v[3]); }
+  __host__ __device__ __forceinline__ static void run(C* v) { dft4<S>(v[0], v[1], v[2], v[3]); }
+  __host__ __device__ __forceinline__ static void run_half(C* v) { dft4_half<S>(v[0], v[1], v[2], v[3]); }
 };
 template <int S, typename C> struct Dft<8, S, C> {
-  __device__ __forceinline__ static void run(C* v) { dft8_impl<S, false>(v); }
-  __device__ __forceinline__ static void run_half(C* v) { dft8_impl<S, true>(v); }
+  __host__ __device__ __forceinline__ static void run(C* v) { dft8_impl<S, false>(v); }
+  __host__ __device__ __forceinline__ static void run_half(C* v) { dft8_impl<S, true>(v); }
 };
+
+// ---------------------------------------------------------------------------
+// Twiddled radix-8 and radix-4 butterflies with the twiddles in scaled form.
+// Input r of a butterfly is multiplied by w_r = cos(th_r) + S i sin(th_r),
+// th_r = 2 pi r m / (Ns R) for butterfly m = j mod Ns. Writing
+// w_r = c_r (1 + S i t_r), c_r = cos th_r, t_r = tan th_r, the rotation
+// u_r = a_r (1 + S i t_r) costs two fused multiply-adds, and the scale c_r is
+// carried into the sums of the DFT, where it rides on fused multiply-adds
+// that are needed anyway: x2 + x6 = c2 (u2 + (c6/c2) u6), and so on. Only
+// the input with th = pi m / Ns (r = R/2), whose cosine vanishes at
+// m = Ns/2, keeps the full complex product. The cosines that are divided by
+// are nonzero for Ns not divisible by 3 (the stages that use this form).
+// Slots of a radix-8 butterfly (7 complex values, the table space of the
+// R-1 plain twiddles): (t1, t2), (t3, t5), (t6, t7), w4, (c6/c2, c5/c1),
+// (c7/c3, c3/c1), (c2, c1). Radix 4: (t1, t3), w2, (c3/c1, c1). A plain
+// twiddle w is stored with the forward sign (cos th, -sin th) and conjugated
+// for S > 0; the tangents are those of the angle th itself (th >= 0).
+// ---------------------------------------------------------------------------
+template <int S, typename C, typename T>
+__host__ __device__ __forceinline__ C rot_tan(C a, T t) {  // a (1 + S i t)
+  if constexpr (S < 0) return C{fmaT(t, a.y, a.x), fmaT(-t, a.x, a.y)};
+  else return C{fmaT(-t, a.y, a.x), fmaT(t, a.x, a.y)};
+}
+template <int S, typename C> __host__ __device__ __forceinline__ C twiddle_mul(C a, C w) {
+  if constexpr (S < 0) return c_mul(a, w);
+  else return c_mulc(a, w);
+}
+
+template <int S, typename C> __host__ __device__ __forceinline__ void dft8_tw(C* v, const C* w) {
+  using T = decltype(v[0].x);
+  const T t1 = w[0].x, t2 = w[0].y, t3 = w[1].x, t5 = w[1].y, t6 = w[2].x, t7 = w[2].y;
+  const T r62 = w[4].x, r51 = w[4].y, r73 = w[5].x, r31 = w[5].y, c2 = w[6].x, c1 = w[6].y;
+  const C u1 = rot_tan<S>(v[1], t1), u2 = rot_tan<S>(v[2], t2), u3 = rot_tan<S>(v[3], t3);
+  const C u5 = rot_tan<S>(v[5], t5), u6 = rot_tan<S>(v[6], t6), u7 = rot_tan<S>(v[7], t7);
+  const C x4 = twiddle_mul<S>(v[4], w[3]);
+  // even half: DFT4 of (a0, c2 u2, x4, c2 (c6/c2) u6)
+  const C g0 = c_add(v[0], x4), g1 = c_sub(v[0], x4);
+  const C s26 = c_fma(r62, u6, u2), d26 = c_fma(-r62, u6, u2);
+  const C e0 = c_fma(c2, s26, g0), e2 = c_fma(-c2, s26, g0);
+  const C e1 = c_fmai<S>(c2, d26, g1), e3 = c_fmai<S>(-c2, d26, g1);
+  // odd half: DFT4 of (c1 u1, c3 u3, c5 u5, c7 u7) = c1 (o0', o1', o2', o3')
+  const C s15 = c_fma(r51, u5, u1), d15 = c_fma(-r51, u5, u1);
+  const C s37 = c_fma(r73, u7, u3), d37 = c_fma(-r73, u7, u3);
+  const C o0 = c_fma(r31, s37, s15), o2 = c_fma(-r31, s37, s15);
+  const C o1 = c_fmai<S>(r31, d37, d15), o3 = c_fmai<S>(-r31, d37, d15);
+  dft8_combine<S>(v, e0, e1, e2, e3, o0, o1, o2, o3, c1);
+}
+
+template <int S, typename C> __host__ __device__ __forceinline__ void dft4_tw(C* v, const C* w) {
+  using T = decltype(v[0].x);
+  const T t1 = w[0].x, t3 = w[0].y, r31 = w[2].x, c1 = w[2].y;
+  const C u1 = rot_tan<S>(v[1], t1), u3 = rot_tan<S>(v[3], t3);
+  const C x2 = twiddle_mul<S>(v[2], w[1]);
+  const C g0 = c_add(v[0], x2), g1 = c_sub(v[0], x2);
+  const C s13 = c_fma(r31, u3, u1), d13 = c_fma(-r31, u3, u1);
+  v[0] = c_fma(c1, s13, g0);
+  v[2] = c_fma(-c1, s13, g0);
+  v[1] = c_fmai<S>(c1, d13, g1);
+  v[3] = c_fmai<S>(-c1, d13, g1);
+}
+
+// Stages whose twiddles are stored in the scaled form above.
+constexpr bool stage_scaled(int R, int NS) { return NS > 1 && (R == 8 || R == 4) && NS % 3 != 0; }
 
 // ---------------------------------------------------------------------------
 // one Stockham stage of a workgroup-wide batched transform
@@ -201,19 +295,16 @@ struct Stage {
   static constexpr int NTASK = (NB + NQ - 1) / NQ;
   static constexpr bool EXACT = (NB % NQ) == 0;
   static constexpr bool LAST = (S == n_stages(P) - 1);
+  static constexpr bool SCALED = stage_scaled(R, NS);
   static_assert(NT % NL == 0, "threads must cover whole lines");
 
   struct Regs { C v[NTASK][R]; };
+  // the twiddle slots of the thread's butterflies (R - 1 per butterfly)
+  struct Tw { C w[NTASK][R - 1]; };
 
   __device__ __forceinline__ static bool active(int t, int q) { return EXACT || (q + t * NQ) < NB; }
   __device__ __forceinline__ static int in_pos(int j, int r) { return j + r * NB; }
   __device__ __forceinline__ static int out_pos(int j, int r) { return (j / NS) * NS * R + (j % NS) + r * NS; }
-
-  __device__ __forceinline__ static C twiddle(const C* tw, int e) {
-    C w = tw[e];
-    if constexpr (SIGN > 0) w.y = -w.y;
-    return w;
-  }
 
   // first stage (Ns = 1, no twiddles); ld(j, r) returns the input at
   // position j + r*NB (r is a compile-time constant at every call).
@@ -234,13 +325,47 @@ struct Stage {
     }
   }
 
-  // HALF: the first stage of a pruned load (inputs r >= R/2 are zero)
+  // R-point DFTs of the first stage (no twiddles). HALF: the first stage of
+  // a pruned load (inputs r >= R/2 are zero)
   template <bool HALF = false> __device__ __forceinline__ static void butterflies(Regs& g, int q) {
+    static_assert(NS == 1, "a stage with twiddles uses tw_butterflies");
 #pragma unroll
     for (int t = 0; t < NTASK; ++t) {
       if (!active(t, q)) continue;
       if constexpr (HALF) Dft<R, SIGN, C>::run_half(g.v[t]);
       else Dft<R, SIGN, C>::run(g.v[t]);
+    }
+  }
+
+  // This stage's twiddle slots from a stage-major table (LDS or global
+  // memory): slot k of butterfly j at (NS - R_0) + k*NS + (j mod NS), so the
+  // R-1 slots of one butterfly are read from one base with immediate offsets.
+  __device__ __forceinline__ static void load_tw(Tw& tw, const C* tab, int q) {
+    static_assert(NS > 1, "the first stage has no twiddles");
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      const int j = q + t * NQ;
+      const C* tb = tab + (NS - radix_at<SIGN>(P, 0)) + (j % NS);
+#pragma unroll
+      for (int k = 0; k < R - 1; ++k) tw.w[t][k] = tb[k * NS];
+    }
+  }
+
+  // twiddles and R-point DFTs of a stage with NS > 1
+  __device__ __forceinline__ static void tw_butterflies(Regs& g, const Tw& tw, int q) {
+#pragma unroll
+    for (int t = 0; t < NTASK; ++t) {
+      if (!active(t, q)) continue;
+      if constexpr (SCALED && R == 8) {
+        dft8_tw<SIGN>(g.v[t], tw.w[t]);
+      } else if constexpr (SCALED && R == 4) {
+        dft4_tw<SIGN>(g.v[t], tw.w[t]);
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) g.v[t][r] = twiddle_mul<SIGN>(g.v[t][r], tw.w[t][r - 1]);
+        Dft<R, SIGN, C>::run(g.v[t]);
+      }
     }
   }
 
@@ -260,20 +385,14 @@ struct Stage {
     }
   }
 
-  // read this stage's inputs from the LDS tile and apply the twiddles
-  __device__ __forceinline__ static void lds_in(Regs& g, const C* lds, const C* tw, int l, int q) {
+  // read this stage's inputs from the LDS tile
+  __device__ __forceinline__ static void lds_in(Regs& g, const C* lds, int l, int q) {
 #pragma unroll
     for (int t = 0; t < NTASK; ++t) {
       if (!active(t, q)) continue;
       const int j = q + t * NQ;
 #pragma unroll
       for (int r = 0; r < R; ++r) g.v[t][r] = lds[in_index(j, r, l)];
-      if constexpr (NS > 1) {
-        // stage-major table: the R-1 twiddles of butterfly j are NS apart
-        const C* tb = tw + (NS - radix_at<SIGN>(P, 0)) + (j % NS);
-#pragma unroll
-        for (int r = 1; r < R; ++r) g.v[t][r] = c_mul(g.v[t][r], twiddle(tb, (r - 1) * NS));
-      }
     }
   }
 
@@ -358,15 +477,19 @@ __device__ __forceinline__ void middle_and_last(
     constexpr int s = decltype(sI)::value;
     using St = Stage<T, P, NT, NL, LP, SIGN, s, LAYOUT>;
     typename St::Regs g;
-    St::lds_in(g, lds, tw, l, q);
-    St::butterflies(g, q);
+    typename St::Tw w;
+    St::lds_in(g, lds, l, q);
+    St::load_tw(w, tw, q);
+    St::tw_butterflies(g, w, q);
     tile_sync<WAVE>();
     St::lds_out(g, lds, l, q);
     tile_sync<WAVE>();
   });
   using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1, LAYOUT>;
-  SL::lds_in(last, lds, tw, l, q);
-  SL::butterflies(last, q);
+  typename SL::Tw w;
+  SL::lds_in(last, lds, l, q);
+  SL::load_tw(w, tw, q);
+  SL::tw_butterflies(last, w, q);
 }
 
 // Ping-pong variant for kernels that run one workgroup per CU anyway: LDS
@@ -395,15 +518,19 @@ __device__ __forceinline__ void transform_pp(
     constexpr int s = decltype(sI)::value;
     using St = Stage<T, P, NT, NL, LP, SIGN, s>;
     typename St::Regs g;
-    St::lds_in(g, pp.now(), tw, l, q);
-    St::butterflies(g, q);
+    typename St::Tw w;
+    St::lds_in(g, pp.now(), l, q);
+    St::load_tw(w, tw, q);
+    St::tw_butterflies(g, w, q);
     pp.flip();
     St::lds_out(g, pp.now(), l, q);
     __syncthreads();
   });
   using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1>;
-  SL::lds_in(last, pp.now(), tw, l, q);
-  SL::butterflies(last, q);
+  typename SL::Tw w;
+  SL::lds_in(last, pp.now(), l, q);
+  SL::load_tw(w, tw, q);
+  SL::tw_butterflies(last, w, q);
   pp.flip();
 }
 

@@ -146,22 +146,24 @@ __device__ __forceinline__ C deriv(C x, int code, T k) {
   if (code < 0) return C{k * x.y, -k * x.x};
   return C{-k * x.y, k * x.x};
 }
+// acc + deriv(x, code, k), the product fused into the sum
+template <typename C, typename T>
+__device__ __forceinline__ C deriv_add(C acc, C x, int code, T k) {
+  if (code == 0) return C{acc.x + x.x, acc.y + x.y};
+  if (code < 0) return C{fmaT(k, x.y, acc.x), fmaT(-k, x.x, acc.y)};
+  return C{fmaT(-k, x.y, acc.x), fmaT(k, x.x, acc.y)};
+}
 
-// Twiddles of the stages of one direction in LDS, stage-major: stage s
-// (Ns > 1, radix R) keeps w^(r*m*P/(Ns*R)) for r = 1..R-1, m = 0..Ns-1 at
-// (Ns - R_0) + (r-1)*Ns + m, so the R-1 twiddles of one butterfly are read
-// from one per-thread base with immediate offsets; P - R_0 entries in all.
-// tw holds w^k, k < P, of the forward sign.
+// Twiddles of the stages of one direction in LDS, stage-major (see
+// Stage::load_tw): the plan keeps, per axis, the table of the forward radix
+// order at tw[0, P) and that of the inverse order at tw[P, 2P) (the same
+// values when the order is a palindrome), each P - R_0 entries long; a
+// workgroup copies the one it needs.
 template <typename C, int P, int NT, int SIGN>
 __device__ __forceinline__ void stage_twiddles(C* twl, const C* __restrict__ tw, int tid) {
   constexpr int R0 = radix_at<SIGN>(P, 0);
-  for (int e = tid; e < P - R0; e += NT) {
-    int ns = R0, s = 1;
-    while (e >= ns * radix_at<SIGN>(P, s) - R0) ns *= radix_at<SIGN>(P, s++);
-    const int rad = radix_at<SIGN>(P, s);
-    const int off = e - (ns - R0), rm1 = off / ns, m = off - rm1 * ns;
-    twl[e] = tw[(rm1 + 1) * m * (P / (ns * rad))];
-  }
+  const C* __restrict__ src = tw + (SIGN < 0 ? 0 : P);
+  for (int e = tid; e < P - R0; e += NT) twl[e] = src[e];
 }
 // LDS entries for the twiddles of a kernel that runs both directions, the
 // forward table first; the inverse table (tw_inverse) is a second one only
@@ -279,19 +281,15 @@ __global__ __launch_bounds__((TileW<T, P>::NT)) void k_r2c(R2CArgs<T> a,
       if (k >= H) continue;
       const C z = tile[lds_index<1, LP>(k, l)];
       const C zm = tile[lds_index<1, LP>((P - k) % P, l)];
-      C xk = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-      C yk = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
-      if (code != 0) {
-        const T kk = a.d.ks * (T)(k < N ? k : 0);
-        xk = deriv(xk, code, kk);
-        yk = deriv(yk, code, kk);
-      }
+      const C xk = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+      const C yk = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
+      const T kk = a.d.ks * (T)(k < N ? k : 0);
       if (term == 0) {
-        acc_a[s] = xk;
-        acc_b[s] = yk;
+        acc_a[s] = deriv(xk, code, kk);
+        acc_b[s] = deriv(yk, code, kk);
       } else {
-        acc_a[s].x += xk.x; acc_a[s].y += xk.y;
-        acc_b[s].x += yk.x; acc_b[s].y += yk.y;
+        acc_a[s] = deriv_add(acc_a[s], xk, code, kk);
+        acc_b[s] = deriv_add(acc_b[s], yk, code, kk);
       }
     }
   }
@@ -467,10 +465,9 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
       const int j = q + t * SL::NQ;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
-        C v = gl.v[t][r];
-        if (code != 0) v = deriv(v, code, axis_k<T, SL::R, SL::NB>(a.d.ks, j, r));
-        if (term == 0) acc.v[t][r] = v;
-        else { acc.v[t][r].x += v.x; acc.v[t][r].y += v.y; }
+        const T kk = code != 0 ? axis_k<T, SL::R, SL::NB>(a.d.ks, j, r) : T(0);
+        if (term == 0) acc.v[t][r] = deriv(gl.v[t][r], code, kk);
+        else acc.v[t][r] = deriv_add(acc.v[t][r], gl.v[t][r], code, kk);
       }
     }
   }
@@ -847,10 +844,8 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
       const int j = q + t * SL::NQ;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
-        C m = rh.v[t][r];
-        if (code != 0) m = deriv(m, 1, axis_k<T, SL::R, SL::NB>(g.ks0, j, r));
-        acc.v[t][r].x += m.x;
-        acc.v[t][r].y += m.y;
+        const T kk = code != 0 ? axis_k<T, SL::R, SL::NB>(g.ks0, j, r) : T(0);
+        acc.v[t][r] = deriv_add(acc.v[t][r], rh.v[t][r], code != 0 ? 1 : 0, kk);
       }
     }
   }
@@ -1085,19 +1080,15 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
       if (k >= H) continue;
       const C z = lds[lds_index<0, LP>(k, l)];
       const C zm = lds[lds_index<0, LP>((P - k) % P, l)];
-      C xa = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-      C xb = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
-      if (code != 0) {
-        const T kk = a.d.ks * (T)(k < N ? k : 0);
-        xa = deriv(xa, code, kk);
-        xb = deriv(xb, code, kk);
-      }
+      const C xa = C{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+      const C xb = C{T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
+      const T kk = a.d.ks * (T)(k < N ? k : 0);
       if (term == 0) {
-        acc_a[s] = xa;
-        acc_b[s] = xb;
+        acc_a[s] = deriv(xa, code, kk);
+        acc_b[s] = deriv(xb, code, kk);
       } else {
-        acc_a[s].x += xa.x; acc_a[s].y += xa.y;
-        acc_b[s].x += xb.x; acc_b[s].y += xb.y;
+        acc_a[s] = deriv_add(acc_a[s], xa, code, kk);
+        acc_b[s] = deriv_add(acc_b[s], xb, code, kk);
       }
     }
   }
@@ -1402,9 +1393,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
         if constexpr (sizeof(T) == 8) asm volatile("" : "+v"(j));
 #pragma unroll
         for (int r = 0; r < SL::R; ++r) {
-          const C m = d ? deriv(rh.v[t][r], 1, axis_k<T, SL::R, SL::NB>(g.ks, j, r)) : rh.v[t][r];
-          acc.v[t][r].x += m.x;
-          acc.v[t][r].y += m.y;
+          const T kk = d ? axis_k<T, SL::R, SL::NB>(g.ks, j, r) : T(0);
+          acc.v[t][r] = deriv_add(acc.v[t][r], rh.v[t][r], d ? 1 : 0, kk);
         }
       }
     }
