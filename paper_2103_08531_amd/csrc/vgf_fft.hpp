@@ -492,6 +492,31 @@ __device__ __forceinline__ void middle_and_last(
   SL::tw_butterflies(last, w, q);
 }
 
+// middle_and_last with the last stage's twiddle slots supplied by the caller
+// (held in registers across the lines a wavefront walks).
+template <typename T, int P, int NT, int NL, int LP, int SIGN, int LAYOUT = 0, bool WAVE = false>
+__device__ __forceinline__ void middle_and_last_tw(
+    typename Stage<T, P, NT, NL, LP, SIGN, n_stages(P) - 1, LAYOUT>::Regs& last, cplx<T>* lds,
+    const cplx<T>* tw, const typename Stage<T, P, NT, NL, LP, SIGN, n_stages(P) - 1, LAYOUT>::Tw& wl, int l,
+    int q) {
+  constexpr int NSTG = n_stages(P);
+  StaticFor<1, NSTG - 1>::run([&](auto sI) {
+    constexpr int s = decltype(sI)::value;
+    using St = Stage<T, P, NT, NL, LP, SIGN, s, LAYOUT>;
+    typename St::Regs g;
+    typename St::Tw w;
+    St::lds_in(g, lds, l, q);
+    St::load_tw(w, tw, q);
+    St::tw_butterflies(g, w, q);
+    tile_sync<WAVE>();
+    St::lds_out(g, lds, l, q);
+    tile_sync<WAVE>();
+  });
+  using SL = Stage<T, P, NT, NL, LP, SIGN, NSTG - 1, LAYOUT>;
+  SL::lds_in(last, lds, l, q);
+  SL::tw_butterflies(last, wl, q);
+}
+
 // Ping-pong variant for kernels that run one workgroup per CU anyway: LDS
 // phases alternate between two tiles, so each stage boundary needs a single
 // barrier (between the writes and the reads of one phase); a tile is written

@@ -200,6 +200,10 @@ template <int P> constexpr int wave_nq() {
 #ifndef VGF_FC_GPW
 #define VGF_FC_GPW 4
 #endif
+// multiply pass of P >= 512 through k_fused_c1 (1) or k_fused_c (0)
+#ifndef VGF_FC1
+#define VGF_FC1 1
+#endif
 constexpr int64_t kFusedCMinBlocks = 2048;
 template <typename T, int P> struct TileW {
   static constexpr int NQ = wave_nq<P>();  // lanes per line pair
@@ -1329,6 +1333,110 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   }
 }
 
+// The multiply pass for lines of P >= 512, one line per wavefront (all 64
+// lanes along it). The line a wavefront works on is the same for all its
+// lanes, so the walk and every line base address live in scalar registers
+// and each lane keeps fixed per-lane offsets; the number of output fields is
+// a template parameter (straight-line code for phi and E_last); and the
+// twiddle slots of the last stage of each direction, the same for every
+// line, are loaded once and held in registers. Same arithmetic per line as
+// k_fused_c.
+template <typename T, int P, int NF>
+__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_c1(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, const T* __restrict__ spec,
+    const cplx<T>* __restrict__ tw, int gpw) {
+  using C = cplx<T>;
+  using TW = TileW<T, P>;
+  static_assert(TW::LPW == 1 && TW::NQ == 64, "one line per wavefront");
+  constexpr int LP = TW::LP, N = P / 2;
+  constexpr int NSTG = n_stages(P);
+  using S0 = Stage<T, P, 64, 1, LP, -1, 0, 1>;
+  using SL = Stage<T, P, 64, 1, LP, -1, NSTG - 1, 1>;
+  using IS0 = Stage<T, P, 64, 1, LP, 1, 0, 1>;
+  using ISL = Stage<T, P, 64, 1, LP, 1, NSTG - 1, 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+  __shared__ C tiles[TW::WPB * LP];
+  __shared__ C twl[tw_both_size<P>()];
+  const int tid = threadIdx.x, q = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  C* tile = tiles + w * LP;
+  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw;
+  LineWalk wk;
+  wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
+  wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
+  {
+    const EntryLine el(line < g.nlines ? line : 0, g.lpe, g.nlines);
+    wk.e = (int)el.e;
+    wk.k0 = (int)el.line / wk.p1;
+    wk.k1 = (int)el.line - wk.k0 * wk.p1;
+  }
+  stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
+  typename SL::Tw twf;
+  typename ISL::Tw twi;
+  SL::load_tw(twf, twl, q);
+  ISL::load_tw(twi, tw_inverse<P>(twl), q);
+
+  for (int it = 0; it < gpw && line < g.nlines; ++it, ++line) {
+    const int64_t lofs = ((int64_t)wk.k0 * wk.p1 + wk.k1) * N;
+    const int row = g.dim == 3 ? wk.k0 * (g.n1 + 1) + (wk.k1 <= g.n1 ? wk.k1 : wk.p1 - wk.k1) : wk.k1;
+    const T* __restrict__ srow = spec + (int64_t)row * (N + 1);
+    const C* __restrict__ src = in + wk.e * g.in_es + lofs;
+    C* __restrict__ dst = out + wk.e * g.out_es + lofs;
+    wk.advance(1);
+    typename S0::Regs x;
+    if (g.nt)
+      S0::template load_first<true>(x, q, [&](int j, int r) { return load_nt(&src[S0::in_pos(j, r)]); });
+    else
+      S0::template load_first<true>(x, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+    T sv[SL::NTASK][SL::R];
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t) {
+      const int j = q + t * SL::NQ;
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        const int p = j + r * SL::NB;
+        sv[t][r] = srow[p <= N ? p : P - p];
+      }
+    }
+    S0::template butterflies<true>(x, q);
+    wave_sync();  // the previous line's reads of the tile are done
+    S0::lds_out(x, tile, 0, q);
+    wave_sync();
+    typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
+    middle_and_last_tw<T, P, 64, 1, LP, -1, 1, true>(rh, tile, twl, twf, 0, q);
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t)
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) {
+        rh.v[t][r].x *= sv[t][r];
+        rh.v[t][r].y *= sv[t][r];
+      }
+    StaticFor<0, NF>::run([&](auto fI) {
+      constexpr int fi = decltype(fI)::value;
+      typename IS0::Regs v;
+#pragma unroll
+      for (int t = 0; t < SL::NTASK; ++t) {
+        const int j = q + t * SL::NQ;
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r)
+          v.v[t][r] = fi == 0 ? rh.v[t][r] : deriv(rh.v[t][r], -1, axis_k<T, SL::R, SL::NB>(g.ks, j, r));
+      }
+      IS0::butterflies(v, q);
+      wave_sync();  // the previous transform's reads of the tile are done
+      IS0::lds_out(v, tile, 0, q);
+      wave_sync();
+      typename ISL::Regs o;
+      middle_and_last_tw<T, P, 64, 1, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), twi, 0, q);
+      C* __restrict__ d = dst + fi * g.fs;
+      if (g.nt)
+        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
+      else
+        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
+    });
+  }
+}
+
 // adjoint: acc = sum_f conj(m_f) FFT(in_f) (m_f = 1 or -i k_last), times the
 // real kernel spectrum, inverted with pruned output; the same line walk as
 // the forward pass
@@ -1624,6 +1732,11 @@ hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const
   const int64_t blocks = (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw);
   if (adjoint)
     hipLaunchKernelGGL((k_fused_c_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
+  else if constexpr (TW::LPW == 1 && VGF_FC1)
+    if (g.nf == 2)
+      hipLaunchKernelGGL((k_fused_c1<T, P, 2>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
+    else
+      hipLaunchKernelGGL((k_fused_c1<T, P, 1>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
   else
     hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
   return hipGetLastError();
