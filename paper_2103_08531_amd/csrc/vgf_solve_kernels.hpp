@@ -919,8 +919,13 @@ __device__ __forceinline__ void grad_multiply(RegsOut& v, const RegsIn& x, const
   }
 }
 
+// Both gradient-field kernels ask for full occupancy in FP32 (64 VGPRs: the
+// allocator then spills 16 bytes per lane, measured 22% faster than one
+// 1024-thread workgroup per CU); FP64 fits two workgroups without it.
+template <typename T, int P> constexpr int grad_minw() { return Tile<T, P>::MINW * (sizeof(T) == 4 ? 2 : 1); }
+
 template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_grad(const cplx<T>* __restrict__ in,
+__global__ __launch_bounds__((Tile<T, P>::NT), (grad_minw<T, P>())) void k_fused_grad(const cplx<T>* __restrict__ in,
                                                                 cplx<T>* __restrict__ out,
                                                                 FusedGeom<T> g, GradSpec<T> sp,
                                                                 const cplx<T>* __restrict__ tw) {
@@ -951,24 +956,29 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
   typename SL::Regs rh;
   middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
   for (int fi = 0; fi < g.nf; ++fi) {
+    // this field's copies of the thread's line and position: the LDS and
+    // twiddle addresses are recomputed per field instead of held through
+    // every transform
+    int lf = l, qf = q;
+    asm volatile("" : "+v"(lf), "+v"(qf));
     typename IS0::Regs v;
-    grad_multiply<T, SL>(v, rh, g, sp, fc.colpart, neg1, g.fields[fi], -1, q);
-    IS0::butterflies(v, q);
+    grad_multiply<T, SL>(v, rh, g, sp, fc.colpart, neg1, g.fields[fi], -1, qf);
+    IS0::butterflies(v, qf);
     __syncthreads();
-    IS0::lds_out(v, lds, l, q);
+    IS0::lds_out(v, lds, lf, qf);
     __syncthreads();
     typename ISL::Regs o;
-    middle_and_last<T, P, NT, NL, LP, 1>(o, lds, tw_inverse<P>(twl), l, q);
+    middle_and_last<T, P, NT, NL, LP, 1>(o, lds, tw_inverse<P>(twl), lf, qf);
     if (cio.valid) {
       C* __restrict__ dst = out + e * g.out_es + fi * g.out_fs;
-      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
+      ISL::template store_last<true>(o, qf, [&](int j, int r, C val) { dst[cio.off<ISL::NB>(j, r)] = val; });
     }
   }
 }
 
 // adjoint: acc = sum_f conj(m_f) FFT(in_f), out = pruned inverse of acc
 template <typename T, int P>
-__global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_grad_adj(
+__global__ __launch_bounds__((Tile<T, P>::NT), (grad_minw<T, P>())) void k_fused_grad_adj(
     const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedGeom<T> g, GradSpec<T> sp,
     const cplx<T>* __restrict__ tw) {
   using C = cplx<T>;
@@ -994,20 +1004,23 @@ __global__ __launch_bounds__((Tile<T, P>::NT), (Tile<T, P>::MINW)) void k_fused_
 #pragma unroll
     for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
   for (int fi = 0; fi < g.nf; ++fi) {
+    // this field's copies of the thread's line and position (as in k_fused_grad)
+    int lf = l, qf = q;
+    asm volatile("" : "+v"(lf), "+v"(qf));
     const C* __restrict__ src = in + fi * g.in_fs;
     typename S0::Regs g0;
-    S0::template load_first<true>(g0, q, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
-    S0::template butterflies<true>(g0, q);
+    S0::template load_first<true>(g0, qf, [&](int j, int r) { return src[cio.off<S0::NB>(j, r)]; });
+    S0::template butterflies<true>(g0, qf);
     __syncthreads();
-    S0::lds_out(g0, lds, l, q);
+    S0::lds_out(g0, lds, lf, qf);
     __syncthreads();
     typename SL::Regs rh;
-    middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, l, q);
+    middle_and_last<T, P, NT, NL, LP, -1>(rh, lds, twl, lf, qf);
     typename IS0::Regs m;
-    grad_multiply<T, SL>(m, rh, g, sp, fc.colpart, neg1, g.fields[fi], 1, q);
+    grad_multiply<T, SL>(m, rh, g, sp, fc.colpart, neg1, g.fields[fi], 1, qf);
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
-      if (!SL::active(t, q)) continue;
+      if (!SL::active(t, qf)) continue;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
         acc.v[t][r].x += m.v[t][r].x;
