@@ -30,9 +30,12 @@
  *    synchronises with the host except vgf_plan_create, vgf_plan_get_kernel
  *    and vgf_plan_get_spectrum, which do. A plan owns a workspace and must be
  *    used by one stream at a time; distinct plans are independent.
- *  - Supported sizes: every n_a in {8, 12, 16, 24, 32, 48, 64, 96, 128, 192,
- *    256, 384, 512} (the padded length 2 n_a must be an FFT length the
- *    library instantiates). Other sizes return VGF_ERR_UNSUPPORTED_SIZE.
+ *  - Supported sizes: every even n_a = 2^a 3^b (a >= 1) with
+ *    8 <= n_a <= 512, i.e. n_a in {8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72,
+ *    96, 108, 128, 144, 162, 192, 216, 256, 288, 324, 384, 432, 486, 512}
+ *    (the padded length 2 n_a is an FFT length of radices 8, 4, 2 and 3 that
+ *    the library instantiates). Other sizes, odd ones included, return
+ *    VGF_ERR_UNSUPPORTED_SIZE.
  */
 #ifndef VGF_H
 #define VGF_H

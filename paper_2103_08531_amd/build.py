@@ -18,11 +18,12 @@ LIB = os.path.join(HERE, "libvgf.so")
 OBJDIR = os.path.join(ROOT, "_build", "vgf")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["vgf_api.cpp", "vgf_precompute.hip", "vgf_batch.hip", "vgf_fd.hip", "vgf_solve_f32.hip", "vgf_solve_f64.hip"]
+SOLVE_UNITS = ["vgf_solve_%s%s.hip" % (p, g) for p in ("f32", "f64") for g in ("", "_g1", "_g2", "_g3", "_g4")]
+SOURCES = ["vgf_api.cpp", "vgf_precompute.hip", "vgf_batch.hip", "vgf_fd.hip"] + SOLVE_UNITS
 # The per-solve passes are compiled without floating-point contraction: their
 # fused multiply-adds are written out (fmaT), so the rounding of every result
 # is fixed by the source and identical in every kernel instantiation.
-NO_CONTRACT = {"vgf_solve_f32.hip", "vgf_solve_f64.hip", "vgf_fd.hip"}
+NO_CONTRACT = set(SOLVE_UNITS) | {"vgf_fd.hip"}
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -12,15 +12,24 @@ template <> struct cplx_of<float> { using type = float2; };
 template <> struct cplx_of<double> { using type = double2; };
 template <typename T> using cplx = typename cplx_of<T>::type;
 
-// FFT lengths (2N) the library instantiates.
+// FFT lengths P = 2N the library instantiates: every P = 2^a 3^b with a >= 2
+// (N = P/2 even) from 16 to 1024, i.e. N = 2^a 3^b, a >= 1, 8 <= N <= 512.
+// The kernels of each length are compiled in one of four groups.
+#define VGF_P_GROUP1(X) X(16) X(24) X(32) X(36) X(48) X(64) X(72)
+#define VGF_P_GROUP2(X) X(96) X(108) X(128) X(144) X(192) X(216)
+#define VGF_P_GROUP3(X) X(256) X(288) X(324) X(384) X(432)
+#define VGF_P_GROUP4(X) X(512) X(576) X(648) X(768) X(864) X(972) X(1024)
+#define VGF_FOR_EACH_P(X) VGF_P_GROUP1(X) VGF_P_GROUP2(X) VGF_P_GROUP3(X) VGF_P_GROUP4(X)
+
 inline bool supported_fft_len(int64_t P) {
+#define VGF_CASE_LEN(PP) case PP:
   switch (P) {
-    case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 192:
-    case 256: case 384: case 512: case 768: case 1024:
-      return true;
+    VGF_FOR_EACH_P(VGF_CASE_LEN)
+    return true;
     default:
       return false;
   }
+#undef VGF_CASE_LEN
 }
 
 // Geometry of a batch of lines along a strided axis: element pos of

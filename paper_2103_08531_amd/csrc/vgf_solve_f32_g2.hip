@@ -1,0 +1,8 @@
+// FP32 per-solve passes of the FFT lengths of group 2 (VGF_P_GROUP2).
+#include "vgf_solve_kernels.hpp"
+
+namespace vgf {
+#define VGF_T float
+VGF_P_GROUP2(VGF_INSTANTIATE_P)
+#undef VGF_T
+}  // namespace vgf

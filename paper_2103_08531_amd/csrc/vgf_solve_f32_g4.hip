@@ -1,0 +1,8 @@
+// FP32 per-solve passes of the FFT lengths of group 4 (VGF_P_GROUP4).
+#include "vgf_solve_kernels.hpp"
+
+namespace vgf {
+#define VGF_T float
+VGF_P_GROUP4(VGF_INSTANTIATE_P)
+#undef VGF_T
+}  // namespace vgf

@@ -1385,10 +1385,15 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   }
   stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
   __syncthreads();
+  // the last stages' twiddle slots stay in registers when they are few
+  // (one butterfly per lane); otherwise they are read from LDS per line
+  constexpr bool TWREG = SL::NTASK * (SL::R - 1) <= 8 && ISL::NTASK * (ISL::R - 1) <= 8;
   typename SL::Tw twf;
   typename ISL::Tw twi;
-  SL::load_tw(twf, twl, q);
-  ISL::load_tw(twi, tw_inverse<P>(twl), q);
+  if constexpr (TWREG) {
+    SL::load_tw(twf, twl, q);
+    ISL::load_tw(twi, tw_inverse<P>(twl), q);
+  }
 
   for (int it = 0; it < gpw && line < g.nlines; ++it, ++line) {
     const int64_t lofs = ((int64_t)wk.k0 * wk.p1 + wk.k1) * N;
@@ -1405,6 +1410,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
     T sv[SL::NTASK][SL::R];
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
       const int j = q + t * SL::NQ;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
@@ -1417,19 +1423,23 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
     S0::lds_out(x, tile, 0, q);
     wave_sync();
     typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
-    middle_and_last_tw<T, P, 64, 1, LP, -1, 1, true>(rh, tile, twl, twf, 0, q);
+    if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, -1, 1, true>(rh, tile, twl, twf, 0, q);
+    else middle_and_last<T, P, 64, 1, LP, -1, 1, true>(rh, tile, twl, 0, q);
 #pragma unroll
-    for (int t = 0; t < SL::NTASK; ++t)
+    for (int t = 0; t < SL::NTASK; ++t) {
+      if (!SL::active(t, q)) continue;
 #pragma unroll
       for (int r = 0; r < SL::R; ++r) {
         rh.v[t][r].x *= sv[t][r];
         rh.v[t][r].y *= sv[t][r];
       }
+    }
     StaticFor<0, NF>::run([&](auto fI) {
       constexpr int fi = decltype(fI)::value;
       typename IS0::Regs v;
 #pragma unroll
       for (int t = 0; t < SL::NTASK; ++t) {
+        if (!SL::active(t, q)) continue;
         const int j = q + t * SL::NQ;
 #pragma unroll
         for (int r = 0; r < SL::R; ++r)
@@ -1440,7 +1450,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       IS0::lds_out(v, tile, 0, q);
       wave_sync();
       typename ISL::Regs o;
-      middle_and_last_tw<T, P, 64, 1, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), twi, 0, q);
+      if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), twi, 0, q);
+      else middle_and_last<T, P, 64, 1, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), 0, q);
       C* __restrict__ d = dst + fi * g.fs;
       if (g.nt)
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
@@ -1550,8 +1561,6 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-#define VGF_FOR_EACH_P(X) \
-  X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 template <typename T, int P>
 hipError_t launch_r2c_p(const R2CArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
@@ -1754,6 +1763,27 @@ hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const
     hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
   return hipGetLastError();
 }
+
+// The per-length launchers of one precision VGF_T: declared extern in the
+// dispatch unit (vgf_solve_f32.hip / vgf_solve_f64.hip) and instantiated in
+// the unit of the length's group (vgf_solve_f32_g1.hip, ...), so the lengths
+// compile in parallel.
+#define VGF_LAUNCHERS_P(PFX, PP)                                                                           \
+  PFX hipError_t launch_r2c_p<VGF_T, PP>(const R2CArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t);         \
+  PFX hipError_t launch_c2r_p<VGF_T, PP>(const C2RArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t);         \
+  PFX hipError_t launch_c2c_fwd_p<VGF_T, PP>(int, const C2CFwdArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
+  PFX hipError_t launch_c2c_inv_p<VGF_T, PP>(int, const C2CInvArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
+  PFX hipError_t launch_fused_p<VGF_T, PP>(int, bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedGeom<VGF_T>&, \
+                                           const VGF_T*, const cplx<VGF_T>*, hipStream_t);                 \
+  PFX hipError_t launch_fused_grad_p<VGF_T, PP>(bool, const cplx<VGF_T>*, cplx<VGF_T>*,                     \
+                                                const FusedGeom<VGF_T>&, const GradSpec<VGF_T>&,           \
+                                                const cplx<VGF_T>*, hipStream_t);                          \
+  PFX hipError_t launch_r2c_s_p<VGF_T, PP>(int, const R2CSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
+  PFX hipError_t launch_c2r_s_p<VGF_T, PP>(int, const C2RSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
+  PFX hipError_t launch_fused_c_p<VGF_T, PP>(bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
+                                             const VGF_T*, const cplx<VGF_T>*, hipStream_t);
+#define VGF_EXTERN_P(PP) VGF_LAUNCHERS_P(extern template, PP)
+#define VGF_INSTANTIATE_P(PP) VGF_LAUNCHERS_P(template, PP)
 
 #define VGF_CASE_R2CS(PP) case PP: return launch_r2c_s_p<VGF_T, PP>(variant, a, tw, s);
 #define VGF_CASE_C2RS(PP) case PP: return launch_c2r_s_p<VGF_T, PP>(variant, a, tw, s);

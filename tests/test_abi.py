@@ -66,6 +66,9 @@ def test_plan_create_rejects_bad_arguments(V):
     assert _create(V, n=(7, 8, 8))[0] == -2
     assert _create(V, n=(1024, 32, 32))[0] == -2
     assert _create(V, dim=2, n=(640, 64))[0] == -2
+    # odd sizes and factors other than 2 and 3 are outside the rule
+    for bad in ((9, 16, 16), (27, 16, 16), (16, 20, 16), (16, 16, 1024), (40, 16, 16), (16, 16, 243)):
+        assert _create(V, n=bad)[0] == -2, bad
 
 
 def test_plan_create_rejects_L_outside_window(V, orc):

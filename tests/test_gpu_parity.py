@@ -102,7 +102,10 @@ def test_mixture_2d_512(method, precision):
     plan.close()
 
 
-SIZE_CASES = [(2, 96), (2, 192), (2, 384), (3, 24), (3, 48), (3, 64)]
+SIZE_CASES = [(2, 96), (2, 192), (2, 384), (3, 24), (3, 48), (3, 64),
+              # lengths 2N with two or more factors 3 (radix plans 4-3-3, 8-3-3, 2-3-3-3, ...)
+              (2, 18), (2, 36), (2, 54), (2, 72), (2, 108), (2, 144), (2, 162), (2, 216), (2, 288),
+              (2, 324), (2, 432), (2, 486), (3, 18), (3, 36), (3, 54), (3, 72)]
 
 
 @pytest.mark.parametrize("dim,N", SIZE_CASES)
@@ -124,7 +127,8 @@ def test_fft_lengths(dim, N):
         plan.close()
 
 
-LONG_AXIS_CASES = [(384, 8, 12), (8, 384, 8), (8, 12, 384), (512, 8, 8), (8, 512, 12), (12, 8, 512)]
+LONG_AXIS_CASES = [(384, 8, 12), (8, 384, 8), (8, 12, 384), (512, 8, 8), (8, 512, 12), (12, 8, 512),
+                   (288, 8, 12), (8, 288, 8), (8, 12, 288), (486, 8, 8), (8, 432, 12), (12, 8, 324)]
 
 
 @pytest.mark.parametrize("n", LONG_AXIS_CASES)

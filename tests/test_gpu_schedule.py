@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 CASES = [((32, 32, 32), "f32", "contiguous"), ((48, 48, 48), "f32", "contiguous"),
          ((24, 16, 32), "f64", "contiguous"), ((64, 48), "f64", "contiguous"),
          ((128, 128), "f32", "contiguous"), ((64, 64, 64), "f64", "contiguous"),
-         ((32, 32, 32), "f32", "axis0"), ((24, 16, 32), "f64", "axis0"), ((64, 48), "f64", "axis0")]
+         ((32, 32, 32), "f32", "axis0"), ((24, 16, 32), "f64", "axis0"), ((64, 48), "f64", "axis0"),
+         ((36, 18, 54), "f64", "contiguous"), ((72, 144), "f32", "contiguous"), ((36, 18, 54), "f32", "axis0")]
 
 
 def _tunable(dim, layout):
