@@ -280,18 +280,25 @@ void vgf_batch_destroy(vgf_batch batch);
  * VGF_PASS_C2R. A value holds two bits: bit 0 is the variant of the pass's
  * first launch, bit 1 that of its later launches (the inverse passes launch
  * once per group of outputs, the two-output launch first; adjoints may
- * launch a pass more than once). Passes that are not strided (and the 2D
- * middle passes, which do not exist) only take 0. */
+ * launch a pass more than once). In the default layout the multiply pass
+ * along the contiguous axis (VGF_PASS_FUSED) has schedules too, its value
+ * taken whole: bit 0 halves the lanes that share one line (twice the lines
+ * per wavefront and the butterflies per lane), bit 1 lets each wavefront
+ * walk 16 instead of 4 lines (fewer, longer workgroups); the walk is cut
+ * where the grid would fall below 2048 workgroups. Passes without variants
+ * (and the 2D middle passes, which do not exist) only take 0. */
 enum { VGF_PASS_R2C = 0, VGF_PASS_C2C_FWD = 1, VGF_PASS_FUSED = 2, VGF_PASS_C2C_INV = 3,
        VGF_PASS_C2R = 4, VGF_NUM_PASSES = 5 };
 
-/* Chooses the plan's schedule by measurement: two warm-up solves per
- * variant, then `reps` rounds that each run, per variant, two solves of
- * (rho, phi, E) (arguments as vgf_solve), the second timed with HIP events
- * after every launch on `stream`. For each pass, its first launch and its later
- * launches each take their fastest repetition per variant and keep the
- * default variant unless another is more than 2% faster; a pass launched
- * once gives both bits its first launch's choice. A schedule so assembled
+/* Chooses the plan's schedule by measurement over four candidates (v = 0..3:
+ * every strided pass at tile variant v & 1, the contiguous multiply pass at
+ * value v): two warm-up solves per candidate, then `reps` rounds that each
+ * run, per candidate, two solves of (rho, phi, E) (arguments as vgf_solve),
+ * the second timed with HIP events after every launch on `stream`. For each
+ * pass, its first launch and its later launches each take their fastest
+ * repetition per value and keep the default unless another value is more
+ * than 2% faster; a strided pass launched once gives both bits its first
+ * launch's choice. A schedule so assembled
  * is kept only if it also beats the default on the whole solve by 1% (two
  * more solves per round and candidate). phi / E receive solve results.
  * Synchronises `stream`.

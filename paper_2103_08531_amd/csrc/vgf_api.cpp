@@ -736,7 +736,8 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
     fin = b.x2;
   }
-  VGF_LAUNCH(kPassFused, vgf::launch_fused_c<T>((int)p->P[d - 1], false, fin, b.y, g, (const T*)p->spec, tw(d - 1), s));
+  VGF_LAUNCH(kPassFused, vgf::launch_fused_c<T>((int)p->P[d - 1], sched[kPassFused], false, fin, b.y, g,
+                                                (const T*)p->spec, tw(d - 1), s));
   // axis-0 inputs: phi's spectrum, and the spectra of E_1 (3D) and E_last
   const cplx<T>* zphi = b.y;
   const cplx<T>* zf[2] = {nullptr, nullptr};  // E_1, E_2 (3D) or E_1 (2D)
@@ -878,13 +879,13 @@ vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool m
 }
 
 // ---------------------------------------------------------------------------
-// Autotuning of the tile schedules. Each candidate schedule (every tunable
-// pass at variant v) runs two warm-up enqueues, then the candidates run
-// interleaved `reps` times; HIP events at the pass boundaries give each
-// pass's time, each pass takes its fastest repetition per variant and keeps
-// the default unless another variant is more than 2% faster. The choice is
-// cached per process for the grid, precision, outputs, field mode and number
-// of entries per launch.
+// Autotuning of the schedules. Four candidate schedules (every strided pass
+// at tile width v & 1, the contiguous multiply pass at value v) run two
+// warm-up enqueues each, then the candidates run interleaved `reps` times;
+// HIP events at the pass boundaries give each pass's time, each pass takes
+// its fastest repetition per value and keeps the default unless another
+// value is more than 2% faster. The choice is cached per process for the
+// grid, precision, outputs, field mode and number of entries per launch.
 // ---------------------------------------------------------------------------
 struct TuneKey {
   int prec, dim, outs, count;
@@ -903,54 +904,59 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, std::array<int, kPasses>> g_tune_cache;
 
-// passes with tile-schedule variants: the strided ones of the plan's layout
+// passes with schedule variants: the strided ones of the plan's layout (tile
+// width) and, in the default layout, the multiply pass along the contiguous
+// axis (lanes per line and walk length)
 bool pass_tunable(vgf_plan p, int pass) {
   if (p->gradk) return p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI);
   if (p->contig)
-    return pass == kPassR2C || pass == kPassC2R || (p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
+    return pass == kPassR2C || pass == kPassC2R || pass == kPassFused ||
+           (p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
   return pass == kPassFused || (p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
 }
+// the contiguous multiply pass takes its schedule value (0..3) whole; the
+// strided passes hold one tile-width bit per launch class
+bool pass_whole_value(vgf_plan p, int pass) { return p->contig && pass == kPassFused; }
 
 // run(sched, events) enqueues one solve (or one group of entries) with the
 // given schedule, recording the pass boundaries into events when non-null.
 template <class Run>
 vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best, hipError_t* herr) {
-  const int dim = p->dim;
-  constexpr int NV = vgf_tile_variants();
-  // events and launch tags [rep][variant][mark]
-  std::vector<hipEvent_t> ev((size_t)reps * NV * kMaxMarks, nullptr);
-  std::vector<int> tags((size_t)reps * NV * kMaxMarks, -1);
-  std::vector<int> nmark((size_t)reps * NV, 0);
+  // candidate v (0..3) sets every strided pass to tile width v & 1 (both
+  // launch classes) and the contiguous multiply pass to schedule value v
+  constexpr int NC = 4;
+  static_assert(vgf_tile_variants() == 2, "schedule values hold one bit per launch class");
+  std::vector<hipEvent_t> ev((size_t)reps * NC * kMaxMarks, nullptr);
+  std::vector<int> tags((size_t)reps * NC * kMaxMarks, -1);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-  // variant v on every launch of every tunable pass (both bits of the value)
-  static_assert(NV == 2, "schedule values hold one bit per launch class");
-  int sched[NV][kPasses];
-  for (int v = 0; v < NV; ++v)
-    for (int k = 0; k < kPasses; ++k) sched[v][k] = pass_tunable(p, k) ? v * 3 : 0;
+  int sched[NC][kPasses];
+  for (int v = 0; v < NC; ++v)
+    for (int k = 0; k < kPasses; ++k)
+      sched[v][k] = !pass_tunable(p, k) ? 0 : pass_whole_value(p, k) ? v : (v & 1) * 3;
   vgf_status st = VGF_OK;
-  // warm-up of every variant, then the variants interleaved rep by rep so
-  // that clock ramps bias none of them; each timed solve follows an untimed
-  // one of the same variant, so that it sees the caches a run of that
-  // schedule leaves (a pass's time depends on what ran before it)
+  // warm-up of every candidate, then the candidates interleaved rep by rep
+  // so that clock ramps bias none of them; each timed solve follows an
+  // untimed one of the same candidate, so that it sees the caches a run of
+  // that schedule leaves (a pass's time depends on what ran before it)
   for (int w = 0; w < 2 && st == VGF_OK && e == hipSuccess; ++w)
-    for (int v = 0; v < NV && st == VGF_OK; ++v) st = run(sched[v], nullptr, nullptr);
+    for (int v = 0; v < NC && st == VGF_OK; ++v) st = run(sched[v], nullptr, nullptr);
   for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
-    for (int v = 0; v < NV && st == VGF_OK; ++v) {
-      const size_t o = ((size_t)r * NV + v) * kMaxMarks;
+    for (int v = 0; v < NC && st == VGF_OK; ++v) {
+      const size_t o = ((size_t)r * NC + v) * kMaxMarks;
       st = run(sched[v], nullptr, nullptr);
       if (st == VGF_OK) st = run(sched[v], &ev[o], &tags[o]);
     }
-  // fastest repetition under each variant of each pass's first launch
-  // (class 0) and of its later launches together (class 1)
-  double t[NV][kPasses][2];
+  // fastest repetition of each pass's first launch (class 0) and of its
+  // later launches together (class 1) under each candidate
+  double t[NC][kPasses][2];
   bool later[kPasses] = {};
-  for (int v = 0; v < NV; ++v)
+  for (int v = 0; v < NC; ++v)
     for (int k = 0; k < kPasses; ++k) t[v][k][0] = t[v][k][1] = 1e30;
   if (st == VGF_OK && e == hipSuccess) e = hipStreamSynchronize(s);
   for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
-    for (int v = 0; v < NV && e == hipSuccess; ++v) {
-      const size_t o = ((size_t)r * NV + v) * kMaxMarks;
+    for (int v = 0; v < NC && e == hipSuccess; ++v) {
+      const size_t o = ((size_t)r * NC + v) * kMaxMarks;
       double pass_ms[kPasses][2] = {};
       int seen[kPasses] = {};
       for (int i = 0; i + 1 < kMaxMarks && tags[o + i] >= 0 && e == hipSuccess; ++i) {
@@ -963,19 +969,27 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
       for (int k = 0; k < kPasses; ++k)
         for (int c = 0; c < 2; ++c) t[v][k][c] = std::min(t[v][k][c], pass_ms[k][c]);
     }
-  // per launch class, keep the default unless another variant is faster by
-  // more than 2%; a pass without later launches gives them its first
-  // launch's variant (the adjoint may launch it more than once)
+  // per pass (and launch class), keep the default unless another value is
+  // faster by more than 2%; a strided pass without later launches gives them
+  // its first launch's width (the adjoint may launch it more than once)
   bool changed = false;
   for (int k = 0; k < kPasses; ++k) {
     best[k] = 0;
     if (!pass_tunable(p, k)) continue;
-    int b[2] = {0, 0};
-    for (int c = 0; c < 2; ++c)
-      for (int v = 1; v < NV; ++v)
-        if (t[v][k][c] < 0.98 * t[b[c]][k][c]) b[c] = v;
-    if (!later[k]) b[1] = b[0];
-    best[k] = b[0] | (b[1] << 1);
+    if (pass_whole_value(p, k)) {
+      int b = 0;
+      for (int v = 1; v < NC; ++v)
+        if (t[v][k][0] < 0.98 * t[b][k][0]) b = v;
+      best[k] = b;
+    } else {
+      int b[2] = {0, 0};
+      for (int c = 0; c < 2; ++c) {
+        const double w0 = std::min(t[0][k][c], t[2][k][c]), w1 = std::min(t[1][k][c], t[3][k][c]);
+        if (w1 < 0.98 * w0) b[c] = 1;
+      }
+      if (!later[k]) b[1] = b[0];
+      best[k] = b[0] | (b[1] << 1);
+    }
     changed = changed || best[k] != 0;
   }
   // a pass's time also depends on the passes before it (caches, tails), so
@@ -985,7 +999,7 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
     double total[2] = {1e30, 1e30};
     for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
       for (int c = 0; c < 2 && st == VGF_OK; ++c) {
-        const size_t o = ((size_t)r * NV + c) * kMaxMarks;
+        const size_t o = ((size_t)r * NC + c) * kMaxMarks;
         for (int i = 0; i < kMaxMarks; ++i) tags[o + i] = -1;
         st = run(cand[c], nullptr, nullptr);
         if (st == VGF_OK) st = run(cand[c], &ev[o], &tags[o]);
@@ -993,7 +1007,7 @@ vgf_status tune_schedule(vgf_plan p, int reps, hipStream_t s, Run run, int* best
     if (st == VGF_OK && e == hipSuccess) e = hipStreamSynchronize(s);
     for (int r = 0; r < reps && st == VGF_OK && e == hipSuccess; ++r)
       for (int c = 0; c < 2 && e == hipSuccess; ++c) {
-        const size_t o = ((size_t)r * NV + c) * kMaxMarks;
+        const size_t o = ((size_t)r * NC + c) * kMaxMarks;
         int last = 0;
         while (last + 1 < kMaxMarks && tags[o + last] >= 0) ++last;
         float ms = 0.f;
@@ -1222,7 +1236,7 @@ vgf_status adjoint_c_entries(vgf_plan p, const AdjEntries<T>& en, const int* sch
       VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 1), f2, tw(1), s));
       g.fields[g.nf++] = 1;
     }
-    VGF_RUN(vgf::launch_fused_c<T>((int)p->P[2], true, b.y, b.x2, g, (const T*)p->spec, tw(2), s));
+    VGF_RUN(vgf::launch_fused_c<T>((int)p->P[2], sched[kPassFused], true, b.y, b.x2, g, (const T*)p->spec, tw(2), s));
     vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
@@ -1235,7 +1249,7 @@ vgf_status adjoint_c_entries(vgf_plan p, const AdjEntries<T>& en, const int* sch
       VGF_RUN(r2c(b.y + fs, 1, 0, 0, 0, true, false));
       g.fields[g.nf++] = 1;
     }
-    VGF_RUN(vgf::launch_fused_c<T>((int)p->P[1], true, b.y, b.x1, g, (const T*)p->spec, tw(1), s));
+    VGF_RUN(vgf::launch_fused_c<T>((int)p->P[1], sched[kPassFused], true, b.y, b.x1, g, (const T*)p->spec, tw(1), s));
   }
   vgf::C2RSArgs<T> ca{};
   ca.in = b.x1;

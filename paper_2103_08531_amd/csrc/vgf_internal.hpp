@@ -192,9 +192,11 @@ template <typename T>
 hipError_t launch_r2c_s(int P, int variant, const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 template <typename T>
 hipError_t launch_c2r_s(int P, int variant, const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s);
+// schedule (0..3) of the multiply pass: bit 0 halves the lanes per line,
+// bit 1 lengthens each wavefront's walk over lines; results do not depend on it
 template <typename T>
-hipError_t launch_fused_c(int P, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
-                          const T* spec, const cplx<T>* tw, hipStream_t s);
+hipError_t launch_fused_c(int P, int schedule, bool adjoint, const cplx<T>* in, cplx<T>* out,
+                          const FusedCGeom<T>& g, const T* spec, const cplx<T>* tw, hipStream_t s);
 
 // Spectra of the gradient-kernel fields: s[0] the kernel spectrum octant,
 // s[1 + a] the octant of T_a (the 2N spectrum of the odd gradient kernel of

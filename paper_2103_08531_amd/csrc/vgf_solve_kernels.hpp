@@ -205,9 +205,16 @@ template <int P> constexpr int wave_nq() {
 #define VGF_FC1 1
 #endif
 constexpr int64_t kFusedCMinBlocks = 2048;
-template <typename T, int P> struct TileW {
-  static constexpr int NQ = wave_nq<P>();  // lanes per line pair
-  static constexpr int LPW = 64 / NQ;      // line pairs per wavefront
+// V = 1 (the multiply pass's second lane schedule): half the lanes per line,
+// twice the lines per wavefront and twice the butterflies per lane, where the
+// four wavefronts' tiles then still fit 64 KiB of LDS (else as V = 0); the
+// per-line arithmetic is the same.
+template <typename T, int P> constexpr bool half_lanes_fit() {
+  return wave_nq<P>() > 1 && 4 * (128 / wave_nq<P>()) * line_pitch<P>() * (int)sizeof(cplx<T>) <= 65536;
+}
+template <typename T, int P, int V = 0> struct TileW {
+  static constexpr int NQ = (V == 1 && half_lanes_fit<T, P>()) ? wave_nq<P>() / 2 : wave_nq<P>();  // lanes per line (pair)
+  static constexpr int LPW = 64 / NQ;      // lines (line pairs) per wavefront
   static constexpr int WPB = 4;            // wavefronts per workgroup
   static constexpr int NT = 64 * WPB;
   static constexpr int LP = line_pitch<P>();
@@ -1234,12 +1241,12 @@ struct LineWalk {
 // phi's spectrum and, when requested, as -i k_last times it (E_last). The
 // walk over several groups shares the twiddle staging and the index set-up
 // among them and needs no per-line division.
-template <typename T, int P>
-__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_c(
+template <typename T, int P, int V>
+__global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) void k_fused_c(
     const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, const T* __restrict__ spec,
     const cplx<T>* __restrict__ tw, int gpw) {
   using C = cplx<T>;
-  using TW = TileW<T, P>;
+  using TW = TileW<T, P, V>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
   using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
@@ -1464,12 +1471,12 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
 // adjoint: acc = sum_f conj(m_f) FFT(in_f) (m_f = 1 or -i k_last), times the
 // real kernel spectrum, inverted with pruned output; the same line walk as
 // the forward pass
-template <typename T, int P>
-__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_c_adj(
+template <typename T, int P, int V>
+__global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) void k_fused_c_adj(
     const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, const T* __restrict__ spec,
     const cplx<T>* __restrict__ tw, int gpw) {
   using C = cplx<T>;
-  using TW = TileW<T, P>;
+  using TW = TileW<T, P, V>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
   using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
@@ -1740,28 +1747,37 @@ hipError_t launch_c2r_s_p(int variant, const C2RSArgs<T>& a, const cplx<T>* tw, 
   return variant == 1 ? launch_c2r_s_v<T, P, 1>(a, tw, s) : launch_c2r_s_v<T, P, 0>(a, tw, s);
 }
 
-template <typename T, int P>
-hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
+// Multiply pass along the contiguous axis. schedule bit 0: lanes per line
+// (TileW variant), bit 1: lines each wavefront walks (VGF_FC_GPW, or 16).
+template <typename T, int P, int V>
+hipError_t launch_fused_c_v(int schedule, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
                             const T* spec, const cplx<T>* tw, hipStream_t s) {
-  using TW = TileW<T, P>;
-  if (g.nf == 0 || g.nlines == 0) return hipSuccess;
-  if (g.nf > 2 || (g.lpe > 0 && g.nlines % g.lpe != 0)) return hipErrorInvalidValue;
-  // line groups per wavefront: up to VGF_FC_GPW, fewer where the grid would
-  // drop below kFusedCMinBlocks workgroups
+  using TW = TileW<T, P, V>;
+  // line groups per wavefront: the schedule's walk length, shortened where
+  // the grid would drop below kFusedCMinBlocks workgroups
   const int64_t groups = (g.nlines + TW::LPW - 1) / TW::LPW;
-  int gpw = VGF_FC_GPW;
+  int gpw = (schedule & 2) ? 16 : VGF_FC_GPW;
   while (gpw > 1 && (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw) < kFusedCMinBlocks) gpw /= 2;
   const int64_t blocks = (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw);
   if (adjoint)
-    hipLaunchKernelGGL((k_fused_c_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
+    hipLaunchKernelGGL((k_fused_c_adj<T, P, V>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
   else if constexpr (TW::LPW == 1 && VGF_FC1)
     if (g.nf == 2)
       hipLaunchKernelGGL((k_fused_c1<T, P, 2>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
     else
       hipLaunchKernelGGL((k_fused_c1<T, P, 1>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
   else
-    hipLaunchKernelGGL((k_fused_c<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
+    hipLaunchKernelGGL((k_fused_c<T, P, V>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, spec, tw, gpw);
   return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_fused_c_p(int schedule, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
+                            const T* spec, const cplx<T>* tw, hipStream_t s) {
+  if (g.nf == 0 || g.nlines == 0) return hipSuccess;
+  if (g.nf > 2 || (g.lpe > 0 && g.nlines % g.lpe != 0) || schedule < 0 || schedule > 3) return hipErrorInvalidValue;
+  return (schedule & 1) ? launch_fused_c_v<T, P, 1>(schedule, adjoint, in, out, g, spec, tw, s)
+                        : launch_fused_c_v<T, P, 0>(schedule, adjoint, in, out, g, spec, tw, s);
 }
 
 // The per-length launchers of one precision VGF_T: declared extern in the
@@ -1780,14 +1796,14 @@ hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const
                                                 const cplx<VGF_T>*, hipStream_t);                          \
   PFX hipError_t launch_r2c_s_p<VGF_T, PP>(int, const R2CSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
   PFX hipError_t launch_c2r_s_p<VGF_T, PP>(int, const C2RSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
-  PFX hipError_t launch_fused_c_p<VGF_T, PP>(bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
+  PFX hipError_t launch_fused_c_p<VGF_T, PP>(int, bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
                                              const VGF_T*, const cplx<VGF_T>*, hipStream_t);
 #define VGF_EXTERN_P(PP) VGF_LAUNCHERS_P(extern template, PP)
 #define VGF_INSTANTIATE_P(PP) VGF_LAUNCHERS_P(template, PP)
 
 #define VGF_CASE_R2CS(PP) case PP: return launch_r2c_s_p<VGF_T, PP>(variant, a, tw, s);
 #define VGF_CASE_C2RS(PP) case PP: return launch_c2r_s_p<VGF_T, PP>(variant, a, tw, s);
-#define VGF_CASE_FC(PP) case PP: return launch_fused_c_p<VGF_T, PP>(adjoint, in, out, g, spec, tw, s);
+#define VGF_CASE_FC(PP) case PP: return launch_fused_c_p<VGF_T, PP>(schedule, adjoint, in, out, g, spec, tw, s);
 #define VGF_CASE_R2C(PP) case PP: return launch_r2c_p<VGF_T, PP>(a, tw, s);
 #define VGF_CASE_FGRAD(PP) case PP: return launch_fused_grad_p<VGF_T, PP>(adjoint, in, out, g, sp, tw, s);
 #define VGF_CASE_C2R(PP) case PP: return launch_c2r_p<VGF_T, PP>(a, tw, s);
@@ -1831,7 +1847,7 @@ hipError_t launch_fused_c_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2RS) default: return hipErrorInvalidValue; }          \
   }                                                                                             \
   template <>                                                                                   \
-  hipError_t launch_fused_c<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,            \
+  hipError_t launch_fused_c<T>(int P, int schedule, bool adjoint, const cplx<T>* in, cplx<T>* out,            \
                                const FusedCGeom<T>& g, const T* spec, const cplx<T>* tw,        \
                                hipStream_t s) {                                                 \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_FC) default: return hipErrorInvalidValue; }            \
