@@ -1878,9 +1878,14 @@ vgf_status batch_capture(vgf_batch b, bool want_phi, bool want_E) {
   hipError_t e = hipStreamBeginCapture(b->cs, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return batch_hip(b, e);
   vgf_status st = VGF_OK;
-  e = hipEventRecord(b->fork, b->cs);
-  if (e != hipSuccess) st = batch_hip(b, e);
-  if (st == VGF_OK) st = batch_enqueue_groups(b, want_phi, want_E, true, b->cs);
+  // several groups run as parallel branches (fork / join events); a single
+  // group is captured as one chain of launches, without event nodes
+  const bool branches = b->groups.size() > 1;
+  if (branches) {
+    e = hipEventRecord(b->fork, b->cs);
+    if (e != hipSuccess) st = batch_hip(b, e);
+  }
+  if (st == VGF_OK) st = batch_enqueue_groups(b, want_phi, want_E, branches, b->cs);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(b->cs, &graph);  // always ends the capture
   if (st == VGF_OK && e != hipSuccess) st = batch_hip(b, e);
