@@ -219,6 +219,66 @@ def write_traffic_profile(fetch_csv, fetch_out, write_csv, write_out, command):
     print(TRAFFIC_JSON)
 
 
+COUNTERS_MD = os.path.join(PROFILES, "vgf_solve_beam_3d_256_counters.md")
+# one rocprofv3 --pmc run per set (at most 8 SQ counters per run)
+PMC_SETS = (("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CU_CYCLES", "SQ_WAVE_CYCLES"),
+            ("SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS",
+             "SQ_WAIT_INST_ANY"))
+
+
+def digest_pmc(csvs, outs):
+    """Per-kernel means over the dispatches of the SQ counters of rocprofv3
+    --pmc runs of the bench (one counter set per run). Every profiled run
+    must have run these sources."""
+    src = kernel_source_hash()
+    for path in outs:
+        if _bench_line(path).get("source_hash") != src:
+            raise SystemExit("%s was measured on other sources than these" % path)
+    per = {}
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            if "vgf::" not in r["Kernel_Name"]:
+                continue
+            d = per.setdefault(_short_name(r["Kernel_Name"]), {"vgpr": r["VGPR_Count"], "lds": r["LDS_Block_Size"]})
+            d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = {}
+    for name, d in per.items():
+        out[name] = {"vgpr_field": d.pop("vgpr"), "lds_bytes": d.pop("lds")}
+        for c, v in d.items():
+            out[name][c] = sum(v) / len(v)
+            out[name]["dispatches"] = len(v)
+    return src, out
+
+
+def write_counters_profile(csvs, outs, command):
+    src, per = digest_pmc(csvs, outs)
+    nlines = 257 * 512  # multiply-pass lines of a 256^3 solve (H0 x P1)
+    md = ["# SQ counters per kernel: VGF solve, beam_3d_256 (3D 256^3, phi+E), FP32 and FP64", "",
+          "rocprofv3 --pmc runs of the bench, one counter set per run, means over each kernel's dispatches "
+          "(the run autotunes the tile schedules, so both variants of the strided kernels appear). Counts are "
+          "wave-level instructions summed over the chip; SQ_ACTIVE_INST_* and SQ_LDS_BANK_CONFLICT are "
+          "cycles. Per-line figures divide by the 131 584 lines of the multiply pass.", "",
+          "Commands:", "", "```", command, "```", "",
+          "| kernel | VALU instr | VALU instr per line | LDS instr | LDS active | bank-conflict cycles | "
+          "conflict / LDS active | wait LDS / wait any | busy CU cycles | VGPR field |",
+          "|---|---|---|---|---|---|---|---|---|---|"]
+    for name in sorted(per):
+        v = per[name]
+        g = lambda c: v.get(c, float("nan"))
+        per_line = "%.0f" % (g("SQ_INSTS_VALU") / nlines) if "fused_c" in name else "-"
+        md.append("| %s | %.3g | %s | %.3g | %.3g | %.3g | %.2f | %.2f | %.3g | %s |" % (
+            name, g("SQ_INSTS_VALU"), per_line, g("SQ_INSTS_LDS"), g("SQ_ACTIVE_INST_LDS"),
+            g("SQ_LDS_BANK_CONFLICT"), g("SQ_LDS_BANK_CONFLICT") / g("SQ_ACTIVE_INST_LDS"),
+            g("SQ_WAIT_INST_LDS") / g("SQ_WAIT_INST_ANY"), g("SQ_BUSY_CU_CYCLES"), v["vgpr_field"]))
+    md += ["", "VGPR field: rocprofv3's VGPR_Count column, which counts registers in units of two here "
+           "(a kernel the compiler reports at 80 VGPRs shows 40).", "",
+           "Source hash (sha256 of the library code, comments and whitespace ignored, and its build script, "
+           "that the counters describe): `%s`" % src, ""]
+    with open(COUNTERS_MD, "w") as f:
+        f.write("\n".join(md))
+    print(COUNTERS_MD)
+
+
 WORKLOAD_TITLES = {
     "batch_3d_mixed": "64 FP32 grids of N in {32, 48, 64, 96, 128}, phi + E: one solve per grid, grouped "
                       "launches, one replayed graph, and the graph after autotuning",
@@ -524,9 +584,15 @@ def run_small_configs(vgf, torch, workloads, steps, warmup, seed):
             plan = vgf.Plan(ch.n, ch.h, method=method, precision="f64")
             phi = torch.empty(ch.n, dtype=torch.float64, device="cuda")
             E = torch.empty((len(ch.n),) + ch.n, dtype=torch.float64, device="cuda")
-            plan.autotune(rho, phi, E, reps=3)
+            sched = plan.autotune(rho, phi, E, reps=3)
             ms = time_fn(torch, lambda: plan.solve(rho, phi, E), max(steps, 50), warmup)
-            res[method] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms}
+            res[method] = {"ms_per_solve": ms, "solves_per_s": 1e3 / ms, "schedule": list(sched)}
+            if any(sched):
+                # what the tuned schedule gains over the default one
+                plan.schedule = (0, 0, 0, 0, 0)
+                ms0 = time_fn(torch, lambda: plan.solve(rho, phi, E), max(steps, 50), warmup)
+                plan.schedule = sched
+                res[method]["ms_per_solve_default_schedule"] = ms0
             # the same solve replayed as one captured graph (a one-entry batch)
             batch = vgf.Batch([plan], graph=True)
             ms_g = time_fn(torch, lambda: batch.solve([rho], [phi], [E]), max(steps, 50), warmup)
@@ -807,6 +873,10 @@ def main():
                          "the outputs of the two profiled bench runs")
     ap.add_argument("--digest-trace", nargs=2, metavar=("TRACE_CSV", "BENCH_JSON"),
                     help="write the kernel-trace profile from a rocprofv3 kernel_trace.csv file")
+    ap.add_argument("--digest-pmc", nargs="+", metavar="CSV_OR_OUT",
+                    help="write profiles/vgf_solve_beam_3d_256_counters.md from rocprofv3 --pmc "
+                         "counter_collection.csv files and the outputs of their profiled bench runs "
+                         "(all CSV files first, then the same number of outputs)")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the profile")
     ap.add_argument("--plan-only", action="store_true",
                     help="create the 256^3 and 512^2 plans twice each, print their creation times, exit")
@@ -835,6 +905,10 @@ def main():
         return
     if args.digest_counters:
         write_traffic_profile(*args.digest_counters, command=args.command)
+        return
+    if args.digest_pmc:
+        half = len(args.digest_pmc) // 2
+        write_counters_profile(args.digest_pmc[:half], args.digest_pmc[half:], args.command)
         return
     if args.digest_trace:
         write_trace_profile(args.digest_trace[0], args.digest_trace[1], args.command)
