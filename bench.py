@@ -411,7 +411,7 @@ def launch_model(n, prec_bytes):
     return [
         ("r2c", "k_r2c_s<{t}, %d, 1, {v}>" % P, real + x1),
         ("c2c_fwd", "k_c2c_fwd<{t}, %d, 1, {v}>" % P, x1 + x2),
-        ("fused", "k_fused_c<{t}, %d>" % P, x2 + spec + 2 * x2),
+        ("fused", "k_fused_c{fc}<{t}, %d, {fv}>" % P, x2 + spec + 2 * x2),
         ("c2c_inv", "k_c2c_inv<{t}, %d, 3, {v}>" % P, 2 * x2 + 3 * x1),
         ("c2r", "k_c2r_s<{t}, %d, 4, {v}>" % P, 3 * x1 + 4 * real),
     ]
@@ -450,12 +450,35 @@ def launch_indices(model):
     return out
 
 
+def wave_lanes(P):
+    """Lanes that share one line in the contiguous multiply pass (a power of
+    two up to P/8 and 64)."""
+    nq = 1
+    while nq * 2 <= P // 8 and nq * 2 <= 64:
+        nq *= 2
+    return nq
+
+
 def launch_kernel_name(name_pattern, prec, schedule, pass_name, idx=0):
-    """Concrete kernel name of a pass's launch number idx under a tile
-    schedule (bit 0 of the pass's value: its first launch; bit 1: the later
-    ones)."""
-    v = (schedule[PASS_INDEX[pass_name]] >> (1 if idx > 0 else 0)) & 1
-    return name_pattern.format(t="float" if prec == "f32" else "double", v=v)
+    """Concrete kernel name of a pass's launch number idx under a schedule.
+    Strided passes: bit 0 of the pass's value is the tile width of its first
+    launch, bit 1 that of the later ones. The contiguous multiply pass takes
+    its value whole: bit 0 halves the lanes per line where four such tiles
+    fit 64 KiB of LDS; one line per wavefront (64 lanes) runs k_fused_c1 with
+    the field count (2) as template argument, otherwise k_fused_c with the
+    lane variant."""
+    t = "float" if prec == "f32" else "double"
+    value = schedule[PASS_INDEX[pass_name]]
+    if pass_name == "fused":
+        P = int(re.search(r", (\d+), \{fv\}", name_pattern).group(1))
+        nq = wave_lanes(P)
+        cb = 8 if prec == "f32" else 16
+        half = (value & 1) and nq > 1 and 4 * (128 // nq) * (P + P // 8) * cb <= 65536
+        if nq // (2 if half else 1) == 64:
+            return name_pattern.format(fc="1", t=t, fv=2)
+        return name_pattern.format(fc="", t=t, fv=1 if half else 0)
+    v = (value >> (1 if idx > 0 else 0)) & 1
+    return name_pattern.format(t=t, v=v)
 
 
 def run_precision(vgf, torch, ch, rho64, precision, steps, warmup, tune=True):
