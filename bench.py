@@ -265,11 +265,12 @@ def write_counters_profile(csvs, outs, command):
     for name in sorted(per):
         v = per[name]
         g = lambda c: v.get(c, float("nan"))
+        q = lambda a, b: g(a) / g(b) if g(b) else float("nan")
         per_line = "%.0f" % (g("SQ_INSTS_VALU") / nlines) if "fused_c" in name else "-"
         md.append("| %s | %.3g | %s | %.3g | %.3g | %.3g | %.2f | %.2f | %.3g | %s |" % (
             name, g("SQ_INSTS_VALU"), per_line, g("SQ_INSTS_LDS"), g("SQ_ACTIVE_INST_LDS"),
-            g("SQ_LDS_BANK_CONFLICT"), g("SQ_LDS_BANK_CONFLICT") / g("SQ_ACTIVE_INST_LDS"),
-            g("SQ_WAIT_INST_LDS") / g("SQ_WAIT_INST_ANY"), g("SQ_BUSY_CU_CYCLES"), v["vgpr_field"]))
+            g("SQ_LDS_BANK_CONFLICT"), q("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS"),
+            q("SQ_WAIT_INST_LDS", "SQ_WAIT_INST_ANY"), g("SQ_BUSY_CU_CYCLES"), v["vgpr_field"]))
     md += ["", "VGPR field: rocprofv3's VGPR_Count column, which counts registers in units of two here "
            "(a kernel the compiler reports at 80 VGPRs shows 40).", "",
            "Source hash (sha256 of the library code, comments and whitespace ignored, and its build script, "
