@@ -277,9 +277,12 @@ constexpr bool stage_scaled(int R, int NS) { return NS > 1 && (R == 8 || R == 4)
 // (strided axes: adjacent lines are adjacent columns in HBM); 1 = [line][position]
 // with one pad slot every 8 positions and line pitch LP (contiguous axes,
 // one wavefront per line group; the pad keeps radix-8 scatters free of bank
-// conflicts).
+// conflicts); 2 = [line][position] of a 512-point line held by one wavefront
+// (three radix-8 stages, one butterfly per lane), with a layout of its own for
+// each of the two exchanges (see Stage::in_index).
 template <int LAYOUT, int LP>
 __device__ __forceinline__ int lds_index(int pos, int l) {
+  static_assert(LAYOUT == 0 || LAYOUT == 1, "layout 2 is addressed per exchange");
   if constexpr (LAYOUT == 0) return pos * LP + l;
   else return l * LP + pos + (pos >> 3);
 }
@@ -372,12 +375,34 @@ struct Stage {
   // LDS index of in_pos(j, r) / out_pos(j, r) of line l, written as a
   // per-(j, l) base plus r times a compile-time step wherever the layout
   // allows it, so one address serves all R accesses (immediate offsets).
+  //
+  // Layout 2: position p = 64 a2 + 8 a1 + a0 sits at
+  //   exchange 0 (stage 0 -> 1): 72 a2 + 18 (a1 >> 1) + (a1 & 1) + 2 a0,
+  //   exchange 1 (stage 1 -> 2): 72 a2 + 8 a1 + a0.
+  // LDS resolves bank conflicts of 8-byte writes over each half-wavefront
+  // (32 lanes, 32 slots of 8 bytes) and of 8-byte reads over each quarter
+  // (16 lanes, 16 slots). Stage 0 writes (a2, a1) = lane digits and a0 = r,
+  // stage 1 writes a2 = lane >> 3, a0 = lane & 7 and a1 = r, and both reads
+  // take a2 = r and (a1, a0) = lane digits: every access of the three
+  // patterns then touches distinct slots, while layout 1 serves the reads in
+  // two passes.
   __device__ __forceinline__ static int in_index(int j, int r, int l) {
-    if constexpr (LAYOUT == 1 && NB % 8 == 0) return l * LP + j + (j >> 3) + r * (NB + NB / 8);
-    else return lds_index<LAYOUT, LP>(in_pos(j, r), l);
+    if constexpr (LAYOUT == 2) {
+      static_assert(P == 512 && R == 8 && NQ == 64 && NTASK == 1 && S >= 1, "layout 2: 512-point lines");
+      if constexpr (S == 1) return l * LP + 18 * (j >> 4) + ((j >> 3) & 1) + 2 * (j & 7) + 72 * r;
+      else return l * LP + j + 72 * r;
+    } else if constexpr (LAYOUT == 1 && NB % 8 == 0) {
+      return l * LP + j + (j >> 3) + r * (NB + NB / 8);
+    } else {
+      return lds_index<LAYOUT, LP>(in_pos(j, r), l);
+    }
   }
   __device__ __forceinline__ static int out_index(int j, int r, int l) {
-    if constexpr (LAYOUT == 1 && (NS % 8 == 0 || (NS == 1 && 8 % R == 0))) {
+    if constexpr (LAYOUT == 2) {
+      static_assert(P == 512 && R == 8 && NQ == 64 && NTASK == 1 && S <= 1, "layout 2: 512-point lines");
+      if constexpr (S == 0) return l * LP + 72 * (j >> 3) + 18 * ((j & 7) >> 1) + (j & 1) + 2 * r;
+      else return l * LP + 72 * (j >> 3) + (j & 7) + 8 * r;
+    } else if constexpr (LAYOUT == 1 && (NS % 8 == 0 || (NS == 1 && 8 % R == 0))) {
       const int u = (j / NS) * NS * R + (j % NS);
       return l * LP + u + (u >> 3) + r * (NS == 1 ? 1 : NS + NS / 8);
     } else {

@@ -204,6 +204,10 @@ template <int P> constexpr int wave_nq() {
 #ifndef VGF_FC1
 #define VGF_FC1 1
 #endif
+// k_fused_c1 exchanges 512-point lines through LDS layout 2 (1) or 1 (0)
+#ifndef VGF_LAY2
+#define VGF_LAY2 1
+#endif
 constexpr int64_t kFusedCMinBlocks = 2048;
 // V = 1 (the multiply pass's second lane schedule): half the lanes per line,
 // twice the lines per wavefront and twice the butterflies per lane, where the
@@ -1370,10 +1374,12 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   static_assert(TW::LPW == 1 && TW::NQ == 64, "one line per wavefront");
   constexpr int LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  using S0 = Stage<T, P, 64, 1, LP, -1, 0, 1>;
-  using SL = Stage<T, P, 64, 1, LP, -1, NSTG - 1, 1>;
-  using IS0 = Stage<T, P, 64, 1, LP, 1, 0, 1>;
-  using ISL = Stage<T, P, 64, 1, LP, 1, NSTG - 1, 1>;
+  // 512-point lines exchange through the bank-conflict-free layout 2
+  constexpr int LAY = (VGF_LAY2 && P == 512) ? 2 : 1;
+  using S0 = Stage<T, P, 64, 1, LP, -1, 0, LAY>;
+  using SL = Stage<T, P, 64, 1, LP, -1, NSTG - 1, LAY>;
+  using IS0 = Stage<T, P, 64, 1, LP, 1, 0, LAY>;
+  using ISL = Stage<T, P, 64, 1, LP, 1, NSTG - 1, LAY>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LP];
   __shared__ C twl[tw_both_size<P>()];
@@ -1430,8 +1436,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
     S0::lds_out(x, tile, 0, q);
     wave_sync();
     typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
-    if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, -1, 1, true>(rh, tile, twl, twf, 0, q);
-    else middle_and_last<T, P, 64, 1, LP, -1, 1, true>(rh, tile, twl, 0, q);
+    if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, -1, LAY, true>(rh, tile, twl, twf, 0, q);
+    else middle_and_last<T, P, 64, 1, LP, -1, LAY, true>(rh, tile, twl, 0, q);
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
       if (!SL::active(t, q)) continue;
@@ -1457,8 +1463,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       IS0::lds_out(v, tile, 0, q);
       wave_sync();
       typename ISL::Regs o;
-      if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), twi, 0, q);
-      else middle_and_last<T, P, 64, 1, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), 0, q);
+      if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), twi, 0, q);
+      else middle_and_last<T, P, 64, 1, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), 0, q);
       C* __restrict__ d = dst + fi * g.fs;
       if (g.nt)
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
