@@ -670,13 +670,14 @@ def run_diff(vgf, torch, workloads, steps, warmup, seed):
 def run_variants(vgf, torch, ch, rho64, steps, warmup):
     """The comparison variants at the headline size, FP32, phi + E, each on
     its own autotuned plan: the HE methods (same passes, another kernel
-    spectrum), the finite-difference and gradient-kernel fields, the axis-0
-    layout, and a rectangular grid (256 x 128 x 192 points, spacing 2/255 on
+    spectrum), the finite-difference and gradient-kernel fields (the latter
+    in both layouts), the axis-0 layout, and a rectangular grid (256 x 128 x 192 points, spacing 2/255 on
     every axis, the beam's leading block of points)."""
     rho = torch.from_numpy(rho64).to("cuda", torch.float32)
     cases = [("vgf", {}), ("vgf_axis0_layout", {"layout": "axis0"}), ("he", {"method": "he"}),
              ("he_nearby", {"method": "he_nearby"}), ("he_cellavg", {"method": "he_cellavg"}),
-             ("vgf_fd_field", {"field": "centered"}), ("vgf_gradient_kernel", {"field": "gradient_kernel"})]
+             ("vgf_fd_field", {"field": "centered"}), ("vgf_gradient_kernel", {"field": "gradient_kernel"}),
+             ("vgf_gradient_kernel_axis0_layout", {"field": "gradient_kernel", "layout": "axis0"})]
     out = {"grid": list(ch.n), "precision": "f32", "outputs": "phi+E"}
 
     def timed(plan, r):

@@ -89,13 +89,13 @@ typedef enum { VGF_F64 = 0, VGF_F32 = 1 } vgf_precision;
  *     of -i k_a times the windowed spectrum, restricted like the potential's
  *     kernel (Sec. II, applied to the field; the other reading of Sec. III.A's
  *     "multiplying by the wavevector"). The plan stores dim more kernel
- *     spectra; the axis-0 pass multiplies every field by its own spectrum and
- *     inverts each field separately. */
+ *     spectra; the multiply pass multiplies every field by its own spectrum
+ *     and each field is inverted separately. */
 /*   VGF_LAYOUT_AXIS0 : run the spectral multiply inside the axis-0 pass
  *     (real-to-complex along the last axis, strided axis-0 multiply pass)
  *     instead of the default (real-to-complex along axis 0, multiply pass
  *     along the contiguous last axis). Both compute the same discrete
- *     result; gradient-kernel plans always use this layout. */
+ *     result, for every field mode. */
 enum {
   VGF_OUT_PHI = 1u,
   VGF_OUT_E = 2u,
@@ -272,8 +272,8 @@ void vgf_batch_destroy(vgf_batch batch);
  * segment of columns per workgroup (the default), 1 = half of it (more and
  * smaller workgroups). Strided are, in the default layout, the axis-0 R2C
  * and C2R passes and the axis-1 passes (3D); in the axis-0 layout
- * (VGF_LAYOUT_AXIS0, gradient-kernel plans) the axis-1 passes and the axis-0
- * multiply pass. A variant changes only the launch shape: every line is
+ * (VGF_LAYOUT_AXIS0) the axis-1 passes and the axis-0 multiply pass
+ * (gradient-kernel plans: the axis-1 passes only). A variant changes only the launch shape: every line is
  * transformed with the same arithmetic, so results are bit-identical across
  * schedules. A schedule is an int[5], one value per pass in the order
  * VGF_PASS_R2C, VGF_PASS_C2C_FWD, VGF_PASS_FUSED, VGF_PASS_C2C_INV,
@@ -281,7 +281,8 @@ void vgf_batch_destroy(vgf_batch batch);
  * first launch, bit 1 that of its later launches (the inverse passes launch
  * once per group of outputs, the two-output launch first; adjoints may
  * launch a pass more than once). In the default layout the multiply pass
- * along the contiguous axis (VGF_PASS_FUSED) has schedules too, its value
+ * along the contiguous axis (VGF_PASS_FUSED; not for gradient-kernel
+ * plans, whose multiply pass has one schedule) has schedules too, its value
  * taken whole: bit 0 halves the lanes that share one line (twice the lines
  * per wavefront and the butterflies per lane), bit 1 lets each wavefront
  * walk 16 instead of 4 lines (fewer, longer workgroups); the walk is cut

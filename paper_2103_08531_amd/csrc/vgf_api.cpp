@@ -789,9 +789,109 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   return VGF_OK;
 }
 
+// Multiply-pass geometry of the default layout (lines along the contiguous
+// last axis of X2 in 3D, X1 in 2D).
+template <typename T>
+vgf::FusedCGeom<T> fused_c_geom(vgf_plan p, int count, int64_t es, bool nt) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], H0 = N0 + 1, NL = p->n[d - 1];
+  vgf::FusedCGeom<T> g{};
+  g.dim = d;
+  g.n0 = (int)N0;
+  g.n1 = (int)p->n[1];
+  g.n_last = (int)NL;
+  g.lpe = d == 3 ? H0 * p->P[1] : H0;
+  g.nlines = g.lpe * count;
+  g.in_es = g.out_es = es;
+  g.fs = g.lpe * NL;
+  g.ks = (T)wavenumber_step(p, d - 1);
+  g.nt = nt;
+  return g;
+}
+
+// Forward solve with gradient kernels in the default layout: the axis-0 R2C
+// and the axis-1 forward as for Fourier fields, then the multiply pass along
+// the contiguous axis gives every requested field its own spectrum (phi: the
+// kernel spectrum, E_a: -i T_a) and inverts each, and every field is then
+// inverted on its own along axis 1 and axis 0 (no derivative factors).
+template <typename T>
+vgf_status enqueue_solve_cg(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks, const int* sched,
+                            hipEvent_t* mark_events, int* mark_tags) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H0 = N0 + 1, NL = p->n[d - 1];
+  const int64_t vol = prod(p->n, d);
+  char* base = en.ws;
+  Bufs<T> b{(cplx<T>*)(base + p->off_x1), (cplx<T>*)(base + p->off_x2), (cplx<T>*)(base + p->off_y),
+            (cplx<T>*)(base + p->off_z)};
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  Marks mk(p, s, marks, mark_events, mark_tags);
+  const bool nt = vol * en.count * (int64_t)sizeof(T) >= p->stream_min;
+  vgf::R2CSArgs<T> ra{};
+  if (en.rho_tab) ra.in_tab[0] = en.rho_tab;
+  else ra.in[0] = en.rho;
+  ra.out = b.x1;
+  ra.out_es = en.es;
+  ra.ncols = vol / N0;
+  ra.nentry = en.count;
+  ra.d = deriv1<T>(p, 0, 0);
+  ra.nt_load = nt;
+  VGF_LAUNCH(kPassR2C, vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(sched, kPassR2C, 0), ra, tw(0), s));
+  const cplx<T>* fin = b.x1;
+  vgf::FusedCGeom<T> g = fused_c_geom<T>(p, en.count, en.es, nt);
+  g.nf = 0;
+  if (en.want_phi) g.fields[g.nf++] = 0;
+  if (en.want_E)
+    for (int a = 0; a < d; ++a) g.fields[g.nf++] = 1 + a;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], N2 = NL;
+    vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
+    fg.nentry = en.count;
+    fg.es_in = fg.es_out = en.es;
+    fg.nt_store = nt;
+    vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.x2, fg, deriv1<T>(p, 1, 0)};
+    VGF_LAUNCH(kPassC2CF, vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 0), fa, tw(1), s));
+    fin = b.x2;
+  }
+  VGF_LAUNCH(kPassFused, vgf::launch_fused_cg<T>((int)p->P[d - 1], false, fin, b.y, g, grad_spec<T>(p),
+                                                 tw(d - 1), s));
+  // spectra along axis 0 of the fields, one array each
+  const cplx<T>* zin = b.y;
+  int64_t zfs = g.fs;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], N2 = NL;
+    zfs = H0 * N1 * N2;
+    vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
+    ig.nentry = en.count;
+    ig.es_in = ig.es_out = en.es;
+    ig.nt_load = ig.nt_store = nt;
+    for (int f = 0; f < g.nf; ++f) {
+      vgf::C2CInvArgs<T> ia{b.y + f * g.fs, {b.z + f * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
+      VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, f), ia, tw(1), s));
+    }
+    zin = b.z;
+  }
+  // one axis-0 launch: the first field from its own spectrum (no factor),
+  // the others as extra inputs
+  vgf::C2RSArgs<T> ca{};
+  ca.in = zin;
+  ca.in_es = en.es;
+  ca.ncols = vol / N0;
+  ca.nentry = en.count;
+  ca.d = deriv1<T>(p, 0, 0);
+  c2r_s_out(ca, 0, en, g.fields[0] - 1, vol);
+  for (int f = 1; f < g.nf; ++f) {
+    ca.in_x[ca.nx] = zin + f * zfs;
+    c2r_s_out(ca, 1 + ca.nx, en, g.fields[f] - 1, vol);
+    ++ca.nx;
+  }
+  VGF_LAUNCH(kPassC2R, vgf::launch_c2r_s<T>((int)p->P[0], launch_variant(sched, kPassC2R, 0), ca, tw(0), s));
+  return VGF_OK;
+}
+
 template <typename T>
 vgf_status enqueue_solve(vgf_plan p, const Entries<T>& en, hipStream_t s, bool marks,
                          const int* sched, hipEvent_t* mark_events = nullptr, int* mark_tags = nullptr) {
+  if (p->gradk && p->contig) return enqueue_solve_cg<T>(p, en, s, marks, sched, mark_events, mark_tags);
   if (p->gradk) return enqueue_solve_grad<T>(p, en, s, marks, sched, mark_events, mark_tags);
   if (p->contig) return enqueue_solve_c<T>(p, en, s, marks, sched, mark_events, mark_tags);
   const int d = p->dim;
@@ -908,6 +1008,8 @@ std::map<TuneKey, std::array<int, kPasses>> g_tune_cache;
 // width) and, in the default layout, the multiply pass along the contiguous
 // axis (lanes per line and walk length)
 bool pass_tunable(vgf_plan p, int pass) {
+  if (p->gradk && p->contig)
+    return pass == kPassR2C || pass == kPassC2R || (p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI));
   if (p->gradk) return p->dim == 3 && (pass == kPassC2CF || pass == kPassC2CI);
   if (p->contig)
     return pass == kPassR2C || pass == kPassC2R || pass == kPassFused ||
@@ -1149,6 +1251,68 @@ vgf_status adjoint_grad_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hi
   return VGF_OK;
 }
 
+// Adjoint with gradient kernels in the default layout: every cotangent goes
+// through the axis-0 R2C and the axis-1 forward on its own; the multiply
+// pass sums their line transforms with the conjugate multipliers (+i T_a for
+// the fields) and inverts the sum once, followed by one axis-1 inverse and
+// one axis-0 C2R.
+template <typename T>
+vgf_status adjoint_cg_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  const int d = p->dim;
+  const int64_t N0 = p->n[0], N1 = p->n[1], H0 = N0 + 1, NL = p->n[d - 1];
+  const int64_t vol = prod(p->n, d);
+  Bufs<T> b = bufs<T>(p);
+  auto tw = [&](int a) { return (const cplx<T>*)p->tw[a]; };
+  const bool nt = vol * (int64_t)sizeof(T) >= p->stream_min;
+  vgf::FusedCGeom<T> g = fused_c_geom<T>(p, 1, 0, false);
+  const T* srcs[4];
+  g.nf = 0;
+  if (g_phi) {
+    srcs[g.nf] = g_phi;
+    g.fields[g.nf++] = 0;
+  }
+  if (g_E)
+    for (int a = 0; a < d; ++a) {
+      srcs[g.nf] = g_E + a * vol;
+      g.fields[g.nf++] = 1 + a;
+    }
+  // the line transforms' inputs: [field][lines] at stride fs in Y
+  for (int f = 0; f < g.nf; ++f) {
+    vgf::R2CSArgs<T> ra{};
+    ra.in[0] = srcs[f];
+    ra.out = d == 3 ? b.x1 : b.y + f * g.fs;
+    ra.ncols = vol / N0;
+    ra.nentry = 1;
+    ra.d = deriv1<T>(p, 0, 0);
+    ra.nt_load = nt;
+    VGF_RUN(vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(p->schedule, kPassR2C, 0), ra, tw(0), s));
+    if (d == 3) {
+      const int64_t P1 = p->P[1], N2 = NL;
+      const vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
+      vgf::C2CFwdArgs<T> fa{{b.x1, nullptr}, b.y + f * g.fs, fg, deriv1<T>(p, 1, 0)};
+      VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(p->schedule, kPassC2CF, 0), fa, tw(1), s));
+    }
+  }
+  cplx<T>* acc = d == 3 ? b.x2 : b.x1;
+  VGF_RUN(vgf::launch_fused_cg<T>((int)p->P[d - 1], true, b.y, acc, g, grad_spec<T>(p), tw(d - 1), s));
+  const cplx<T>* zin = acc;
+  if (d == 3) {
+    const int64_t P1 = p->P[1], N2 = NL;
+    const vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
+    vgf::C2CInvArgs<T> ia{acc, {b.z, nullptr}, ig, deriv1<T>(p, 1, 0)};
+    VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, launch_variant(p->schedule, kPassC2CI, 0), ia, tw(1), s));
+    zin = b.z;
+  }
+  vgf::C2RSArgs<T> ca{};
+  ca.in = zin;
+  ca.ncols = vol / N0;
+  ca.nentry = 1;
+  ca.d = deriv1<T>(p, 0, 0);
+  ca.out[0] = g_rho;
+  VGF_RUN(vgf::launch_c2r_s<T>((int)p->P[0], launch_variant(p->schedule, kPassC2R, 0), ca, tw(0), s));
+  return VGF_OK;
+}
+
 // Adjoint in the contiguous-multiply layout: the mirror image of
 // enqueue_solve_c (forward passes sum their inputs with +i k of their axis).
 // The cotangents of the entries one adjoint launch covers: direct pointers
@@ -1277,6 +1441,7 @@ vgf_status adjoint_c_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipSt
 
 template <typename T>
 vgf_status adjoint_t(vgf_plan p, const T* g_phi, const T* g_E, T* g_rho, hipStream_t s) {
+  if (p->gradk && p->contig) return adjoint_cg_t<T>(p, g_phi, g_E, g_rho, s);
   if (p->gradk) return adjoint_grad_t<T>(p, g_phi, g_E, g_rho, s);
   if (p->contig) return adjoint_c_t<T>(p, g_phi, g_E, g_rho, s);
   const int d = p->dim;
@@ -1429,9 +1594,8 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->fd = (outputs & VGF_FIELD_CENTERED) != 0;
   p->gradk = (outputs & VGF_FIELD_GRADIENT_KERNEL) != 0;
   p->stream_min = stream_min_env();
-  // the multiply pass runs along the contiguous axis unless asked otherwise;
-  // gradient-kernel plans use the axis-0 layout
-  p->contig = !p->gradk && !(outputs & VGF_LAYOUT_AXIS0);
+  // the multiply pass runs along the contiguous axis unless asked otherwise
+  p->contig = !(outputs & VGF_LAYOUT_AXIS0);
 
   const size_t rb = prec == VGF_F32 ? 4 : 8, cb = 2 * rb;
   const int64_t N0 = n[0], N1 = n[1], H = p->Hs;

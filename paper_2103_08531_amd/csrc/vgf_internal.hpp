@@ -170,7 +170,7 @@ template <typename T> struct C2RSArgs {
   Deriv<T> d;     // outputs 0 .. d.n-1 from `in`, each with its factor
   // outputs d.n .. d.n+nx-1 from in_x[0 .. nx), without a factor, in the
   // same launch (inputs laid out like `in`)
-  const cplx<T>* in_x[2];
+  const cplx<T>* in_x[3];
   int nx;
 };
 // Lines along the contiguous last axis (length n_last in, 2 n_last transformed)
@@ -185,7 +185,8 @@ template <typename T> struct FusedCGeom {
   int64_t fs;         // field stride (elements): output fields (forward), input fields (adjoint)
   T ks;               // 2 pi / (P_last h_last)
   int nf;             // forward: 1 (phi) or 2 (phi, E_last); adjoint: inputs
-  int fields[2];      // adjoint: per input 0 or 1 (+i k_last)
+  int fields[4];      // adjoint: per input 0 or 1 (+i k_last); gradient kernels: 0 .. dim
+                      // (the multipliers of GradSpec), up to four fields
   bool nt = false;    // forward: non-temporal loads and stores (large arrays)
 };
 template <typename T>
@@ -209,6 +210,12 @@ template <typename T> struct GradSpec {
 template <typename T>
 hipError_t launch_fused_grad(int P, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g,
                              const GradSpec<T>& sp, const cplx<T>* tw, hipStream_t s);
+// The same multipliers in the multiply pass along the contiguous axis
+// (FusedCGeom lines; forward: g.nf outputs at out + i * fs for the fields
+// g.fields[i]; adjoint: g.nf inputs at in + i * fs summed into one output).
+template <typename T>
+hipError_t launch_fused_cg(int P, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
+                           const GradSpec<T>& sp, const cplx<T>* tw, hipStream_t s);
 
 // ---- finite-difference field (second order; centred inside, one-sided at
 // the two end planes of each axis) ----

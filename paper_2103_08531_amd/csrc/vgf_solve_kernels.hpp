@@ -1572,6 +1572,198 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
 }
 
 // ---------------------------------------------------------------------------
+// gradient-kernel fields with the multiply pass along the contiguous axis
+// ---------------------------------------------------------------------------
+// Multiplier of field f (0: the kernel spectrum, 1 + a: -i T_a) at position p
+// of line (k0, k1): the octant value of the field's spectrum, negated for a
+// gradient field where its own axis index is mirrored (axis 1 in 3D: k1 > n1;
+// the last axis: p > N; axis 0 holds only its non-negative half).
+template <typename T, int P>
+__device__ __forceinline__ T grad_value(const T* __restrict__ srow, int f, int last_field, bool neg1, int p) {
+  constexpr int N = P / 2;
+  const T v = srow[p <= N ? p : P - p];
+  const bool neg = (f == last_field && p > N) || (f == 2 && last_field == 3 && neg1);
+  return neg ? -v : v;
+}
+
+// Forward: each line (k0, k1) of X2 (X1 in 2D) is transformed (pruned input)
+// and, for each requested field, multiplied by that field's spectrum and
+// inverted (pruned output) into out + fi * fs. The line walk and tiles are
+// those of k_fused_c (one schedule).
+template <typename T, int P>
+__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_cg(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, GradSpec<T> sp,
+    const cplx<T>* __restrict__ tw, int gpw) {
+  using C = cplx<T>;
+  using TW = TileW<T, P>;
+  constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
+  constexpr int NSTG = n_stages(P);
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+  __shared__ C tiles[TW::WPB * LPW * LP];
+  __shared__ C twl[tw_both_size<P>()];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = lane / NQ, q = lane % NQ;
+  C* tile = tiles + w * LPW * LP;
+  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw * LPW + l;
+  LineWalk wk;
+  wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
+  wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
+  {
+    const EntryLine el(line < g.nlines ? line : 0, g.lpe, g.nlines);
+    wk.e = (int)el.e;
+    wk.k0 = (int)el.line / wk.p1;
+    wk.k1 = (int)el.line - wk.k0 * wk.p1;
+  }
+  stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
+  const int last_field = g.dim;  // 1 + the last axis
+  for (int it = 0; it < gpw; ++it) {
+    const bool valid = line < g.nlines;
+    const int64_t lofs = ((int64_t)wk.k0 * wk.p1 + wk.k1) * N;
+    const bool neg1 = g.dim == 3 && wk.k1 > g.n1;
+    const int row = !valid ? 0
+                           : g.dim == 3 ? wk.k0 * (g.n1 + 1) + (wk.k1 <= g.n1 ? wk.k1 : wk.p1 - wk.k1)
+                                        : wk.k1;
+    const int64_t e = wk.e;
+    const C* __restrict__ src = valid ? in + e * g.in_es + lofs : in;
+    typename S0::Regs x;
+    if (g.nt)
+      S0::template load_first<true>(x, q, [&](int j, int r) { return load_nt(&src[S0::in_pos(j, r)]); });
+    else
+      S0::template load_first<true>(x, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+    S0::template butterflies<true>(x, q);
+    wave_sync();  // the previous line's reads of the tile are done
+    S0::lds_out(x, tile, l, q);
+    wave_sync();
+    typename SL::Regs rh;  // the line's spectrum
+    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+    for (int fi = 0; fi < g.nf; ++fi) {
+      const int f = g.fields[fi];
+      const T* __restrict__ srow = sp.s[f] + (int64_t)row * (N + 1);
+      typename IS0::Regs v;
+#pragma unroll
+      for (int t = 0; t < SL::NTASK; ++t) {
+        if (!SL::active(t, q)) continue;
+        const int j = q + t * SL::NQ;
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r) {
+          const T m = grad_value<T, P>(srow, f, last_field, neg1, j + r * SL::NB);
+          v.v[t][r] = f == 0 ? C{rh.v[t][r].x * m, rh.v[t][r].y * m} : deriv(rh.v[t][r], -1, m);
+        }
+      }
+      IS0::butterflies(v, q);
+      wave_sync();  // the previous transform's reads of the tile are done
+      IS0::lds_out(v, tile, l, q);
+      wave_sync();
+      typename ISL::Regs o;
+      middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+      if (valid) {
+        C* __restrict__ d = out + e * g.out_es + fi * g.fs + lofs;
+        if (g.nt)
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
+        else
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
+      }
+    }
+    line += LPW;
+    wk.advance(LPW);
+  }
+}
+
+// Adjoint: acc = sum_f conj(m_f) FFT(in_f) with the multipliers of
+// k_fused_cg (+i T_a for the fields), inverted once (pruned output).
+template <typename T, int P>
+__global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_fused_cg_adj(
+    const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out, FusedCGeom<T> g, GradSpec<T> sp,
+    const cplx<T>* __restrict__ tw, int gpw) {
+  using C = cplx<T>;
+  using TW = TileW<T, P>;
+  constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
+  constexpr int NSTG = n_stages(P);
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
+  __shared__ C tiles[TW::WPB * LPW * LP];
+  __shared__ C twl[tw_both_size<P>()];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l = lane / NQ, q = lane % NQ;
+  C* tile = tiles + w * LPW * LP;
+  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw * LPW + l;
+  LineWalk wk;
+  wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
+  wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
+  {
+    const EntryLine el(line < g.nlines ? line : 0, g.lpe, g.nlines);
+    wk.e = (int)el.e;
+    wk.k0 = (int)el.line / wk.p1;
+    wk.k1 = (int)el.line - wk.k0 * wk.p1;
+  }
+  stage_twiddles_both<C, P, TW::NT>(twl, tw, tid);
+  __syncthreads();
+  const int last_field = g.dim;
+  for (int it = 0; it < gpw; ++it) {
+    const bool valid = line < g.nlines;
+    const int64_t lofs = ((int64_t)wk.k0 * wk.p1 + wk.k1) * N;
+    const bool neg1 = g.dim == 3 && wk.k1 > g.n1;
+    const int row = !valid ? 0
+                           : g.dim == 3 ? wk.k0 * (g.n1 + 1) + (wk.k1 <= g.n1 ? wk.k1 : wk.p1 - wk.k1)
+                                        : wk.k1;
+    const int64_t e = wk.e;
+    typename IS0::Regs acc;
+#pragma unroll
+    for (int t = 0; t < SL::NTASK; ++t)
+#pragma unroll
+      for (int r = 0; r < SL::R; ++r) acc.v[t][r] = C{T(0), T(0)};
+    for (int fi = 0; fi < g.nf; ++fi) {
+      const int f = g.fields[fi];
+      const C* __restrict__ src = valid ? in + e * g.in_es + fi * g.fs + lofs : in;
+      typename S0::Regs g0;
+      S0::template load_first<true>(g0, q, [&](int j, int r) { return src[S0::in_pos(j, r)]; });
+      S0::template butterflies<true>(g0, q);
+      wave_sync();  // the previous transform's reads of the tile are done
+      S0::lds_out(g0, tile, l, q);
+      wave_sync();
+      typename SL::Regs rh;
+      middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+      const T* __restrict__ srow = sp.s[f] + (int64_t)row * (N + 1);
+#pragma unroll
+      for (int t = 0; t < SL::NTASK; ++t) {
+        if (!SL::active(t, q)) continue;
+        const int j = q + t * SL::NQ;
+#pragma unroll
+        for (int r = 0; r < SL::R; ++r) {
+          const T m = grad_value<T, P>(srow, f, last_field, neg1, j + r * SL::NB);
+          if (f == 0) {
+            acc.v[t][r].x = fmaT(rh.v[t][r].x, m, acc.v[t][r].x);
+            acc.v[t][r].y = fmaT(rh.v[t][r].y, m, acc.v[t][r].y);
+          } else {
+            acc.v[t][r] = deriv_add(acc.v[t][r], rh.v[t][r], 1, m);
+          }
+        }
+      }
+    }
+    IS0::butterflies(acc, q);
+    wave_sync();
+    IS0::lds_out(acc, tile, l, q);
+    wave_sync();
+    typename ISL::Regs o;
+    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+    if (valid) {
+      C* __restrict__ dst = out + e * g.out_es + lofs;
+      ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
+    }
+    line += LPW;
+    wk.advance(LPW);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -1733,7 +1925,7 @@ hipError_t launch_c2r_s_v(const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s
   if (bx == 0 || a.nentry == 0 || a.d.n == 0) return hipSuccess;
   if (a.nentry > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)bx, (unsigned)a.nentry);
-  if (a.d.n < 1 || a.d.n > 2 || a.nx < 0 || a.nx > 2) return hipErrorInvalidValue;
+  if (a.d.n < 1 || a.d.n > 2 || a.nx < 0 || a.nx > 3 || a.d.n + a.nx > 4) return hipErrorInvalidValue;
   switch (a.d.n + a.nx) {
     case 1: hipLaunchKernelGGL((k_c2r_s<T, P, 1, V>), grid, dim3(TL::NT), 0, s, a, tw); break;
     case 2: hipLaunchKernelGGL((k_c2r_s<T, P, 2, V>), grid, dim3(TL::NT), 0, s, a, tw); break;
@@ -1777,6 +1969,26 @@ hipError_t launch_fused_c_v(int schedule, bool adjoint, const cplx<T>* in, cplx<
   return hipGetLastError();
 }
 
+// Gradient-kernel multiply pass along the contiguous axis (one schedule).
+template <typename T, int P>
+hipError_t launch_fused_cg_p(bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
+                             const GradSpec<T>& sp, const cplx<T>* tw, hipStream_t s) {
+  using TW = TileW<T, P>;
+  if (g.nf == 0 || g.nlines == 0) return hipSuccess;
+  if (g.nf < 0 || g.nf > 4 || (g.lpe > 0 && g.nlines % g.lpe != 0)) return hipErrorInvalidValue;
+  for (int i = 0; i < g.nf; ++i)
+    if (g.fields[i] < 0 || g.fields[i] > g.dim || !sp.s[g.fields[i]]) return hipErrorInvalidValue;
+  const int64_t groups = (g.nlines + TW::LPW - 1) / TW::LPW;
+  int gpw = VGF_FC_GPW;
+  while (gpw > 1 && (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw) < kFusedCMinBlocks) gpw /= 2;
+  const int64_t blocks = (groups + (int64_t)TW::WPB * gpw - 1) / ((int64_t)TW::WPB * gpw);
+  if (adjoint)
+    hipLaunchKernelGGL((k_fused_cg_adj<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, sp, tw, gpw);
+  else
+    hipLaunchKernelGGL((k_fused_cg<T, P>), dim3((unsigned)blocks), dim3(TW::NT), 0, s, in, out, g, sp, tw, gpw);
+  return hipGetLastError();
+}
+
 template <typename T, int P>
 hipError_t launch_fused_c_p(int schedule, bool adjoint, const cplx<T>* in, cplx<T>* out, const FusedCGeom<T>& g,
                             const T* spec, const cplx<T>* tw, hipStream_t s) {
@@ -1803,13 +2015,16 @@ hipError_t launch_fused_c_p(int schedule, bool adjoint, const cplx<T>* in, cplx<
   PFX hipError_t launch_r2c_s_p<VGF_T, PP>(int, const R2CSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
   PFX hipError_t launch_c2r_s_p<VGF_T, PP>(int, const C2RSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
   PFX hipError_t launch_fused_c_p<VGF_T, PP>(int, bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
-                                             const VGF_T*, const cplx<VGF_T>*, hipStream_t);
+                                             const VGF_T*, const cplx<VGF_T>*, hipStream_t);               \
+  PFX hipError_t launch_fused_cg_p<VGF_T, PP>(bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
+                                              const GradSpec<VGF_T>&, const cplx<VGF_T>*, hipStream_t);
 #define VGF_EXTERN_P(PP) VGF_LAUNCHERS_P(extern template, PP)
 #define VGF_INSTANTIATE_P(PP) VGF_LAUNCHERS_P(template, PP)
 
 #define VGF_CASE_R2CS(PP) case PP: return launch_r2c_s_p<VGF_T, PP>(variant, a, tw, s);
 #define VGF_CASE_C2RS(PP) case PP: return launch_c2r_s_p<VGF_T, PP>(variant, a, tw, s);
 #define VGF_CASE_FC(PP) case PP: return launch_fused_c_p<VGF_T, PP>(schedule, adjoint, in, out, g, spec, tw, s);
+#define VGF_CASE_FCG(PP) case PP: return launch_fused_cg_p<VGF_T, PP>(adjoint, in, out, g, sp, tw, s);
 #define VGF_CASE_R2C(PP) case PP: return launch_r2c_p<VGF_T, PP>(a, tw, s);
 #define VGF_CASE_FGRAD(PP) case PP: return launch_fused_grad_p<VGF_T, PP>(adjoint, in, out, g, sp, tw, s);
 #define VGF_CASE_C2R(PP) case PP: return launch_c2r_p<VGF_T, PP>(a, tw, s);
@@ -1857,6 +2072,12 @@ hipError_t launch_fused_c_p(int schedule, bool adjoint, const cplx<T>* in, cplx<
                                const FusedCGeom<T>& g, const T* spec, const cplx<T>* tw,        \
                                hipStream_t s) {                                                 \
     switch (P) { VGF_FOR_EACH_P(VGF_CASE_FC) default: return hipErrorInvalidValue; }            \
+  }                                                                                             \
+  template <>                                                                                   \
+  hipError_t launch_fused_cg<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,           \
+                                const FusedCGeom<T>& g, const GradSpec<T>& sp,                  \
+                                const cplx<T>* tw, hipStream_t s) {                             \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FCG) default: return hipErrorInvalidValue; }           \
   }                                                                                             \
   template <>                                                                                   \
   hipError_t launch_fused_grad<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,         \

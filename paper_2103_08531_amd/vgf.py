@@ -150,8 +150,7 @@ class Plan:
     (E by second-order finite differences of phi) or 'gradient_kernel' (E_a =
     w_a * rho with the restricted 4N transform of -i k_a Ghat; VGF only);
     layout: 'contiguous' (default: the spectral multiply runs along the
-    contiguous last axis) or 'axis0' (inside the strided axis-0 pass; the
-    layout gradient-kernel plans always use).
+    contiguous last axis) or 'axis0' (inside the strided axis-0 pass).
     """
 
     def __init__(self, n, h, method="vgf", precision="f64", L=None, outputs=("phi", "E"),

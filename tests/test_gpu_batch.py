@@ -90,12 +90,13 @@ def test_batch_equals_single_solves(graph):
 
 
 # plans of every field mode and layout in one batch: centred differences,
-# gradient kernels (axis-0 layout), the axis-0 layout with Fourier fields, and
+# gradient kernels (both layouts), the axis-0 layout with Fourier fields, and
 # the default; 3D and 2D, both precisions, groups of 1 and 2 entries
 MODE_SPECS = [((24, 32, 16), "f64", "centered", "contiguous"), ((48, 64), "f32", "centered", "contiguous"),
               ((32, 32, 32), "f32", "gradient_kernel", "axis0"), ((64, 48), "f64", "gradient_kernel", "axis0"),
-              ((24, 24, 24), "f64", "fourier", "axis0"), ((32, 32, 32), "f32", "fourier", "contiguous")]
-MODE_ENTRIES = [0, 1, 2, 3, 4, 5, 2, 0, 3]
+              ((24, 24, 24), "f64", "fourier", "axis0"), ((32, 32, 32), "f32", "fourier", "contiguous"),
+              ((24, 32, 16), "f32", "gradient_kernel", "contiguous"), ((48, 64), "f64", "gradient_kernel", "contiguous")]
+MODE_ENTRIES = [0, 1, 2, 3, 4, 5, 2, 0, 3, 6, 7, 6]
 
 
 @pytest.mark.parametrize("graph", [False, True])

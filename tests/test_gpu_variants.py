@@ -199,17 +199,18 @@ def test_gradient_kernels_and_spectra(n, h):
     plan.close()
 
 
+@pytest.mark.parametrize("layout", ["contiguous", "axis0"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("n,h", GRAD_CASES)
-def test_gradient_kernel_solve_and_adjoint(precision, n, h):
+def test_gradient_kernel_solve_and_adjoint(precision, n, h, layout):
     torch, vgf = need_gpu()
     h = _grid(n, h)
-    plan = gpu_plan(vgf, n, h, method="vgf", precision=precision, field="gradient_kernel")
+    plan = gpu_plan(vgf, n, h, method="vgf", precision=precision, field="gradient_kernel", layout=layout)
     tol = FP64_TOL if precision == "f64" else FP32_TOL
     rho = rounded_input(W.random_field(21, n), precision)
     phi_g, E_g = gpu_solve(plan, rho)
     phi_o, E_o = orc.solve_grad_kernel(n, h, plan.L, rho)
-    check_fields(phi_g, E_g, phi_o, E_o, tol, "gradk %s %s" % (n, precision))
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "gradk %s %s %s" % (n, precision, layout))
     _, E_only = gpu_solve(plan, rho, want_phi=False)
     assert np.array_equal(E_only, E_g)
     g_phi = rounded_input(W.random_field(22, n), precision)
@@ -223,7 +224,7 @@ def test_gradient_kernel_solve_and_adjoint(precision, n, h):
         V = orc.periodic_kernel_odd(n, orc.vgf_grad_kernel(n, h, plan.L, a), a)
         ref = ref - orc.conv_fft2n(n, V, g_E[a])  # K_a^T: the odd kernel reflected
     e = err(g_rho, ref)
-    say("gradk adjoint %s %s rel-L2 %.3e" % (n, precision, e))
+    say("gradk adjoint %s %s %s rel-L2 %.3e" % (n, precision, layout, e))
     assert e <= tol
     plan.close()
 
