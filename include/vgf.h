@@ -32,9 +32,11 @@
  *    used by one stream at a time; distinct plans are independent.
  *  - Supported sizes: every even n_a = 2^a 3^b (a >= 1) with
  *    8 <= n_a <= 512, i.e. n_a in {8, 12, 16, 18, 24, 32, 36, 48, 54, 64, 72,
- *    96, 108, 128, 144, 162, 192, 216, 256, 288, 324, 384, 432, 486, 512}
- *    (the padded length 2 n_a is an FFT length of radices 8, 4, 2 and 3 that
- *    the library instantiates). Other sizes, odd ones included, return
+ *    96, 108, 128, 144, 162, 192, 216, 256, 288, 324, 384, 432, 486, 512};
+ *    2D plans in the default layout (no VGF_LAYOUT_AXIS0) also take
+ *    n_a in {576, 648, 768, 864, 972, 1024}, i.e. every even 2^a 3^b up to
+ *    1024 (the padded length 2 n_a is an FFT length of radices 8, 4, 2 and 3
+ *    that the library instantiates). Other sizes, odd ones included, return
  *    VGF_ERR_UNSUPPORTED_SIZE.
  */
 #ifndef VGF_H

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libvgf.so")
 OBJDIR = os.path.join(ROOT, "_build", "vgf")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOLVE_UNITS = ["vgf_solve_%s%s.hip" % (p, g) for p in ("f32", "f64") for g in ("", "_g1", "_g2", "_g3", "_g4")]
+SOLVE_UNITS = ["vgf_solve_%s%s.hip" % (p, g) for p in ("f32", "f64") for g in ("", "_g1", "_g2", "_g3", "_g4", "_g5", "_g6")]
 SOURCES = ["vgf_api.cpp", "vgf_precompute.hip", "vgf_batch.hip", "vgf_fd.hip"] + SOLVE_UNITS
 # The per-solve passes are compiled without floating-point contraction: their
 # fused multiply-adds are written out (fmaT), so the rounding of every result

@@ -114,7 +114,12 @@ hipError_t scratch_address(void** out) {
   return hipSuccess;
 }
 
-bool size_supported(int64_t n) { return n >= 8 && vgf::supported_fft_len(2 * n); }
+// n points along an axis: every even n = 2^a 3^b from 8 to 512; 2D plans in
+// the default layout also take 576 .. 1024 (the longer lengths are built for
+// their passes only)
+bool size_supported(int64_t n, bool wide) {
+  return n >= 8 && (vgf::supported_fft_len(2 * n) || (wide && vgf::supported_fft_len_wide(2 * n)));
+}
 
 double he_origin(int dim, const double* h, vgf_method m);
 
@@ -1556,8 +1561,9 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
     if (!(h[a] > 0.0) || !std::isfinite(h[a])) return VGF_ERR_INVALID_ARG;
     if (n[a] <= 0) return VGF_ERR_INVALID_ARG;
   }
+  const bool wide = dim == 2 && !(outputs & VGF_LAYOUT_AXIS0);
   for (int a = 0; a < dim; ++a)
-    if (!size_supported(n[a])) return VGF_ERR_UNSUPPORTED_SIZE;
+    if (!size_supported(n[a], wide)) return VGF_ERR_UNSUPPORTED_SIZE;
 
   double diam2 = 0.0, upper = INFINITY;
   for (int a = 0; a < dim; ++a) {

@@ -32,6 +32,24 @@ inline bool supported_fft_len(int64_t P) {
 #undef VGF_CASE_LEN
 }
 
+// Longer lengths, P = 2^a 3^b from 1152 to 2048 (N = 576 .. 1024), for the
+// passes of 2D grids in the default layout only: the axis-0 R2C and C2R and
+// the multiply pass along the contiguous axis. Two more compile groups.
+#define VGF_P_GROUP5(X) X(1152) X(1296) X(1536)
+#define VGF_P_GROUP6(X) X(1728) X(1944) X(2048)
+#define VGF_FOR_EACH_P_WIDE(X) VGF_P_GROUP5(X) VGF_P_GROUP6(X)
+
+inline bool supported_fft_len_wide(int64_t P) {
+#define VGF_CASE_LEN(PP) case PP:
+  switch (P) {
+    VGF_FOR_EACH_P_WIDE(VGF_CASE_LEN)
+    return true;
+    default:
+      return false;
+  }
+#undef VGF_CASE_LEN
+}
+
 // Geometry of a batch of lines along a strided axis: element pos of
 // column col (contiguous), batch b of entry e is at
 // base + e*es + b*bs + pos*ls + col. The launch covers nbatch x nentry

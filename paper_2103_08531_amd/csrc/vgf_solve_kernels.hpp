@@ -216,10 +216,18 @@ constexpr int64_t kFusedCMinBlocks = 2048;
 template <typename T, int P> constexpr bool half_lanes_fit() {
   return wave_nq<P>() > 1 && 4 * (128 / wave_nq<P>()) * line_pitch<P>() * (int)sizeof(cplx<T>) <= 65536;
 }
+// Wavefronts per workgroup of the contiguous passes: four, fewer where
+// their line tiles and the twiddle tables would not fit the 160 KiB of LDS
+// (FP64 lines of 2048 points).
+template <typename T, int P, int LPW> constexpr int tilew_wpb() {
+  int w = 4;
+  while (w > 1 && (w * LPW * line_pitch<P>() + tw_both_size<P>()) * (int)sizeof(cplx<T>) > 160 * 1024) w /= 2;
+  return w;
+}
 template <typename T, int P, int V = 0> struct TileW {
   static constexpr int NQ = (V == 1 && half_lanes_fit<T, P>()) ? wave_nq<P>() / 2 : wave_nq<P>();  // lanes per line (pair)
   static constexpr int LPW = 64 / NQ;      // lines (line pairs) per wavefront
-  static constexpr int WPB = 4;            // wavefronts per workgroup
+  static constexpr int WPB = tilew_wpb<T, P, LPW>();  // wavefronts per workgroup
   static constexpr int NT = 64 * WPB;
   static constexpr int LP = line_pitch<P>();
   static constexpr int PAIRS = LPW * WPB;  // line pairs per workgroup
@@ -2020,6 +2028,16 @@ hipError_t launch_fused_c_p(int schedule, bool adjoint, const cplx<T>* in, cplx<
                                               const GradSpec<VGF_T>&, const cplx<VGF_T>*, hipStream_t);
 #define VGF_EXTERN_P(PP) VGF_LAUNCHERS_P(extern template, PP)
 #define VGF_INSTANTIATE_P(PP) VGF_LAUNCHERS_P(template, PP)
+// the launchers of the longer 2D lengths (VGF_FOR_EACH_P_WIDE)
+#define VGF_LAUNCHERS_P_WIDE(PFX, PP)                                                                      \
+  PFX hipError_t launch_r2c_s_p<VGF_T, PP>(int, const R2CSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
+  PFX hipError_t launch_c2r_s_p<VGF_T, PP>(int, const C2RSArgs<VGF_T>&, const cplx<VGF_T>*, hipStream_t); \
+  PFX hipError_t launch_fused_c_p<VGF_T, PP>(int, bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
+                                             const VGF_T*, const cplx<VGF_T>*, hipStream_t);               \
+  PFX hipError_t launch_fused_cg_p<VGF_T, PP>(bool, const cplx<VGF_T>*, cplx<VGF_T>*, const FusedCGeom<VGF_T>&, \
+                                              const GradSpec<VGF_T>&, const cplx<VGF_T>*, hipStream_t);
+#define VGF_EXTERN_P_WIDE(PP) VGF_LAUNCHERS_P_WIDE(extern template, PP)
+#define VGF_INSTANTIATE_P_WIDE(PP) VGF_LAUNCHERS_P_WIDE(template, PP)
 
 #define VGF_CASE_R2CS(PP) case PP: return launch_r2c_s_p<VGF_T, PP>(variant, a, tw, s);
 #define VGF_CASE_C2RS(PP) case PP: return launch_c2r_s_p<VGF_T, PP>(variant, a, tw, s);
@@ -2060,24 +2078,24 @@ hipError_t launch_fused_c_p(int schedule, bool adjoint, const cplx<T>* in, cplx<
   template <>                                                                                   \
   hipError_t launch_r2c_s<T>(int P, int variant, const R2CSArgs<T>& a, const cplx<T>* tw,      \
                              hipStream_t s) {                                                   \
-    switch (P) { VGF_FOR_EACH_P(VGF_CASE_R2CS) default: return hipErrorInvalidValue; }          \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_R2CS) VGF_FOR_EACH_P_WIDE(VGF_CASE_R2CS) default: return hipErrorInvalidValue; }          \
   }                                                                                             \
   template <>                                                                                   \
   hipError_t launch_c2r_s<T>(int P, int variant, const C2RSArgs<T>& a, const cplx<T>* tw,      \
                              hipStream_t s) {                                                   \
-    switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2RS) default: return hipErrorInvalidValue; }          \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_C2RS) VGF_FOR_EACH_P_WIDE(VGF_CASE_C2RS) default: return hipErrorInvalidValue; }          \
   }                                                                                             \
   template <>                                                                                   \
   hipError_t launch_fused_c<T>(int P, int schedule, bool adjoint, const cplx<T>* in, cplx<T>* out,            \
                                const FusedCGeom<T>& g, const T* spec, const cplx<T>* tw,        \
                                hipStream_t s) {                                                 \
-    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FC) default: return hipErrorInvalidValue; }            \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FC) VGF_FOR_EACH_P_WIDE(VGF_CASE_FC) default: return hipErrorInvalidValue; }            \
   }                                                                                             \
   template <>                                                                                   \
   hipError_t launch_fused_cg<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,           \
                                 const FusedCGeom<T>& g, const GradSpec<T>& sp,                  \
                                 const cplx<T>* tw, hipStream_t s) {                             \
-    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FCG) default: return hipErrorInvalidValue; }           \
+    switch (P) { VGF_FOR_EACH_P(VGF_CASE_FCG) VGF_FOR_EACH_P_WIDE(VGF_CASE_FCG) default: return hipErrorInvalidValue; }           \
   }                                                                                             \
   template <>                                                                                   \
   hipError_t launch_fused_grad<T>(int P, bool adjoint, const cplx<T>* in, cplx<T>* out,         \

@@ -69,6 +69,17 @@ def test_plan_create_rejects_bad_arguments(V):
     # odd sizes and factors other than 2 and 3 are outside the rule
     for bad in ((9, 16, 16), (27, 16, 16), (16, 20, 16), (16, 16, 1024), (40, 16, 16), (16, 16, 243)):
         assert _create(V, n=bad)[0] == -2, bad
+    # 576 .. 1024 points only for 2D plans in the default layout
+    for bad in ((576, 32, 32), (32, 648, 32)):
+        assert _create(V, n=bad)[0] == -2, bad
+    for bad in ((2048, 64), (64, 1152), (1000, 64), (1536, 64)):
+        assert _create(V, dim=2, n=bad)[0] == -2, bad
+    assert _create(V, dim=2, n=(1024, 64), outputs=3 | 64)[0] == -2
+    for good in ((1024, 1024), (576, 648), (768, 864), (972, 64)):
+        st, handle = _create(V, dim=2, n=good)
+        assert st != -2, good
+        if st == 0:
+            V.lib().vgf_plan_destroy(handle)
 
 
 def test_plan_create_rejects_L_outside_window(V, orc):

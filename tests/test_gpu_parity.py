@@ -19,7 +19,8 @@ def make_plan(n, h, method="vgf", precision="f64", outputs=("phi", "E"), L=None)
 
 
 KERNEL_CASES = [((8, 8, 8), "vgf"), ((12, 12, 12), "he"), ((32, 32, 32), "vgf"), ((32, 32, 32), "he"),
-                ((16, 24, 32), "vgf"), ((16, 16), "vgf"), ((64, 48), "he"), ((512, 512), "vgf")]
+                ((16, 24, 32), "vgf"), ((16, 16), "vgf"), ((64, 48), "he"), ((512, 512), "vgf"),
+                ((1024, 1024), "vgf")]
 
 
 @pytest.mark.parametrize("n,method", KERNEL_CASES)
@@ -145,6 +146,52 @@ def test_fft_lengths_3d_long_axes(n):
         phi_o, E_o = oracle_solve("vgf", n, h, plan.L, r)
         check_fields(phi_g, E_g, phi_o, E_o, tol, "long %s %s" % (n, precision))
         plan.close()
+
+
+# 2D grids of 576 .. 1024 points per axis: FFT lengths 1152 .. 2048, which the
+# library builds for the 2D default layout only
+WIDE_2D_CASES = [((1024, 1024), "f64"), ((1024, 1024), "f32"), ((576, 648), "f64"), ((768, 972), "f32"),
+                 ((864, 96), "f64"), ((96, 1024), "f32")]
+
+
+def _mixture(n, h, seed):
+    """Eight Gaussians of the 2D example's recipe (centres in [-0.5, 0.5]^2,
+    sigma in [0.05, 0.15], weights +-1) on the grid starting at -1."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-0.5, 0.5, (8, 2))
+    s = rng.uniform(0.05, 0.15, 8)
+    q = rng.choice([-1.0, 1.0], 8)
+    return W.gaussian_density(n, (-1.0, -1.0), h, c, np.repeat(s[:, None], 2, axis=1), q)
+
+
+@pytest.mark.parametrize("n,precision", WIDE_2D_CASES)
+def test_wide_2d_grids(n, precision):
+    """phi + E against the oracle, and at 1024^2 FP64 the adjoint too. FP64
+    takes the 2D example's Gaussian mixture: with white noise the fields are
+    dominated by the highest frequencies, where the kernel spectrum is
+    smallest, so the rounding of the two precomputes (GEMMs here, direct sums
+    in the oracle; the kernels agree to 1e-14 relative) reaches ~2e-12 in E
+    at 1024^2. FP32 takes white noise (its own rounding dominates)."""
+    torch, vgf = need_gpu()
+    h = (2.0 / (n[0] - 1), 2.2 / (n[1] - 1))
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    src = _mixture(n, h, sum(n)) if precision == "f64" else W.random_field(sum(n) + 1, n)
+    rho = rounded_input(src, precision)
+    say("wide 2D", n, precision)
+    plan = make_plan(n, h, "vgf", precision)
+    phi_g, E_g = gpu_solve(plan, rho)
+    w = orc.vgf_kernel(n, h, plan.L)
+    phi_o, E_o = orc.solve_fft2n(n, h, w, rho)
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "wide %s %s" % (n, precision))
+    if n == (1024, 1024) and precision == "f64":
+        y = _mixture(n, h, 5)
+        z = np.stack([_mixture(n, h, 6), _mixture(n, h, 7)])
+        dt = plan.dtype
+        g = plan.adjoint(torch.from_numpy(y).to("cuda", dt), torch.from_numpy(z).to("cuda", dt))
+        e = err(g.double().cpu().numpy(), orc.adjoint_fft2n(n, h, w, y, z))
+        say("  adjoint vs oracle %.3e" % e)
+        assert e <= tol
+    plan.close()
 
 
 def test_rectangular_grid():

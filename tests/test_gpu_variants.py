@@ -173,6 +173,8 @@ def test_paper_3d_sweep_all_methods():
 # transform of -i k_a Ghat.
 # ---------------------------------------------------------------------------
 GRAD_CASES = [((16, 12, 24), (0.1, 0.12, 0.07)), ((32, 32, 32), None), ((48, 64), (0.04, 0.03))]
+# a 2D grid with the longer FFT lengths (default layout only)
+GRAD_WIDE = ((576, 1024), (2.0 / 575, 2.0 / 1023))
 
 
 def _grid(n, h):
@@ -226,6 +228,22 @@ def test_gradient_kernel_solve_and_adjoint(precision, n, h, layout):
     e = err(g_rho, ref)
     say("gradk adjoint %s %s %s rel-L2 %.3e" % (n, precision, layout, e))
     assert e <= tol
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gradient_kernel_wide_2d(precision):
+    torch, vgf = need_gpu()
+    n, h = GRAD_WIDE
+    plan = gpu_plan(vgf, n, h, method="vgf", precision=precision, field="gradient_kernel")
+    tol = FP64_TOL if precision == "f64" else FP32_TOL
+    # a smooth charge (white noise would make the FP64 fields hinge on the
+    # rounding of the two precomputes at the highest frequencies)
+    c, s = np.array([[0.1, -0.2], [-0.3, 0.25]]), np.array([[0.08, 0.1], [0.12, 0.06]])
+    rho = rounded_input(W.gaussian_density(n, (-1.0, -1.0), h, c, s, np.array([1.0, -0.7])), precision)
+    phi_g, E_g = gpu_solve(plan, rho)
+    phi_o, E_o = orc.solve_grad_kernel(n, h, plan.L, rho)
+    check_fields(phi_g, E_g, phi_o, E_o, tol, "gradk wide %s %s" % (n, precision))
     plan.close()
 
 
