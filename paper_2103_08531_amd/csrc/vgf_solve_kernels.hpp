@@ -1498,10 +1498,12 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
   using TW = TileW<T, P, V>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
-  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
-  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
-  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  // one 512-point line per wavefront: the bank-conflict-free layout 2
+  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : 1;
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, LAY>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, LAY>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, LAY>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, LAY>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LPW * LP];
   __shared__ C twl[tw_both_size<P>()];
@@ -1542,7 +1544,7 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
       S0::lds_out(g0, tile, l, q);
       wave_sync();
       typename SL::Regs rh;
-      middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+      middle_and_last<T, P, 64, LPW, LP, -1, LAY, true>(rh, tile, twl, l, q);
       const bool d = g.fields[fi] != 0;
 #pragma unroll
       for (int t = 0; t < SL::NTASK; ++t) {
@@ -1573,7 +1575,7 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
     IS0::lds_out(acc, tile, l, q);
     wave_sync();
     typename ISL::Regs o;
-    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+    middle_and_last<T, P, 64, LPW, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), l, q);
     if (valid) {
       C* __restrict__ dst = out + wk.e * g.out_es + lofs;
       ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
@@ -1611,10 +1613,12 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   using TW = TileW<T, P>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
-  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
-  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
-  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  // one 512-point line per wavefront: the bank-conflict-free layout 2
+  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : 1;
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, LAY>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, LAY>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, LAY>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, LAY>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LPW * LP];
   __shared__ C twl[tw_both_size<P>()];
@@ -1653,7 +1657,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
     S0::lds_out(x, tile, l, q);
     wave_sync();
     typename SL::Regs rh;  // the line's spectrum
-    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+    middle_and_last<T, P, 64, LPW, LP, -1, LAY, true>(rh, tile, twl, l, q);
     for (int fi = 0; fi < g.nf; ++fi) {
       const int f = g.fields[fi];
       const T* __restrict__ srow = sp.s[f] + (int64_t)row * (N + 1);
@@ -1673,7 +1677,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       IS0::lds_out(v, tile, l, q);
       wave_sync();
       typename ISL::Regs o;
-      middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+      middle_and_last<T, P, 64, LPW, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), l, q);
       if (valid) {
         C* __restrict__ d = out + e * g.out_es + fi * g.fs + lofs;
         if (g.nt)
@@ -1697,10 +1701,12 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   using TW = TileW<T, P>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
-  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
-  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
-  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  // one 512-point line per wavefront: the bank-conflict-free layout 2
+  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : 1;
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, LAY>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, LAY>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, LAY>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, LAY>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LPW * LP];
   __shared__ C twl[tw_both_size<P>()];
@@ -1743,7 +1749,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       S0::lds_out(g0, tile, l, q);
       wave_sync();
       typename SL::Regs rh;
-      middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+      middle_and_last<T, P, 64, LPW, LP, -1, LAY, true>(rh, tile, twl, l, q);
       const T* __restrict__ srow = sp.s[f] + (int64_t)row * (N + 1);
 #pragma unroll
       for (int t = 0; t < SL::NTASK; ++t) {
@@ -1766,7 +1772,7 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
     IS0::lds_out(acc, tile, l, q);
     wave_sync();
     typename ISL::Regs o;
-    middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+    middle_and_last<T, P, 64, LPW, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), l, q);
     if (valid) {
       C* __restrict__ dst = out + e * g.out_es + lofs;
       ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
