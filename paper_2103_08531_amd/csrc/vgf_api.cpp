@@ -775,6 +775,10 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   ca.in_es = en.es;
   ca.ncols = vol / N0;
   ca.nentry = en.count;
+  // FP32 reads phi's spectrum a second time for E_0: non-temporal loads of
+  // the once-read inputs keep those columns in the caches (C2R 157 -> 152 us
+  // at 256^3); FP64 holds them in registers, and the hint only slowed it
+  ca.nt_x = nt && sizeof(T) == 4;
   if (want_phi && want_E) {
     ca.d = deriv2<T>(p, 0, 0, -1);
     c2r_s_out(ca, 0, en, -1, vol);

@@ -190,6 +190,9 @@ template <typename T> struct C2RSArgs {
   // same launch (inputs laid out like `in`)
   const cplx<T>* in_x[3];
   int nx;
+  // non-temporal loads of the in_x inputs (read once; keeps `in`, which the
+  // second output of `in` reads again, in the caches)
+  bool nt_x = false;
 };
 // Lines along the contiguous last axis (length n_last in, 2 n_last transformed)
 // of the arrays [H0][P1][n_last] (3D) or [H0][n_last] (2D), H0 = n0 + 1; line

@@ -79,6 +79,16 @@ __device__ __forceinline__ void load_pair(const double2* p, double2& a, double2&
   a = p[0];
   b = p[1];
 }
+__device__ __forceinline__ void load_pair_nt(const float2* p, float2& a, float2& b) {
+  typedef float V __attribute__((ext_vector_type(4)));
+  const V w = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  a = make_float2(w.x, w.y);
+  b = make_float2(w.z, w.w);
+}
+__device__ __forceinline__ void load_pair_nt(const double2* p, double2& a, double2& b) {
+  a = load_nt(p);
+  b = load_nt(p + 1);
+}
 __device__ __forceinline__ void store_pair(float2* p, float2 a, float2 b) {
   *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
 }
@@ -1166,16 +1176,17 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   // workgroups per CU allow, and reading them again from cache is faster
   constexpr bool HOLD = sizeof(T) == 8;
   C xs[NSLOT], ys[NSLOT];
-  auto load = [&](const C* __restrict__ src) {
+  auto load = [&](const C* __restrict__ src, bool nt) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
       const int k = q0 + NQ * s;
       xs[s] = ys[s] = C{T(0), T(0)};
       if (k >= H) continue;
-      load_pair(src + k * a.ncols, xs[s], ys[s]);
+      if (nt) load_pair_nt(src + k * a.ncols, xs[s], ys[s]);
+      else load_pair(src + k * a.ncols, xs[s], ys[s]);
     }
   };
-  load(in);
+  load(in, false);
   stage_twiddles<C, P, NT, 1>(twl, tw, tid);
 
 #pragma unroll
@@ -1188,7 +1199,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
       // transform
       uint32_t z = 0;
       asm volatile("" : "+s"(z));
-      load((own ? in : a.in_x[o - a.d.n] + e * a.in_es + 2 * (int64_t)ci.col) + z);
+      load((own ? in : a.in_x[o - a.d.n] + e * a.in_es + 2 * (int64_t)ci.col) + z, !own && a.nt_x);
     }
     __syncthreads();  // twiddles staged / the previous output's reads are done
     // this output's copies of the thread's line and position: the compiler
