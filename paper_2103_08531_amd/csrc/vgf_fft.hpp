@@ -27,6 +27,7 @@
 #include <utility>
 
 #include "vgf_internal.hpp"
+#include "vgf_lds_pads.hpp"
 
 namespace vgf {
 
@@ -279,10 +280,12 @@ constexpr bool stage_scaled(int R, int NS) { return NS > 1 && (R == 8 || R == 4)
 // one wavefront per line group; the pad keeps radix-8 scatters free of bank
 // conflicts); 2 = [line][position] of a 512-point line held by one wavefront
 // (three radix-8 stages, one butterfly per lane), with a layout of its own for
-// each of the two exchanges (see Stage::in_index).
+// each of the two exchanges (see Stage::in_index); 3 = [line][position] with a
+// pad of its own per exchange, p + k (p >> s), from the table lds_pad (the
+// pad of layout 1 where the table keeps it).
 template <int LAYOUT, int LP>
 __device__ __forceinline__ int lds_index(int pos, int l) {
-  static_assert(LAYOUT == 0 || LAYOUT == 1, "layout 2 is addressed per exchange");
+  static_assert(LAYOUT == 0 || LAYOUT == 1, "layouts 2 and 3 are addressed per exchange");
   if constexpr (LAYOUT == 0) return pos * LP + l;
   else return l * LP + pos + (pos >> 3);
 }
@@ -386,8 +389,36 @@ struct Stage {
   // take a2 = r and (a1, a0) = lane digits: every access of the three
   // patterns then touches distinct slots, while layout 1 serves the reads in
   // two passes.
+  // layout 1 addressing (also layout 3 where its table keeps that pad)
+  __device__ __forceinline__ static int in_index1(int j, int r, int l) {
+    if constexpr (NB % 8 == 0) return l * LP + j + (j >> 3) + r * (NB + NB / 8);
+    else return lds_index<1, LP>(in_pos(j, r), l);
+  }
+  __device__ __forceinline__ static int out_index1(int j, int r, int l) {
+    if constexpr (NS % 8 == 0 || (NS == 1 && 8 % R == 0)) {
+      const int u = (j / NS) * NS * R + (j % NS);
+      return l * LP + u + (u >> 3) + r * (NS == 1 ? 1 : NS + NS / 8);
+    } else {
+      return lds_index<1, LP>(out_pos(j, r), l);
+    }
+  }
+  // layout 3: the pad of exchange S - 1 (reads) or S (writes); the table
+  // holds only pads under which every access is a per-lane base plus r times
+  // a constant
+  static constexpr LdsPad pad_in() { return lds_pad(P, SIGN, S - 1, NQ); }
+  static constexpr LdsPad pad_out() { return lds_pad(P, SIGN, S, NQ); }
+  static constexpr bool pad1(LdsPad p) { return p.k == 1 && p.s == 3; }
+
   __device__ __forceinline__ static int in_index(int j, int r, int l) {
-    if constexpr (LAYOUT == 2) {
+    if constexpr (LAYOUT == 3) {
+      constexpr LdsPad pd = pad_in();
+      if constexpr (pad1(pd)) {
+        return in_index1(j, r, l);
+      } else {
+        constexpr int step = NB + pd.k * (NB >> pd.s);
+        return l * LP + j + pd.k * (j >> pd.s) + r * step;
+      }
+    } else if constexpr (LAYOUT == 2) {
       static_assert(P == 512 && R == 8 && NQ == 64 && NTASK == 1 && S >= 1, "layout 2: 512-point lines");
       if constexpr (S == 1) return l * LP + 18 * (j >> 4) + ((j >> 3) & 1) + 2 * (j & 7) + 72 * r;
       else return l * LP + j + 72 * r;
@@ -398,7 +429,16 @@ struct Stage {
     }
   }
   __device__ __forceinline__ static int out_index(int j, int r, int l) {
-    if constexpr (LAYOUT == 2) {
+    if constexpr (LAYOUT == 3) {
+      constexpr LdsPad pd = pad_out();
+      if constexpr (pad1(pd)) {
+        return out_index1(j, r, l);
+      } else {
+        constexpr int step = NS + pd.k * (NS >> pd.s);
+        const int u = (j / NS) * NS * R + (j % NS);
+        return l * LP + u + pd.k * (u >> pd.s) + r * step;
+      }
+    } else if constexpr (LAYOUT == 2) {
       static_assert(P == 512 && R == 8 && NQ == 64 && NTASK == 1 && S <= 1, "layout 2: 512-point lines");
       if constexpr (S == 0) return l * LP + 72 * (j >> 3) + 18 * ((j & 7) >> 1) + (j & 1) + 2 * r;
       else return l * LP + 72 * (j >> 3) + (j & 7) + 8 * r;

@@ -223,6 +223,12 @@ template <int P> constexpr int wave_nq() {
 #ifndef VGF_LAY2
 #define VGF_LAY2 1
 #endif
+// the multiply passes exchange other lengths through the per-exchange pads of
+// layout 3 (1) or the pad of layout 1 (0)
+#ifndef VGF_LAY3
+#define VGF_LAY3 1
+#endif
+constexpr int kPadLayout = VGF_LAY3 ? 3 : 1;
 constexpr int64_t kFusedCMinBlocks = 2048;
 // V = 1 (the multiply pass's second lane schedule): half the lanes per line,
 // twice the lines per wavefront and twice the butterflies per lane, where the
@@ -1277,10 +1283,11 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
   using TW = TileW<T, P, V>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, 1>;
-  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, 1>;
-  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, 1>;
-  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, 1>;
+  // exchanges through the per-exchange pads of layout 3
+  using S0 = Stage<T, P, 64, LPW, LP, -1, 0, kPadLayout>;
+  using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, kPadLayout>;
+  using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, kPadLayout>;
+  using ISL = Stage<T, P, 64, LPW, LP, 1, NSTG - 1, kPadLayout>;
   static_assert(IS0::R == SL::R && IS0::NTASK == SL::NTASK, "register hand-off");
   __shared__ C tiles[TW::WPB * LPW * LP];
   __shared__ C twl[tw_both_size<P>()];
@@ -1341,7 +1348,7 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
     valid = line < g.nlines;
     wave_sync();
     typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
-    middle_and_last<T, P, 64, LPW, LP, -1, 1, true>(rh, tile, twl, l, q);
+    middle_and_last<T, P, 64, LPW, LP, -1, kPadLayout, true>(rh, tile, twl, l, q);
 #pragma unroll
     for (int t = 0; t < SL::NTASK; ++t) {
       if (!SL::active(t, q)) continue;
@@ -1369,7 +1376,7 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
       IS0::lds_out(v, tile, l, q);
       wave_sync();
       typename ISL::Regs o;
-      middle_and_last<T, P, 64, LPW, LP, 1, 1, true>(o, tile, tw_inverse<P>(twl), l, q);
+      middle_and_last<T, P, 64, LPW, LP, 1, kPadLayout, true>(o, tile, tw_inverse<P>(twl), l, q);
       if (store) {
         C* __restrict__ d = dst + fi * g.fs;
         if (g.nt)
@@ -1398,8 +1405,9 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   static_assert(TW::LPW == 1 && TW::NQ == 64, "one line per wavefront");
   constexpr int LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  // 512-point lines exchange through the bank-conflict-free layout 2
-  constexpr int LAY = (VGF_LAY2 && P == 512) ? 2 : 1;
+  // 512-point lines exchange through the bank-conflict-free layout 2, the
+  // other lengths through the per-exchange pads of layout 3
+  constexpr int LAY = (VGF_LAY2 && P == 512) ? 2 : kPadLayout;
   using S0 = Stage<T, P, 64, 1, LP, -1, 0, LAY>;
   using SL = Stage<T, P, 64, 1, LP, -1, NSTG - 1, LAY>;
   using IS0 = Stage<T, P, 64, 1, LP, 1, 0, LAY>;
@@ -1509,8 +1517,9 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
   using TW = TileW<T, P, V>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  // one 512-point line per wavefront: the bank-conflict-free layout 2
-  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : 1;
+  // one 512-point line per wavefront: the bank-conflict-free layout 2;
+  // otherwise the per-exchange pads of layout 3
+  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : kPadLayout;
   using S0 = Stage<T, P, 64, LPW, LP, -1, 0, LAY>;
   using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, LAY>;
   using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, LAY>;
@@ -1624,8 +1633,9 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   using TW = TileW<T, P>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  // one 512-point line per wavefront: the bank-conflict-free layout 2
-  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : 1;
+  // one 512-point line per wavefront: the bank-conflict-free layout 2;
+  // otherwise the per-exchange pads of layout 3
+  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : kPadLayout;
   using S0 = Stage<T, P, 64, LPW, LP, -1, 0, LAY>;
   using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, LAY>;
   using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, LAY>;
@@ -1712,8 +1722,9 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   using TW = TileW<T, P>;
   constexpr int NQ = TW::NQ, LPW = TW::LPW, LP = TW::LP, N = P / 2;
   constexpr int NSTG = n_stages(P);
-  // one 512-point line per wavefront: the bank-conflict-free layout 2
-  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : 1;
+  // one 512-point line per wavefront: the bank-conflict-free layout 2;
+  // otherwise the per-exchange pads of layout 3
+  constexpr int LAY = (VGF_LAY2 && P == 512 && LPW == 1 && NQ == 64) ? 2 : kPadLayout;
   using S0 = Stage<T, P, 64, LPW, LP, -1, 0, LAY>;
   using SL = Stage<T, P, 64, LPW, LP, -1, NSTG - 1, LAY>;
   using IS0 = Stage<T, P, 64, LPW, LP, 1, 0, LAY>;
