@@ -84,6 +84,8 @@ def kernel_source_hash(root=None):
     pkg = os.path.join(root or ROOT, "paper_2103_08531_amd")
     csrc = os.path.join(pkg, "csrc")
     for name in sorted(os.listdir(csrc)):
+        if not os.path.isfile(os.path.join(csrc, name)) or name.endswith(".pyc"):
+            continue  # caches a test run may leave beside the sources
         with open(os.path.join(csrc, name)) as f:
             h.update(name.encode() + b"\0" + _code_only(f.read()).encode())
     with open(os.path.join(pkg, "build.py"), "rb") as f:

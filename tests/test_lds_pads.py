@@ -3,9 +3,9 @@ every entry keeps each line inside its pitch, is one-to-one, and keeps every
 exchange access a per-lane base plus r times a constant (the form the
 kernels address); and the committed table is the generator's output for a
 sample of lengths (the full table takes about a minute to regenerate)."""
-import importlib.util
 import os
 import re
+import types
 
 import pytest
 
@@ -14,9 +14,10 @@ CSRC = os.path.join(HERE, "..", "paper_2103_08531_amd", "csrc")
 
 
 def _gen():
-    spec = importlib.util.spec_from_file_location("gen_lds_pads", os.path.join(CSRC, "gen_lds_pads.py"))
-    m = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(m)
+    # loaded without writing a bytecode cache beside the library sources
+    m = types.ModuleType("gen_lds_pads")
+    path = os.path.join(CSRC, "gen_lds_pads.py")
+    exec(compile(open(path).read(), path, "exec"), m.__dict__)
     return m
 
 
