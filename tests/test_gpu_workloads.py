@@ -6,6 +6,11 @@ beam_3d_256     3D 256^3 VGF, phi + E, FP64 (<= 1e-12) and FP32 (<= 1e-5):
                 potentials against the FFT-free direct sums.
 batch_3d_mixed  64 right-hand sides of uneven N in {32,48,64,96,128}, FP32:
                 every one against the oracle, and batched == one at a time.
+variants_256    the comparison variants bench.py times on the beam input, FP32,
+                phi + E, each on its own autotuned plan: HE with its three
+                origin conventions, the axis-0 layout, the finite-difference
+                and gradient-kernel fields (both layouts) and the rectangular
+                256 x 128 x 192 grid, full grids against the oracle.
 diff_3d_128     8 right-hand sides at 128^3, FP32, E only: the gradient of
                 sum ||E(rho) - E_target||^2 through the hand-written adjoint
                 (torch.autograd) against the FP64 oracle gradient and against
@@ -36,8 +41,24 @@ def beam_kernel(beam):
     return L, orc.vgf_kernel(ch.n, ch.h, L)
 
 
+@pytest.fixture(scope="module")
+def beam_oracle(beam, beam_kernel):
+    """The oracle's 2N-path phi and E of the beam for each precision's rounded
+    input, computed once and shared by the tests of this module."""
+    ch, rho = beam
+    L, w = beam_kernel
+    memo = {}
+
+    def get(precision):
+        if precision not in memo:
+            say("  oracle 2N path 256^3 (%s input) ..." % precision)
+            memo[precision] = orc.solve_fft2n(ch.n, ch.h, w, rounded_input(rho, precision))
+        return memo[precision]
+    return get
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_beam_3d_256(beam, beam_kernel, precision):
+def test_beam_3d_256(beam, beam_kernel, beam_oracle, precision):
     torch, vgf = need_gpu()
     ch, rho64 = beam
     L, w = beam_kernel
@@ -47,8 +68,7 @@ def test_beam_3d_256(beam, beam_kernel, precision):
     rho = rounded_input(rho64, precision)
     phi_g, E_g = gpu_solve(plan, rho)
     plan.close()
-    say("  oracle 2N path 256^3 ...")
-    phi_o, E_o = orc.solve_fft2n(ch.n, ch.h, w, rho)
+    phi_o, E_o = beam_oracle(precision)
     tol = FP64_TOL if precision == "f64" else FP32_TOL
     check_fields(phi_g, E_g, phi_o, E_o, tol, "beam %s" % precision)
     # sampled points against the direct discrete convolution (no FFT at all)
@@ -71,6 +91,87 @@ def test_beam_3d_256(beam, beam_kernel, precision):
         ea = rel_l2(phi_g[sub], pa)
         say("  vs analytic (stride 8): phi %.3e E %.3e" % (ea, rel_l2(E_g[(slice(None),) + sub], Ea)))
         assert ea < 5e-3
+
+
+@pytest.fixture(scope="module")
+def beam_grad_field(beam, beam_kernel):
+    """E_a = w_a * rho on the FP32-rounded beam input, with the oracle's
+    restricted 4N gradient kernels (one per axis)."""
+    ch, rho = beam
+    L, _ = beam_kernel
+    rho32 = rounded_input(rho, "f32")
+    say("  oracle gradient kernels and fields 256^3 ...")
+    return np.stack([orc.conv_fft2n(ch.n, orc.periodic_kernel_odd(ch.n, orc.vgf_grad_kernel(ch.n, ch.h, L, a), a),
+                                    rho32) for a in range(3)])
+
+
+# (name, plan options) as bench.py times them at 256^3 FP32
+VARIANTS_256 = [("vgf_axis0_layout", {"layout": "axis0"}), ("he", {"method": "he"}),
+                ("he_nearby", {"method": "he_nearby"}), ("he_cellavg", {"method": "he_cellavg"}),
+                ("vgf_fd_field", {"field": "centered"}), ("vgf_gradient_kernel", {"field": "gradient_kernel"}),
+                ("vgf_gradient_kernel_axis0_layout", {"field": "gradient_kernel", "layout": "axis0"}),
+                ("vgf_rect_256x128x192", {"n": (256, 128, 192)})]
+
+
+@pytest.mark.parametrize("name,opts", VARIANTS_256, ids=[v[0] for v in VARIANTS_256])
+def test_variants_256(beam, beam_oracle, beam_grad_field, name, opts):
+    torch, vgf = need_gpu()
+    ch, rho64 = beam
+    opts = dict(opts)
+    n = opts.pop("n", ch.n)
+    method = opts.pop("method", "vgf")
+    rho_np = np.ascontiguousarray(rho64[tuple(slice(0, x) for x in n)])
+    rho32 = rounded_input(rho_np, "f32")
+    say("variant", name, n)
+    plan = gpu_plan(vgf, n, ch.h, method=method, precision="f32", **opts)
+    rho = torch.from_numpy(rho32).to("cuda", torch.float32)
+    phi = torch.empty(n, dtype=torch.float32, device="cuda")
+    E = torch.empty((3,) + n, dtype=torch.float32, device="cuda")
+    sched = plan.autotune(rho, phi, E, reps=3)
+    plan.solve(rho, phi, E)
+    torch.cuda.synchronize()
+    phi_g, E_g = phi.double().cpu().numpy(), E.double().cpu().numpy()
+    plan.close()
+    say("  schedule", list(sched))
+    if method != "vgf":
+        phi_o, E_o = orc.solve_fft2n(n, ch.h, orc.he_kernel(n, ch.h, orc.HE_MODES[method]), rho32)
+    elif n != ch.n:
+        phi_o, E_o = orc.solve_fft2n(n, ch.h, orc.vgf_kernel(n, ch.h, orc.default_L(n, ch.h)), rho32)
+    else:
+        phi_o, E_o = beam_oracle("f32")
+        if opts.get("field") == "centered":
+            check_fields(phi_g, None, phi_o, None, FP32_TOL, name)
+            check_fd_field(phi_g, E_g, phi_o, orc.fd_field(n, ch.h, phi_o), ch.h, name)
+            return
+        if opts.get("field") == "gradient_kernel":
+            E_o = beam_grad_field
+    check_fields(phi_g, E_g, phi_o, E_o, FP32_TOL, name)
+
+
+def check_fd_field(phi_g, E_g, phi_o, E_o, h, label):
+    """The finite-difference field against the oracle's differences of its own
+    phi. The stencil (centred inside, one-sided second order at the ends) has
+    weights of at most 8 / (2 h_a) in absolute sum per row and, per column, at
+    most 5 / (2 h_a), so its 2-norm is at most sqrt(4 * 2.5) / h_a. The GPU
+    field therefore differs from the oracle's by at most the stencil applied
+    to phi's error (max |dphi| and ||dphi||_2 measured here, phi itself being
+    held to the FP32 bar above) plus the FP32 evaluation of the stencil
+    (8 u max |phi| / h_a) and the rounding of the scaled result (2 u |E|)."""
+    u = 2.0 ** -24
+    d = phi_g - phi_o
+    e_max, e_l2 = float(np.max(np.abs(d))), float(np.sqrt(np.sum(d * d)))
+    p_max, p_l2 = float(np.max(np.abs(phi_o))), float(np.sqrt(np.sum(phi_o * phi_o)))
+    for a in range(E_o.shape[0]):
+        g, o = E_g[a], E_o[a]
+        o_max, o_l2 = float(np.max(np.abs(o))), float(np.sqrt(np.sum(o * o)))
+        m = float(np.max(np.abs(g - o)))
+        l2 = float(np.sqrt(np.sum((g - o) ** 2)))
+        m_bound = (4.0 * e_max + 8.0 * u * p_max) / h[a] + 2.0 * u * o_max
+        l2_bound = (np.sqrt(10.0) * e_l2 + 8.0 * u * p_l2) / h[a] + 2.0 * u * o_l2
+        say("%s E%d max %.3e (bound %.3e) rel-L2 %.3e (bound %.3e)"
+            % (label, a, m / o_max, m_bound / o_max, l2 / o_l2, l2_bound / o_l2))
+        assert m <= m_bound, (label, a, m, m_bound)
+        assert l2 <= l2_bound, (label, a, l2, l2_bound)
 
 
 def test_batch_3d_mixed():
