@@ -131,9 +131,14 @@ def _torch():
 
 def _stream(stream=None):
     torch = _torch()
-    if stream is None:
-        stream = torch.cuda.current_stream()
-    return C.c_void_p(stream.cuda_stream)
+    if stream is not None:
+        return C.c_void_p(stream.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        # the current stream's handle without building a Stream object (a few
+        # microseconds per call, which small solves notice)
+        return C.c_void_p(raw(torch.cuda.current_device()))
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _ptr(t):

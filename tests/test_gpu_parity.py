@@ -383,3 +383,25 @@ def test_axis0_layout_matches_oracle(n, method, precision):
         res[layout] = phi_g
         plan.close()
     assert rel_l2(res["axis0"], res["contiguous"]) <= 2 * tol
+
+
+def test_solve_follows_the_current_stream():
+    """With no stream argument the binding enqueues on torch's current stream:
+    inside a side-stream context the solve runs there, with the same result."""
+    torch, vgf = need_gpu()
+    n = (32, 24, 16)
+    h = tuple(2.0 / (x - 1) for x in n)
+    plan = make_plan(n, h)
+    rho = torch.from_numpy(W.random_field(31, n)).to("cuda", torch.float64)
+    phi0, E0 = plan.solve(rho)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    # c_void_p(0).value is None: the default stream's handle is 0
+    assert (vgf._stream().value or 0) == torch.cuda.current_stream().cuda_stream
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        assert (vgf._stream().value or 0) == side.cuda_stream != 0
+        phi1, E1 = plan.solve(rho)
+    side.synchronize()
+    assert torch.equal(phi0, phi1) and torch.equal(E0, E1)
+    plan.close()
