@@ -131,7 +131,9 @@ enum {
  * Environment, read here: VGF_STREAM_MIN_BYTES (default 33554432): forward
  * solves in the default layout whose input (rho of all entries of a launch)
  * has at least this many bytes use non-temporal loads and stores in their
- * middle passes; results are identical either way, only speed differs.
+ * middle passes; VGF_TILED_Y=0: 3D forward solves in the default layout keep
+ * the multiply pass's output in plain rows instead of the axis-1 inverse's
+ * tile order. Results are identical either way, only speed differs.
  * Errors: INVALID_ARG, UNSUPPORTED_SIZE, L_WINDOW, OUT_OF_MEMORY, HIP. On
  * error *out is set to NULL and nothing is leaked. */
 vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const double* h,

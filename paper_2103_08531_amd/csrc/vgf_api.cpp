@@ -68,6 +68,7 @@ struct vgf_plan_s {
   void* specg = nullptr;         // [dim][prod(n+1)] plan type, scaled by 1/prod(P)
   size_t off_phi = 0;            // real phi array in the workspace (fd only)
   int64_t stream_min = 0;        // input bytes per launch from which solves stream (stream_min_env)
+  bool tile_y = true;            // 3D default layout: tiled hand-off to the axis-1 inverse (tile_y_env)
   size_t bytes = 0;
   hipError_t last_err = hipSuccess;
 
@@ -222,6 +223,31 @@ int64_t stream_min_env() {
   const long long v = std::strtoll(e, &end, 10);
   if (end == e) return kDefault;  // not a number
   return v < 0 ? 0 : (int64_t)v;
+}
+
+// VGF_TILED_Y=0 keeps the multiply pass's output in plain rows (the tiled
+// hand-off to the axis-1 inverse is the default). Read once per plan.
+bool tile_y_env() {
+  const char* e = std::getenv("VGF_TILED_Y");
+  return !(e && e[0] == '0' && e[1] == 0);
+}
+
+// log2 of the block width B of the tiled hand-off from the multiply pass to
+// the axis-1 inverse (3D, default layout), 0 where it is not used. B is the
+// inverse's default tile width (one 128-byte row segment, halved while a
+// tile of P1 rows would exceed 64 KiB), so each of its workgroups reads one
+// contiguous block; n_last and the butterfly count of the last inverse stage
+// along the last axis must be multiples of B.
+template <typename T> int y_tile_log2(vgf_plan p) {
+  if (!p->tile_y || p->dim != 3) return 0;
+  const int64_t P1 = p->P[1], P2 = p->P[2], N2 = p->n[2];
+  int b = sizeof(T) == 4 ? 16 : 8;
+  while (b > 1 && P1 * b * 2 * (int64_t)sizeof(T) > 65536) b /= 2;
+  const int64_t nb_last = P2 / vgf::fwd_radix((int)P2, 0);
+  if (b < 2 || N2 % b != 0 || nb_last % b != 0) return 0;
+  int sh = 0;
+  while ((1 << sh) < b) ++sh;
+  return sh;
 }
 
 size_t max_workspace_env() {
@@ -731,6 +757,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
   g.ks = (T)wavenumber_step(p, d - 1);
   g.nf = want_E ? 2 : 1;
   g.nt = nt;
+  g.ytile = y_tile_log2<T>(p);
   if (d == 3) {
     const int64_t P1 = p->P[1], N2 = NL;
     vgf::StridedGeom fg{N2, N2, N2, N1 * N2, P1 * N2, (int)H0};
@@ -753,6 +780,7 @@ vgf_status enqueue_solve_c(vgf_plan p, const Entries<T>& en, hipStream_t s, bool
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
     ig.nt_load = ig.nt_store = nt;
+    ig.in_tile = g.ytile;  // the multiply pass wrote this launch's tile order
     // one launch: phi and E_1 from phi's spectrum, E_2 from its own
     vgf::C2CInvArgs<T> ia{b.y, {b.z, b.z + zfs}, ig, want_E ? deriv2<T>(p, 1, 0, -1) : deriv1<T>(p, 1, 0)};
     if (want_E) {
@@ -1604,6 +1632,7 @@ vgf_status vgf_plan_create(vgf_plan* out, int dim, const int64_t* n, const doubl
   p->fd = (outputs & VGF_FIELD_CENTERED) != 0;
   p->gradk = (outputs & VGF_FIELD_GRADIENT_KERNEL) != 0;
   p->stream_min = stream_min_env();
+  p->tile_y = tile_y_env();
   // the multiply pass runs along the contiguous axis unless asked otherwise
   p->contig = !(outputs & VGF_LAYOUT_AXIS0);
 

@@ -64,6 +64,11 @@ struct StridedGeom {
   int64_t es_in = 0, es_out = 0;
   // non-temporal loads of the input / stores of the outputs (large arrays)
   bool nt_load = false, nt_store = false;
+  // inverse passes: log2 of the block width B of a tiled input (0: rows of
+  // ls_in elements). Tiled, column c of transform row k sits at
+  // (c >> log2 B) * P * B + k * B + (c mod B): the B columns of a workgroup's
+  // tile are one contiguous block of P rows.
+  int in_tile = 0;
 };
 
 // Spectral derivative factors along the transformed axis. A forward pass
@@ -209,6 +214,12 @@ template <typename T> struct FusedCGeom {
   int fields[4];      // adjoint: per input 0 or 1 (+i k_last); gradient kernels: 0 .. dim
                       // (the multipliers of GradSpec), up to four fields
   bool nt = false;    // forward: non-temporal loads and stores (large arrays)
+  // forward 3D: log2 of the block width B of the tiled output layout read by
+  // the axis-1 inverse (StridedGeom::in_tile), 0 for plain rows. Tiled,
+  // output x_last of line (k0, k1) sits at
+  // k0 P1 n_last + (x_last >> log2 B) P1 B + k1 B + (x_last mod B);
+  // n_last and the last inverse stage's butterfly count are multiples of B.
+  int ytile = 0;
 };
 template <typename T>
 hipError_t launch_r2c_s(int P, int variant, const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s);

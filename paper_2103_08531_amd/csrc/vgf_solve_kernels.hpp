@@ -215,6 +215,12 @@ template <int P> constexpr int wave_nq() {
 #ifndef VGF_FC_GPW
 #define VGF_FC_GPW 4
 #endif
+// line order of the forward multiply pass: 1 = the wavefronts of a workgroup
+// take neighbouring lines and step by WPB, 0 = each wavefront walks its own
+// gpw consecutive lines (same results either way)
+#ifndef VGF_FC_WALK
+#define VGF_FC_WALK 1
+#endif
 // multiply pass of P >= 512 through k_fused_c1 (1) or k_fused_c (0)
 #ifndef VGF_FC1
 #define VGF_FC1 1
@@ -538,8 +544,14 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
   const int tid = threadIdx.x, l0 = tid % NL, q0 = tid / NL;
   using S0 = Stage<T, P, NT, NL, LP, 1, 0>;
   using SL = Stage<T, P, NT, NL, LP, 1, NSTG - 1>;
-  const ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l0, a.g.ncols, a.g.ls_in);
+  ColIO ci(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l0, a.g.ncols, a.g.ls_in);
   const ColIO co(tile_of_block<V>(blockIdx.x, gridDim.x) * NL + l0, a.g.ncols, a.g.ls_out);
+  if (a.g.in_tile) {
+    // tiled input: the column's block of P rows of B elements
+    const uint32_t sh = (uint32_t)a.g.in_tile, c = ci.col;
+    ci.col = ((c >> sh) * (uint32_t)P << sh) + (c & ((1u << sh) - 1u));
+    ci.ls = 1u << sh;
+  }
   const int e = (int)blockIdx.y / a.g.nbatch, bb = (int)blockIdx.y - e * a.g.nbatch;
   const C* __restrict__ src = a.in + e * a.g.es_in + bb * a.g.bs_in;
   // NOUT = 3: outputs 0 and 1 from `in` (factors d), output 2 from in2
@@ -1268,8 +1280,8 @@ struct LineWalk {
 };
 
 // Multiply-and-inverse pass along the contiguous last axis: each wavefront
-// walks gpw consecutive groups of LPW lines (lanes along the line, every
-// exchange inside the wavefront). Line (k0, k1) of length n_last is
+// walks gpw groups of LPW lines (VGF_FC_WALK sets their order; lanes along
+// the line, every exchange inside the wavefront). Line (k0, k1) of length n_last is
 // transformed forward (pruned input), multiplied by the kernel-spectrum
 // octant row (k0, fold(k1)) at fold(k_last), and inverted (pruned output) as
 // phi's spectrum and, when requested, as -i k_last times it (E_last). The
@@ -1294,7 +1306,12 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l = lane / NQ, q = lane % NQ;
   C* tile = tiles + w * LPW * LP;
-  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw * LPW + l;
+  // VGF_FC_WALK: the workgroup's WPB wavefronts take consecutive line groups
+  // and step by WPB groups (neighbouring lines read and written together);
+  // else each wavefront walks its own gpw consecutive groups
+  constexpr int STEP = VGF_FC_WALK ? TW::WPB : 1;
+  int64_t line = (VGF_FC_WALK ? (int64_t)blockIdx.x * TW::WPB * gpw + w : ((int64_t)blockIdx.x * TW::WPB + w) * gpw) *
+                     LPW + l;
   LineWalk wk;
   wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
   wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
@@ -1339,12 +1356,17 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
     load_spec(valid);
     load_input(valid);
     const bool store = valid;
-    C* __restrict__ dst = store ? out + wk.e * g.out_es + ((int64_t)wk.k0 * wk.p1 + wk.k1) * N : out;
+    // plain rows: line (k0, k1) at (k0 p1 + k1) N; tiled: its B-element
+    // pieces at k0 p1 N + k1 B + (x >> log2 B) p1 B
+    C* __restrict__ dst = !store ? out
+                          : out + wk.e * g.out_es +
+                                (g.ytile ? (int64_t)wk.k0 * wk.p1 * N + ((int64_t)wk.k1 << g.ytile)
+                                         : ((int64_t)wk.k0 * wk.p1 + wk.k1) * N);
     S0::template butterflies<true>(x, q);
     wave_sync();  // the previous line's reads of the tile are done
     S0::lds_out(x, tile, l, q);
-    line += LPW;
-    wk.advance(LPW);
+    line += STEP * LPW;
+    wk.advance(STEP * LPW);
     valid = line < g.nlines;
     wave_sync();
     typename SL::Regs rh;  // forward spectrum, then times the kernel spectrum
@@ -1379,10 +1401,19 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
       middle_and_last<T, P, 64, LPW, LP, 1, kPadLayout, true>(o, tile, tw_inverse<P>(twl), l, q);
       if (store) {
         C* __restrict__ d = dst + fi * g.fs;
-        if (g.nt)
+        if (g.ytile) {
+          // position j + r NB: block (j >> sh) + r (NB >> sh), offset j mod B
+          const int sh = g.ytile, bs = wk.p1 << sh;
+          auto at = [&](int j, int r) { return (j >> sh) * bs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * bs; };
+          if (g.nt)
+            ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[at(j, r)], val); });
+          else
+            ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[at(j, r)] = val; });
+        } else if (g.nt) {
           ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
-        else
+        } else {
           ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
+        }
       }
     }
   }
@@ -1418,7 +1449,10 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   const int tid = threadIdx.x, q = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   C* tile = tiles + w * LP;
-  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw;
+  // VGF_FC_WALK: consecutive lines to the WPB wavefronts, then steps of WPB
+  // lines; else each wavefront walks its own gpw consecutive lines
+  constexpr int STEP = VGF_FC_WALK ? TW::WPB : 1;
+  int64_t line = VGF_FC_WALK ? (int64_t)blockIdx.x * TW::WPB * gpw + w : ((int64_t)blockIdx.x * TW::WPB + w) * gpw;
   LineWalk wk;
   wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
   wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
@@ -1440,13 +1474,17 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
     ISL::load_tw(twi, tw_inverse<P>(twl), q);
   }
 
-  for (int it = 0; it < gpw && line < g.nlines; ++it, ++line) {
+  for (int it = 0; it < gpw && line < g.nlines; ++it, line += STEP) {
     const int64_t lofs = ((int64_t)wk.k0 * wk.p1 + wk.k1) * N;
     const int row = g.dim == 3 ? wk.k0 * (g.n1 + 1) + (wk.k1 <= g.n1 ? wk.k1 : wk.p1 - wk.k1) : wk.k1;
     const T* __restrict__ srow = spec + (int64_t)row * (N + 1);
     const C* __restrict__ src = in + wk.e * g.in_es + lofs;
-    C* __restrict__ dst = out + wk.e * g.out_es + lofs;
-    wk.advance(1);
+    // plain rows, or the tiled layout: the line's B-element pieces at
+    // k0 p1 N + k1 B + (x >> log2 B) p1 B
+    C* __restrict__ dst = out + wk.e * g.out_es +
+                          (g.ytile ? (int64_t)wk.k0 * wk.p1 * N + ((int64_t)wk.k1 << g.ytile) : lofs);
+    const int ybs = wk.p1 << g.ytile;
+    wk.advance(STEP);
     typename S0::Regs x;
     if (g.nt)
       S0::template load_first<true>(x, q, [&](int j, int r) { return load_nt(&src[S0::in_pos(j, r)]); });
@@ -1498,10 +1536,19 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       if constexpr (TWREG) middle_and_last_tw<T, P, 64, 1, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), twi, 0, q);
       else middle_and_last<T, P, 64, 1, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), 0, q);
       C* __restrict__ d = dst + fi * g.fs;
-      if (g.nt)
+      if (g.ytile) {
+        // position j + r NB: block (j >> sh) + r (NB >> sh), offset j mod B
+        const int sh = g.ytile;
+        auto at = [&](int j, int r) { return (j >> sh) * ybs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * ybs; };
+        if (g.nt)
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[at(j, r)], val); });
+        else
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[at(j, r)] = val; });
+      } else if (g.nt) {
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
-      else
+      } else {
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
+      }
     });
   }
 }

@@ -186,3 +186,42 @@ def test_batch_autotune_keeps_results():
     batch.close()
     for p in plans.values():
         p.close()
+
+
+# tiled: (16, 24, 128), (48, 64, 96), (64, 32, 256), and (8, 512, 64) with
+# half-width blocks (P1 = 1024); plain rows kept: (24, 16, 32) (8 butterflies
+# in the last inverse stage), (36, 18, 54) (54 not a multiple of 8)
+@pytest.mark.parametrize("n,prec", [((16, 24, 128), "f32"), ((48, 64, 96), "f64"), ((64, 32, 256), "f32"),
+                                    ((8, 512, 64), "f32"), ((24, 16, 32), "f32"), ((36, 18, 54), "f64")])
+def test_tiled_handoff_is_bit_identical(n, prec, monkeypatch):
+    """The multiply pass writes the axis-1 inverse's tile order unless
+    VGF_TILED_Y=0 (read at plan creation); only addresses differ, so the
+    fields match plain rows bit for bit, under every schedule of the two
+    passes and in a batch."""
+    torch, vgf = need_gpu()
+    h = tuple(2.0 / (x - 1) for x in n)
+    plans = {}
+    for v in ("0", "1"):
+        monkeypatch.setenv("VGF_TILED_Y", v)
+        plans[v] = gpu_plan(vgf, n, h, precision=prec)
+    rho = torch.from_numpy(W.random_field(8, n)).to("cuda", plans["0"].dtype)
+    phi0, E0 = plans["0"].solve(rho)
+    for sched in [(0, 0, 0, 0, 0), (0, 0, 1, 0, 0), (0, 0, 2, 1, 0), (0, 0, 3, 3, 0), (0, 1, 0, 2, 0)]:
+        plans["1"].schedule = sched
+        phi1, E1 = plans["1"].solve(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(phi0, phi1) and torch.equal(E0, E1), sched
+    plans["1"].schedule = (0, 0, 0, 0, 0)
+    rhos = [rho, torch.from_numpy(W.random_field(9, n)).to("cuda", rho.dtype)]
+    outs = vgf.Batch([plans["1"], plans["1"]], graph=False)
+    phis = [torch.empty_like(r) for r in rhos]
+    Es = [torch.empty((3,) + n, dtype=rho.dtype, device="cuda") for _ in rhos]
+    outs.solve(rhos, phis, Es)
+    torch.cuda.synchronize()
+    for r, p, E in zip(rhos, phis, Es):
+        pr, Er = plans["0"].solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(p, pr) and torch.equal(E, Er)
+    outs.close()
+    for p in plans.values():
+        p.close()
