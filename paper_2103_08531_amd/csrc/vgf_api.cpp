@@ -1437,10 +1437,13 @@ vgf_status adjoint_c_entries(vgf_plan p, const AdjEntries<T>& en, const int* sch
       VGF_RUN(vgf::launch_c2c_fwd<T>((int)P1, launch_variant(sched, kPassC2CF, 1), f2, tw(1), s));
       g.fields[g.nf++] = 1;
     }
+    // the multiply pass writes X2 in the axis-1 inverse's tile order
+    g.ytile = y_tile_log2<T>(p);
     VGF_RUN(vgf::launch_fused_c<T>((int)p->P[2], sched[kPassFused], true, b.y, b.x2, g, (const T*)p->spec, tw(2), s));
     vgf::StridedGeom ig{N2, N2, N2, P1 * N2, N1 * N2, (int)H0};
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
+    ig.in_tile = g.ytile;
     vgf::C2CInvArgs<T> ia{b.x2, {b.x1, nullptr}, ig, deriv1<T>(p, 1, 0)};
     VGF_RUN(vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, 0), ia, tw(1), s));
   } else {

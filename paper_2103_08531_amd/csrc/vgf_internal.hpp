@@ -214,8 +214,8 @@ template <typename T> struct FusedCGeom {
   int fields[4];      // adjoint: per input 0 or 1 (+i k_last); gradient kernels: 0 .. dim
                       // (the multipliers of GradSpec), up to four fields
   bool nt = false;    // forward: non-temporal loads and stores (large arrays)
-  // forward 3D: log2 of the block width B of the tiled output layout read by
-  // the axis-1 inverse (StridedGeom::in_tile), 0 for plain rows. Tiled,
+  // 3D (forward and adjoint): log2 of the block width B of the tiled output
+  // layout read by the axis-1 inverse (StridedGeom::in_tile), 0 for plain rows. Tiled,
   // output x_last of line (k0, k1) sits at
   // k0 P1 n_last + (x_last >> log2 B) P1 B + k1 B + (x_last mod B);
   // n_last and the last inverse stage's butterfly count are multiples of B.

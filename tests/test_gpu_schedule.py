@@ -194,10 +194,10 @@ def test_batch_autotune_keeps_results():
 @pytest.mark.parametrize("n,prec", [((16, 24, 128), "f32"), ((48, 64, 96), "f64"), ((64, 32, 256), "f32"),
                                     ((8, 512, 64), "f32"), ((24, 16, 32), "f32"), ((36, 18, 54), "f64")])
 def test_tiled_handoff_is_bit_identical(n, prec, monkeypatch):
-    """The multiply pass writes the axis-1 inverse's tile order unless
-    VGF_TILED_Y=0 (read at plan creation); only addresses differ, so the
-    fields match plain rows bit for bit, under every schedule of the two
-    passes and in a batch."""
+    """The multiply pass (forward and adjoint) writes the axis-1 inverse's
+    tile order unless VGF_TILED_Y=0 (read at plan creation); only addresses
+    differ, so the fields and the adjoint match plain rows bit for bit, under
+    several schedules of the two passes and in a batch."""
     torch, vgf = need_gpu()
     h = tuple(2.0 / (x - 1) for x in n)
     plans = {}
@@ -205,12 +205,17 @@ def test_tiled_handoff_is_bit_identical(n, prec, monkeypatch):
         monkeypatch.setenv("VGF_TILED_Y", v)
         plans[v] = gpu_plan(vgf, n, h, precision=prec)
     rho = torch.from_numpy(W.random_field(8, n)).to("cuda", plans["0"].dtype)
+    g_phi = torch.from_numpy(W.random_field(10, n)).to("cuda", rho.dtype)
+    g_E = torch.from_numpy(W.random_field(11, (3,) + n)).to("cuda", rho.dtype)
     phi0, E0 = plans["0"].solve(rho)
+    adj0 = plans["0"].adjoint(g_phi, g_E)
     for sched in [(0, 0, 0, 0, 0), (0, 0, 1, 0, 0), (0, 0, 2, 1, 0), (0, 0, 3, 3, 0), (0, 1, 0, 2, 0)]:
         plans["1"].schedule = sched
         phi1, E1 = plans["1"].solve(rho)
+        adj1 = plans["1"].adjoint(g_phi, g_E)
         torch.cuda.synchronize()
         assert torch.equal(phi0, phi1) and torch.equal(E0, E1), sched
+        assert torch.equal(adj0, adj1), sched
     plans["1"].schedule = (0, 0, 0, 0, 0)
     rhos = [rho, torch.from_numpy(W.random_field(9, n)).to("cuda", rho.dtype)]
     outs = vgf.Batch([plans["1"], plans["1"]], graph=False)
