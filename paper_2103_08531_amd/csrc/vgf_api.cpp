@@ -875,6 +875,7 @@ vgf_status enqueue_solve_cg(vgf_plan p, const Entries<T>& en, hipStream_t s, boo
   VGF_LAUNCH(kPassR2C, vgf::launch_r2c_s<T>((int)p->P[0], launch_variant(sched, kPassR2C, 0), ra, tw(0), s));
   const cplx<T>* fin = b.x1;
   vgf::FusedCGeom<T> g = fused_c_geom<T>(p, en.count, en.es, nt);
+  g.ytile = y_tile_log2<T>(p);
   g.nf = 0;
   if (en.want_phi) g.fields[g.nf++] = 0;
   if (en.want_E)
@@ -901,6 +902,7 @@ vgf_status enqueue_solve_cg(vgf_plan p, const Entries<T>& en, hipStream_t s, boo
     ig.nentry = en.count;
     ig.es_in = ig.es_out = en.es;
     ig.nt_load = ig.nt_store = nt;
+    ig.in_tile = g.ytile;  // the multiply pass wrote the inverse's tile order
     for (int f = 0; f < g.nf; ++f) {
       vgf::C2CInvArgs<T> ia{b.y + f * g.fs, {b.z + f * zfs, nullptr}, ig, deriv1<T>(p, 1, 0)};
       VGF_LAUNCH(kPassC2CI, vgf::launch_c2c_inv<T>((int)P1, launch_variant(sched, kPassC2CI, f), ia, tw(1), s));

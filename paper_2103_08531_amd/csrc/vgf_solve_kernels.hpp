@@ -1704,7 +1704,10 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l = lane / NQ, q = lane % NQ;
   C* tile = tiles + w * LPW * LP;
-  int64_t line = ((int64_t)blockIdx.x * TW::WPB + w) * gpw * LPW + l;
+  // line order as in k_fused_c (VGF_FC_WALK)
+  constexpr int STEP = VGF_FC_WALK ? TW::WPB : 1;
+  int64_t line = (VGF_FC_WALK ? (int64_t)blockIdx.x * TW::WPB * gpw + w : ((int64_t)blockIdx.x * TW::WPB + w) * gpw) *
+                     LPW + l;
   LineWalk wk;
   wk.p1 = g.dim == 3 ? 2 * g.n1 : (int)g.lpe;
   wk.h0 = g.dim == 3 ? g.n0 + 1 : 1;
@@ -1757,7 +1760,16 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       wave_sync();
       typename ISL::Regs o;
       middle_and_last<T, P, 64, LPW, LP, 1, LAY, true>(o, tile, tw_inverse<P>(twl), l, q);
-      if (valid) {
+      if (valid && g.ytile) {
+        // the axis-1 inverse's tile order (as in k_fused_c)
+        const int sh = g.ytile, bs = wk.p1 << sh;
+        C* __restrict__ d = out + e * g.out_es + fi * g.fs + (int64_t)wk.k0 * wk.p1 * N + ((int64_t)wk.k1 << sh);
+        auto at = [&](int j, int r) { return (j >> sh) * bs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * bs; };
+        if (g.nt)
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[at(j, r)], val); });
+        else
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[at(j, r)] = val; });
+      } else if (valid) {
         C* __restrict__ d = out + e * g.out_es + fi * g.fs + lofs;
         if (g.nt)
           ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
@@ -1765,8 +1777,8 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
           ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[j + r * ISL::NB] = val; });
       }
     }
-    line += LPW;
-    wk.advance(LPW);
+    line += STEP * LPW;
+    wk.advance(STEP * LPW);
   }
 }
 

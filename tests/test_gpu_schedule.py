@@ -230,3 +230,34 @@ def test_tiled_handoff_is_bit_identical(n, prec, monkeypatch):
     outs.close()
     for p in plans.values():
         p.close()
+
+
+@pytest.mark.parametrize("n,prec", [((48, 64, 96), "f64"), ((64, 32, 256), "f32")])
+def test_tiled_handoff_gradient_kernel_is_bit_identical(n, prec, monkeypatch):
+    """The gradient-kernel multiply pass writes every field in the axis-1
+    inverse's tile order unless VGF_TILED_Y=0: fields bit-identical, in a
+    batch too."""
+    torch, vgf = need_gpu()
+    h = tuple(2.0 / (x - 1) for x in n)
+    plans = {}
+    for v in ("0", "1"):
+        monkeypatch.setenv("VGF_TILED_Y", v)
+        plans[v] = gpu_plan(vgf, n, h, precision=prec, field="gradient_kernel")
+    rhos = [torch.from_numpy(W.random_field(s, n)).to("cuda", plans["0"].dtype) for s in (12, 13)]
+    ref = [plans["0"].solve(r) for r in rhos]
+    for sched in [(0, 0, 0, 0, 0), (0, 0, 0, 3, 0)]:
+        plans["1"].schedule = sched
+        phi1, E1 = plans["1"].solve(rhos[0])
+        torch.cuda.synchronize()
+        assert torch.equal(ref[0][0], phi1) and torch.equal(ref[0][1], E1), sched
+    plans["1"].schedule = (0, 0, 0, 0, 0)
+    b = vgf.Batch([plans["1"], plans["1"]], graph=False)
+    phis = [torch.empty_like(r) for r in rhos]
+    Es = [torch.empty((3,) + n, dtype=rhos[0].dtype, device="cuda") for _ in rhos]
+    b.solve(rhos, phis, Es)
+    torch.cuda.synchronize()
+    for (pr, Er), p, E in zip(ref, phis, Es):
+        assert torch.equal(p, pr) and torch.equal(E, Er)
+    b.close()
+    for p in plans.values():
+        p.close()
