@@ -1279,6 +1279,18 @@ struct LineWalk {
   }
 };
 
+// Address of position j + r NB of a line written in the tiled layout
+// (FusedCGeom::ytile = sh, bs = p1 << sh): a uniform base per r plus a 32-bit
+// per-lane offset, which the stores take as scalar base and vector offset
+// without 64-bit address arithmetic per store.
+template <int NB, typename C>
+__device__ __forceinline__ C* tiled_ptr(C* d, int j, int r, int sh, int bs) {
+  C* dr = d + (int64_t)r * (int64_t)((NB >> sh) * bs);
+  // byte offset as a 32-bit value (every tiled plane is below 4 GiB)
+  const uint32_t lo = (uint32_t)((j >> sh) * bs + (j & ((1 << sh) - 1))) * (uint32_t)sizeof(C);
+  return reinterpret_cast<C*>(reinterpret_cast<char*>(dr) + lo);
+}
+
 // Multiply-and-inverse pass along the contiguous last axis: each wavefront
 // walks gpw groups of LPW lines (VGF_FC_WALK sets their order; lanes along
 // the line, every exchange inside the wavefront). Line (k0, k1) of length n_last is
@@ -1404,11 +1416,14 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
         if (g.ytile) {
           // position j + r NB: block (j >> sh) + r (NB >> sh), offset j mod B
           const int sh = g.ytile, bs = wk.p1 << sh;
-          auto at = [&](int j, int r) { return (j >> sh) * bs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * bs; };
           if (g.nt)
-            ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[at(j, r)], val); });
+            ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+              store_nt(tiled_ptr<ISL::NB>(d, j, r, sh, bs), val);
+            });
           else
-            ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[at(j, r)] = val; });
+            ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+              *tiled_ptr<ISL::NB>(d, j, r, sh, bs) = val;
+            });
         } else if (g.nt) {
           ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
         } else {
@@ -1539,11 +1554,14 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
       if (g.ytile) {
         // position j + r NB: block (j >> sh) + r (NB >> sh), offset j mod B
         const int sh = g.ytile;
-        auto at = [&](int j, int r) { return (j >> sh) * ybs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * ybs; };
         if (g.nt)
-          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[at(j, r)], val); });
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+            store_nt(tiled_ptr<ISL::NB>(d, j, r, sh, ybs), val);
+          });
         else
-          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[at(j, r)] = val; });
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+            *tiled_ptr<ISL::NB>(d, j, r, sh, ybs) = val;
+          });
       } else if (g.nt) {
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[j + r * ISL::NB], val); });
       } else {
@@ -1651,8 +1669,9 @@ __global__ __launch_bounds__((TileW<T, P, V>::NT), (TileW<T, P, V>::MINW_FC)) vo
         // the axis-1 inverse's tile order (as in k_fused_c)
         const int sh = g.ytile, bs = wk.p1 << sh;
         C* __restrict__ dst = out + wk.e * g.out_es + (int64_t)wk.k0 * wk.p1 * N + ((int64_t)wk.k1 << sh);
-        auto at = [&](int j, int r) { return (j >> sh) * bs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * bs; };
-        ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[at(j, r)] = val; });
+        ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+          *tiled_ptr<ISL::NB>(dst, j, r, sh, bs) = val;
+        });
       } else {
         C* __restrict__ dst = out + wk.e * g.out_es + lofs;
         ISL::template store_last<true>(o, q, [&](int j, int r, C val) { dst[j + r * ISL::NB] = val; });
@@ -1764,11 +1783,14 @@ __global__ __launch_bounds__((TileW<T, P>::NT), (TileW<T, P>::MINW_FC)) void k_f
         // the axis-1 inverse's tile order (as in k_fused_c)
         const int sh = g.ytile, bs = wk.p1 << sh;
         C* __restrict__ d = out + e * g.out_es + fi * g.fs + (int64_t)wk.k0 * wk.p1 * N + ((int64_t)wk.k1 << sh);
-        auto at = [&](int j, int r) { return (j >> sh) * bs + (j & ((1 << sh) - 1)) + r * (ISL::NB >> sh) * bs; };
         if (g.nt)
-          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { store_nt(&d[at(j, r)], val); });
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+            store_nt(tiled_ptr<ISL::NB>(d, j, r, sh, bs), val);
+          });
         else
-          ISL::template store_last<true>(o, q, [&](int j, int r, C val) { d[at(j, r)] = val; });
+          ISL::template store_last<true>(o, q, [&](int j, int r, C val) {
+            *tiled_ptr<ISL::NB>(d, j, r, sh, bs) = val;
+          });
       } else if (valid) {
         C* __restrict__ d = out + e * g.out_es + fi * g.fs + lofs;
         if (g.nt)
