@@ -234,15 +234,13 @@ bool tile_y_env() {
 
 // log2 of the block width B of the tiled hand-off from the multiply pass to
 // the axis-1 inverse (3D, default layout), 0 where it is not used. B is the
-// inverse's default tile width (one 128-byte row segment, halved while a
-// tile of P1 rows would exceed 64 KiB), so each of its workgroups reads one
-// contiguous block; n_last and the butterfly count of the last inverse stage
+// inverse's default tile width (strided_tile_width), so each of its
+// workgroups reads one contiguous block; n_last and the butterfly count of the last inverse stage
 // along the last axis must be multiples of B.
 template <typename T> int y_tile_log2(vgf_plan p) {
   if (!p->tile_y || p->dim != 3) return 0;
   const int64_t P1 = p->P[1], P2 = p->P[2], N2 = p->n[2];
-  int b = sizeof(T) == 4 ? 16 : 8;
-  while (b > 1 && P1 * b * 2 * (int64_t)sizeof(T) > 65536) b /= 2;
+  const int b = vgf::strided_tile_width((int)P1, (int)sizeof(T));
   const int64_t nb_last = P2 / vgf::fwd_radix((int)P2, 0);
   if (b < 2 || N2 % b != 0 || nb_last % b != 0) return 0;
   int sh = 0;

@@ -155,6 +155,19 @@ template <typename T>
 hipError_t launch_c2r(int P, const C2RArgs<T>& a, const cplx<T>* tw, hipStream_t s);
 // Number of tile-schedule variants of the strided passes (see TileV).
 constexpr int kTileVariantsHost = 2;
+
+// Largest LDS tile (bytes) of the default layout's strided passes; their
+// default tile is one 128-byte row segment wide wherever that fits in this
+// and in 1024 threads (8 values per thread), else narrower.
+#ifndef VGF_STRIDED_LDS
+#define VGF_STRIDED_LDS 131072
+#endif
+constexpr int strided_tile_width(int P, int value_bytes) {
+  int nl = 128 / (2 * value_bytes);
+  const int nq = (P + 7) / 8;
+  while (nl > 1 && (P * nl * 2 * value_bytes > VGF_STRIDED_LDS || nl * nq > 1024)) nl /= 2;
+  return nl;
+}
 // The strided passes take a tile-schedule variant (0 or 1, see TileV):
 // every variant computes identical results; only the launch shape differs.
 template <typename T>

@@ -125,8 +125,16 @@ template <typename T, int P, int NL_FORCE = 0> struct Tile {
 // per CU). Every column is transformed with the same arithmetic in both, so
 // the choice never changes a result bit.
 constexpr int kTileVariants = kTileVariantsHost;
+template <typename T, int P> constexpr int strided_nl() {
+  static_assert(VGF_EPT == 8, "strided_tile_width assumes 8 values per thread");
+  return strided_tile_width(P, (int)sizeof(T));
+}
 template <typename T, int P, int V>
-struct TileV : Tile<T, P, (V == 0 ? 0 : (Tile<T, P>::NL > 1 ? Tile<T, P>::NL / 2 : 1))> {};
+struct TileV : Tile<T, P, (V == 0 ? strided_nl<T, P>() : (strided_nl<T, P>() > 1 ? strided_nl<T, P>() / 2 : 1))> {};
+// the axis-0 layout's tiles (two LDS buffers in its multiply pass) keep the
+// 64 KiB rule of Tile
+template <typename T, int P, int V>
+struct TileV64 : Tile<T, P, (V == 0 ? 0 : (Tile<T, P>::NL > 1 ? Tile<T, P>::NL / 2 : 1))> {};
 
 // Block -> column tile of the strided passes. Half-width tiles (V = 1) split
 // each 128-byte row segment between two workgroups; workgroups are dealt to
@@ -614,7 +622,7 @@ __global__ __launch_bounds__((TileV<T, P, V>::NT), (TileV<T, P, V>::MINW)) void 
 }
 
 // Tile of the fused axis-0 pass (two LDS tiles, more registers).
-template <typename T, int P, int V> struct TileF : TileV<T, P, V> {
+template <typename T, int P, int V> struct TileF : TileV64<T, P, V> {
   // inverse fields as two straight-line copies (measured faster in FP64;
   // in FP32 at 1024 threads the copies exceed 128 VGPRs and spill)
   static constexpr bool SPLIT_FIELDS = sizeof(T) == 8;
