@@ -79,9 +79,11 @@ __global__ void k_he(double* __restrict__ out, int dim, int64_t n0, int64_t n1, 
 // mat[m][j] in[o][m][i], so they run as FP64 GEMMs on the matrix cores:
 // C[b][r][c] = sum_k A[b][r][k] B[b][k][c] with arbitrary element strides.
 // A workgroup of four wavefronts owns a 64 x 64 tile of C (32 x 32 per
-// wavefront, four 16 x 16 MFMA blocks) and walks k in steps of 16 through
-// LDS. v_mfma_f64_16x16x4f64 lane layout: lane l holds A[l%16][l/16],
-// B[l/16][l%16] and D[4v + l/16][l%16] (v = 0..3).
+// wavefront, four 16 x 16 MFMA blocks) and walks k in slabs of 32 through
+// LDS; each thread loads its share of the next slab into registers while the
+// wavefronts multiply the current one. v_mfma_f64_16x16x4f64 lane layout:
+// lane l holds A[l%16][l/16], B[l/16][l%16] and D[4v + l/16][l%16]
+// (v = 0..3). The products are accumulated in increasing k, four at a time.
 typedef double d4 __attribute__((ext_vector_type(4)));
 struct GemmF64 {
   const double* A;
@@ -93,8 +95,9 @@ struct GemmF64 {
   int64_t R, Cn;
   int K;
 };
-constexpr int GT = 64;  // rows and columns of C per workgroup
-constexpr int GK = 16;  // k per LDS stage
+constexpr int GT = 64;               // rows and columns of C per workgroup
+constexpr int GK = 32;               // k per LDS slab
+constexpr int GE = GT * GK / 256;    // elements of each operand per thread and slab
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64 g) {
   __shared__ double As[GK][GT + 1];  // [k][row]
@@ -105,27 +108,46 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64 g) {
   const double* __restrict__ A = g.A + (int64_t)blockIdx.z * g.a_b;
   const double* __restrict__ B = g.B + (int64_t)blockIdx.z * g.b_b;
   const bool a_kfast = g.a_k == 1;  // A contiguous along k (else along rows)
+  // element e = tid + 256 i of a slab: A at (row, k) = (e / GK, e % GK) when
+  // A is contiguous along k, else (e % GT, e / GT); B at (e / GT, e % GT)
+  double ra[GE], rb[GE];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < GE; ++i) {
+      const int e = tid + 256 * i;
+      const int rr = a_kfast ? e / GK : e % GT, kk = a_kfast ? e % GK : e / GT;
+      const int64_t r = r0 + rr;
+      const int k = k0 + kk;
+      ra[i] = (r < g.R && k < g.K) ? A[r * g.a_r + (int64_t)k * g.a_k] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < GE; ++i) {
+      const int e = tid + 256 * i;
+      const int64_t c = c0 + e % GT;
+      const int k = k0 + e / GT;
+      rb[i] = (c < g.Cn && k < g.K) ? B[(int64_t)k * g.b_k + c * g.b_c] : 0.0;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < GE; ++i) {
+      const int e = tid + 256 * i;
+      const int rr = a_kfast ? e / GK : e % GT, kk = a_kfast ? e % GK : e / GT;
+      As[kk][rr] = ra[i];
+      Bs[e / GT][e % GT] = rb[i];
+    }
+  };
   d4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  stash();
+  __syncthreads();
   for (int k0 = 0; k0 < g.K; k0 += GK) {
-#pragma unroll
-    for (int e = tid; e < GT * GK; e += 256) {
-      const int rr = a_kfast ? e / GK : e % GT, kk = a_kfast ? e % GK : e / GT;
-      const int64_t r = r0 + rr;
-      const int k = k0 + kk;
-      As[kk][rr] = (r < g.R && k < g.K) ? A[r * g.a_r + (int64_t)k * g.a_k] : 0.0;
-    }
-#pragma unroll
-    for (int e = tid; e < GT * GK; e += 256) {
-      const int cc = e % GT, kk = e / GT;
-      const int64_t c = c0 + cc;
-      const int k = k0 + kk;
-      Bs[kk][cc] = (c < g.Cn && k < g.K) ? B[(int64_t)k * g.b_k + c * g.b_c] : 0.0;
-    }
-    __syncthreads();
+    const bool more = k0 + GK < g.K;
+    if (more) fetch(k0 + GK);  // in flight during this slab's products
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 4) {
       const int kk = ks + lane / 16;
@@ -139,7 +161,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmF64 g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
+    __syncthreads();  // every wavefront is done with this slab
+    if (more) {
+      stash();
+      __syncthreads();
+    }
   }
   double* __restrict__ C = g.C + (int64_t)blockIdx.z * g.c_b;
 #pragma unroll
