@@ -235,8 +235,8 @@ bool tile_y_env() {
 // log2 of the block width B of the tiled hand-off from the multiply pass to
 // the axis-1 inverse (3D, default layout), 0 where it is not used. B is the
 // inverse's default tile width (strided_tile_width), so each of its
-// workgroups reads one contiguous block; n_last and the butterfly count of the last inverse stage
-// along the last axis must be multiples of B.
+// workgroups reads one contiguous block; n_last and the butterfly count of
+// the last inverse stage along the last axis must be multiples of B.
 template <typename T> int y_tile_log2(vgf_plan p) {
   if (!p->tile_y || p->dim != 3) return 0;
   const int64_t P1 = p->P[1], P2 = p->P[2], N2 = p->n[2];
