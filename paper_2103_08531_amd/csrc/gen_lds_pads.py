@@ -34,9 +34,15 @@ def pow3(P):
     return b
 
 
+def radix6_plan(P):
+    return pow2(P) % 3 == 1 and pow2(P) >= 4 and pow3(P) >= 1 and (P // 6 <= 64 or (P // 6) % 64 == 0)
+
+
 def fwd_radix(P, s):
     a = pow2(P)
     q, r = a // 3, a % 3
+    if radix6_plan(P):
+        return 8 if s < q else (6 if s == q else 3)
     s2 = q + (1 if r else 0)
     if s >= s2:
         return 3
@@ -51,7 +57,7 @@ def fwd_radix(P, s):
 
 def radices(P, sign):
     a = pow2(P)
-    n = a // 3 + (1 if a % 3 else 0) + pow3(P)
+    n = (a // 3 if radix6_plan(P) else a // 3 + (1 if a % 3 else 0)) + pow3(P)
     f = [fwd_radix(P, s) for s in range(n)]
     return f if sign < 0 else f[::-1]
 

@@ -69,7 +69,13 @@ template <int S, typename C, typename T> __host__ __device__ __forceinline__ C c
 // radix plan (compile time). P = 2^a 3^b. Forward order: the power-of-two
 // stages (8s, then the 4s or the 2), then the 3s; the inverse uses the
 // reverse order, so the last forward stage and the first inverse stage have
-// the same radix and the same butterfly-to-thread map.
+// the same radix and the same butterfly-to-thread map. Where 2^a = 8^q * 2
+// (a = 3q + 1, q >= 1) and b >= 1, the 2 and one 3 form a radix-6 stage
+// (8^q, 6, 3^(b-1)) instead of 8^(q-1), 4, 4, 3^b: one stage and one LDS
+// exchange fewer. Only where the radix-6 stage's P/6 butterflies fill the
+// 64 lanes of a wavefront evenly (P/6 <= 64 or a multiple of 64: P = 48,
+// 144, 384, 1152); at 432 and 1296 its second round of butterflies would
+// leave most lanes idle (measured slower in FP64 at 216^3).
 // ---------------------------------------------------------------------------
 constexpr int pow2_of(int P) { int a = 0; while (P % 2 == 0) { P /= 2; ++a; } return a; }
 constexpr int pow3_of(int P) { while (P % 2 == 0) P /= 2; int b = 0; while (P % 3 == 0) { P /= 3; ++b; } return b; }
@@ -79,10 +85,14 @@ constexpr bool fft_len_ok(int P) {
   while (p % 3 == 0) p /= 3;
   return p == 1 && pow2_of(P) >= 1;
 }
-constexpr int n_pow2_stages(int P) { return (pow2_of(P) + 2) / 3; }
+constexpr bool radix6_plan(int P) {
+  return pow2_of(P) % 3 == 1 && pow2_of(P) >= 4 && pow3_of(P) >= 1 && (P / 6 <= 64 || (P / 6) % 64 == 0);
+}
+constexpr int n_pow2_stages(int P) { return radix6_plan(P) ? pow2_of(P) / 3 : (pow2_of(P) + 2) / 3; }
 constexpr int n_stages(int P) { return n_pow2_stages(P) + pow3_of(P); }
 constexpr int fwd_radix(int P, int s) {
   const int a = pow2_of(P), q = a / 3, r = a % 3, s2 = n_pow2_stages(P);
+  if (radix6_plan(P)) return s < q ? 8 : (s == q ? 6 : 3);
   if (s >= s2) return 3;
   if (r == 0) return 8;
   if (r == 2) return (s < q) ? 8 : 4;
@@ -189,6 +199,26 @@ template <int S, typename C> __host__ __device__ __forceinline__ void dft3_impl(
   v[2] = c_fmai<S>(-K<T>::s3, d, m);
 }
 
+// 6-point DFT as two 3-point DFTs of the even and odd inputs, combined with
+// W = exp(S 2 pi i / 6) = 1/2 + S i sqrt(3)/2 and W^2 = -1/2 + S i sqrt(3)/2
+// (W^3 = -1): v_k = e_k + W^k o_k, v_{k+3} = e_k - W^k o_k.
+template <int S, typename C> __host__ __device__ __forceinline__ void dft6_impl(C* v) {
+  using T = decltype(v[0].x);
+  C e[3] = {v[0], v[2], v[4]};
+  C o[3] = {v[1], v[3], v[5]};
+  dft3_impl<S>(e);
+  dft3_impl<S>(o);
+  const T h = T(0.5);
+  const C w1 = c_fmai<S>(K<T>::s3, o[1], C{h * o[1].x, h * o[1].y});    // W o_1
+  const C w2 = c_fmai<S>(K<T>::s3, o[2], C{-h * o[2].x, -h * o[2].y});  // W^2 o_2
+  v[0] = c_add(e[0], o[0]);
+  v[3] = c_sub(e[0], o[0]);
+  v[1] = c_add(e[1], w1);
+  v[4] = c_sub(e[1], w1);
+  v[2] = c_add(e[2], w2);
+  v[5] = c_sub(e[2], w2);
+}
+
 // run: full R-point DFT; run_half: the same with inputs R/2 .. R-1 zero
 // (never read)
 template <int R, int S, typename C> struct Dft;
@@ -202,6 +232,9 @@ template <int S, typename C> struct Dft<3, S, C> {
 template <int S, typename C> struct Dft<4, S, C> {
   __host__ __device__ __forceinline__ static void run(C* v) { dft4<S>(v[0], v[1], v[2], v[3]); }
   __host__ __device__ __forceinline__ static void run_half(C* v) { dft4_half<S>(v[0], v[1], v[2], v[3]); }
+};
+template <int S, typename C> struct Dft<6, S, C> {
+  __host__ __device__ __forceinline__ static void run(C* v) { dft6_impl<S>(v); }
 };
 template <int S, typename C> struct Dft<8, S, C> {
   __host__ __device__ __forceinline__ static void run(C* v) { dft8_impl<S, false>(v); }

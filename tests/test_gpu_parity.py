@@ -111,7 +111,7 @@ SIZE_CASES = [(2, 96), (2, 192), (2, 384), (3, 24), (3, 48), (3, 64),
 
 @pytest.mark.parametrize("dim,N", SIZE_CASES)
 def test_fft_lengths(dim, N):
-    """Every radix mix (8/4/2/3) of the supported lengths, ragged column tiles."""
+    """Every radix mix (8/6/4/2/3) of the supported lengths, ragged column tiles."""
     n = (N,) * dim
     h = (2.0 / (N - 1),) * dim
     rng = np.random.default_rng(N)
@@ -129,12 +129,14 @@ def test_fft_lengths(dim, N):
 
 
 LONG_AXIS_CASES = [(384, 8, 12), (8, 384, 8), (8, 12, 384), (512, 8, 8), (8, 512, 12), (12, 8, 512),
-                   (288, 8, 12), (8, 288, 8), (8, 12, 288), (486, 8, 8), (8, 432, 12), (12, 8, 324)]
+                   (288, 8, 12), (8, 288, 8), (8, 12, 288), (486, 8, 8), (8, 432, 12), (12, 8, 324),
+                   # lengths 384 and 432 (radix plans 8-8-6 and 8-6-3-3) on each axis
+                   (192, 8, 12), (8, 192, 8), (12, 8, 192), (216, 8, 8), (8, 216, 12), (8, 12, 216)]
 
 
 @pytest.mark.parametrize("n", LONG_AXIS_CASES)
 def test_fft_lengths_3d_long_axes(n):
-    """Transform lengths 768 and 1024 on each 3D axis (the axis-1 passes meet
+    """Transform lengths 384 to 1024 on each 3D axis (the axis-1 passes meet
     them only in 3D), thin grids so the oracle stays fast."""
     h = tuple(2.0 / (x - 1) for x in n)
     rho = W.random_field(sum(n), n)
