@@ -129,8 +129,18 @@ template <typename T, int P> constexpr int strided_nl() {
   static_assert(VGF_EPT == 8, "strided_tile_width assumes 8 values per thread");
   return strided_tile_width(P, (int)sizeof(T));
 }
+// The half-width schedule: half of the default width, or, for FP64 lengths
+// 576 to 1024 whose default tile is wider than 64 KiB of LDS allows, half of
+// that narrower width, so grids with few columns (2D 512^2: 38 against 41 us)
+// keep small tiles and many workgroups. The 2D lengths above 1024 measured
+// faster with plain halving (2D 768^2 and 1024^2: 56 and 100 us against 58
+// and 106 us).
+template <typename T, int P> constexpr int strided_nl_half() {
+  constexpr int w = (strided_nl<T, P>() > Tile<T, P>::NL && P <= 1024) ? Tile<T, P>::NL : strided_nl<T, P>();
+  return w > 1 ? w / 2 : 1;
+}
 template <typename T, int P, int V>
-struct TileV : Tile<T, P, (V == 0 ? strided_nl<T, P>() : (strided_nl<T, P>() > 1 ? strided_nl<T, P>() / 2 : 1))> {};
+struct TileV : Tile<T, P, (V == 0 ? strided_nl<T, P>() : strided_nl_half<T, P>())> {};
 // the axis-0 layout's tiles (two LDS buffers in its multiply pass) keep the
 // 64 KiB rule of Tile
 template <typename T, int P, int V>
