@@ -2006,13 +2006,27 @@ hipError_t launch_fused_v(const cplx<T>* in, cplx<T>* out, const FusedGeom<T>& g
   return hipGetLastError();
 }
 
+// Default tile of the lengths whose full-width tile exceeds 64 KiB of LDS
+// (long FP64 lengths): where the full-width tiles would give fewer
+// workgroups than the chip has CUs (grids with few columns, 2D), the
+// default schedule takes the half-width tiles. Every column gets the same
+// arithmetic either way, so no result bit changes.
+constexpr int64_t kStridedFewBlocks = 256;
+template <typename T, int P> inline int strided_variant(int variant, int64_t cols, int64_t batches) {
+  if (variant != 0 || strided_nl<T, P>() <= Tile<T, P>::NL) return variant;
+  const int64_t wgs = (cols + TileV<T, P, 0>::NL - 1) / TileV<T, P, 0>::NL * batches;
+  return wgs < kStridedFewBlocks ? 1 : 0;
+}
+
 template <typename T, int P>
 hipError_t launch_c2c_fwd_p(int variant, const C2CFwdArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  variant = strided_variant<T, P>(variant, a.g.ncols, (int64_t)a.g.nbatch * a.g.nentry);
   return variant == 1 ? launch_c2c_fwd_v<T, P, 1>(a, tw, s) : launch_c2c_fwd_v<T, P, 0>(a, tw, s);
 }
 
 template <typename T, int P>
 hipError_t launch_c2c_inv_p(int variant, const C2CInvArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  variant = strided_variant<T, P>(variant, a.g.ncols, (int64_t)a.g.nbatch * a.g.nentry);
   return variant == 1 ? launch_c2c_inv_v<T, P, 1>(a, tw, s) : launch_c2c_inv_v<T, P, 0>(a, tw, s);
 }
 
@@ -2088,11 +2102,13 @@ hipError_t launch_c2r_s_v(const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s
 
 template <typename T, int P>
 hipError_t launch_r2c_s_p(int variant, const R2CSArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  variant = strided_variant<T, P>(variant, a.ncols / 2, a.nentry);
   return variant == 1 ? launch_r2c_s_v<T, P, 1>(a, tw, s) : launch_r2c_s_v<T, P, 0>(a, tw, s);
 }
 
 template <typename T, int P>
 hipError_t launch_c2r_s_p(int variant, const C2RSArgs<T>& a, const cplx<T>* tw, hipStream_t s) {
+  variant = strided_variant<T, P>(variant, a.ncols / 2, a.nentry);
   return variant == 1 ? launch_c2r_s_v<T, P, 1>(a, tw, s) : launch_c2r_s_v<T, P, 0>(a, tw, s);
 }
 
